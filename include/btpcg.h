@@ -1,0 +1,187 @@
+/*
+ * btpcg — preconditioned conjugate gradient for SPD block-tridiagonal systems
+ * on AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Yang, Ohtsuka, Plancher, Jones, arXiv 2503.15269, Section II-A,
+ * eq. (1)): solve A x = b where A is symmetric positive definite and block
+ * tridiagonal with N diagonal blocks D_k (n x n, SPD) and upper blocks
+ * O_k = A[k][k+1] (n x n, k = 0..N-2); the lower blocks are O_k^T. All
+ * blocks are dense.
+ *
+ * Preconditioner: the parametric multi-splitting polynomial preconditioner
+ *   M_m^{-1} = (I + alpha_1 H_ab + ... + alpha_{m-1} H_ab^{m-1}) G_ab
+ * (Section III-A, eq. Mabinv; Section III-E, eq. Mminv-polynomial-
+ * coefficients) with the weights (a, b) of the diagonal and the two stair
+ * splittings on the admissible set 2a + b = 1, a >= 0, b >= -1 (Section
+ * III-C, the set C_g). The optimal weights are (a, b) = (1, -1) (Theorem 3.6).
+ *
+ * Layouts (all row-major, all device memory unless stated):
+ *   D : [R][n][n]   diagonal blocks of every instance, rows concatenated
+ *   O : [R-B][n][n] upper blocks; instance i owns blocks
+ *                   offsets[i]-i .. offsets[i+1]-i-2
+ *   b, x, r, z, g, lambda : [R][n] float64
+ *   dD : [R][n][n] float64, dO : [R-B][n][n] float64
+ * where B is the number of independent instances and R the total number of
+ * block rows; instance i owns rows offsets[i] .. offsets[i+1]-1.
+ * D and O are the system of record, in float64 or float32 (``dtype``);
+ * float32 values are promoted exactly wherever double precision is used.
+ *
+ * Ownership: every buffer, including the workspace, belongs to the caller.
+ * A handle only refers to them: D, O and the workspace must stay alive and
+ * unchanged while the handle is used. The library never allocates device
+ * memory. The handle itself is a small host object freed by bt_destroy.
+ *
+ * Execution: every call that takes a stream enqueues its work on that
+ * stream (a hipStream_t; NULL is the null stream) and returns without
+ * waiting. The return value reports argument validation and launch errors
+ * only. Per-instance outcomes (convergence, iteration counts, a failed
+ * factorisation) are written by the device into a bt_info array. Calls on one
+ * handle must be ordered on one stream; two calls in flight at once on the
+ * same handle share its scratch counters and race.
+ */
+#ifndef BTPCG_H
+#define BTPCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes (return values and bt_info.status). */
+#define BT_OK 0             /* converged / success */
+#define BT_NOT_CONVERGED 1  /* iteration cap reached; x holds the last iterate */
+#define BT_EINVAL (-1)      /* invalid argument (sizes, pointers, parameters) */
+#define BT_ENOTSPD (-2)     /* Cholesky of a diagonal block failed: A not SPD */
+#define BT_EBREAKDOWN (-3)  /* p'Ap <= 0 or r'z <= 0: A or M^{-1} not SPD */
+#define BT_ENONFINITE (-4)  /* a non-finite value appeared */
+#define BT_EHIP (-5)        /* HIP runtime error */
+#define BT_ENOSPACE (-6)    /* workspace too small */
+
+/* Arithmetic of the iteration. */
+#define BT_F64 0     /* float64 throughout */
+#define BT_F32 1     /* float32 iteration, float32 accumulation with
+                        compensated dot products; no refinement */
+#define BT_F32_IR 2  /* float32 inner PCG inside a float64 iterative
+                        refinement on the system of record */
+
+/* Storage type of D and O. */
+#define BT_DT_F64 0
+#define BT_DT_F32 1
+
+/* Preconditioner family. */
+#define BT_PC_POLY 0 /* M_m^{-1} of eq. Mminv-polynomial-coefficients */
+#define BT_PC_NONE 1 /* no preconditioner (plain CG; not in the paper) */
+
+#define BT_MAX_M 8
+
+typedef struct bt_params {
+  double a, b;            /* splitting weights; 2a+b = 1, a >= 0, b >= -1.
+                             (1,-1): optimal (Theorem 3.6); (0,1): block
+                             Jacobi (Section III-D) */
+  int m;                  /* polynomial order, 1..BT_MAX_M */
+  int pc;                 /* BT_PC_POLY or BT_PC_NONE */
+  double alpha[BT_MAX_M]; /* alpha[i] multiplies H^i, i = 1..m-1; alpha[0]
+                             is ignored (the leading term is I) */
+  int prec;               /* BT_F64, BT_F32 or BT_F32_IR */
+  int max_outer;          /* BT_F32_IR: cap on refinement steps */
+  double inner_tol;       /* BT_F32_IR: each inner solve stops when its
+                             residual fell by this factor */
+} bt_params;
+
+/* Defaults: a = 1, b = -1, m = 2, alpha = {1, 7} (the paper's "PolyCoeff"
+ * choice, Section V), BT_PC_POLY, BT_F64, max_outer = 30, inner_tol = 1e-4. */
+void bt_default_params(bt_params* p);
+
+/* Per-instance outcome, written on the device (32 bytes). */
+typedef struct bt_info {
+  int32_t status;      /* BT_OK, BT_NOT_CONVERGED, BT_ENOTSPD, BT_EBREAKDOWN,
+                          BT_ENONFINITE */
+  int32_t iters;       /* PCG iterations = products with A (summed over the
+                          inner solves under BT_F32_IR) */
+  int32_t outer;       /* refinement steps (BT_F32_IR), else 1 */
+  int32_t fail_index;  /* block row (within the instance) of a failed D_k
+                          factorisation, else -1 */
+  double relres;       /* ||r|| / ||b|| seen by the final stopping test */
+  double relres_true;  /* ||b - A x|| / ||b|| in float64 from the record */
+} bt_info;
+
+typedef struct bt_handle bt_handle;
+
+/* Bytes of workspace for a batch: B instances with row offsets
+ * ``offsets_host`` (host memory, B+1 entries, offsets[0] = 0, increasing),
+ * block size n and parameters p. Returns 0 on invalid arguments. */
+size_t bt_workspace_bytes(int B, const int64_t* offsets_host, int n,
+                          const bt_params* p);
+
+/* Set up a batch of B independent systems (Section IV-A: the diagonal-block
+ * inverses and the off-diagonal splitting terms of the preconditioner).
+ * offsets_host: host array, B+1 entries. D, O: device, see the layouts above.
+ * The workspace (device, >= bt_workspace_bytes) receives the factors.
+ * On success *h receives a new handle. Errors: BT_EINVAL (B < 1, n < 1 or
+ * n > 64, an empty instance, an instance too large for one workgroup,
+ * parameters outside C_g, m outside 1..BT_MAX_M, NULL pointers),
+ * BT_ENOSPACE, BT_EHIP. A non-SPD D_k is reported by the next solve
+ * (status BT_ENOTSPD, fail_index). */
+int bt_batch_setup(bt_handle** h, int B, const int64_t* offsets_host, int n,
+                   int dtype, const void* D, const void* O,
+                   const bt_params* p, void* workspace, size_t ws_bytes,
+                   void* stream);
+
+/* Recompute the factors of an existing handle from the current contents of
+ * its D and O buffers (same shapes, same pointers), e.g. after the caller
+ * overwrote them with a new system. Enqueues kernels only (no copies), so it
+ * can be captured into a HIP graph together with a solve. */
+int bt_refactor(bt_handle* h, void* stream);
+
+/* Single system: bt_batch_setup with B = 1 and offsets {0, N}. */
+int bt_setup(bt_handle** h, int N, int n, int dtype, const void* D,
+             const void* O, const bt_params* p, void* workspace,
+             size_t ws_bytes, void* stream);
+
+/* z = M^{-1} r for every instance (one application of the preconditioner,
+ * eq. Mminv-polynomial-coefficients). r, z: device [R][n] float64. */
+int bt_precondition(const bt_handle* h, const double* r, double* z,
+                    void* stream);
+
+/* Solve A x = b for every instance by PCG from x0 = 0 until
+ * ||b - A x|| <= tol ||b|| (recursive residual; under BT_F32_IR the test is
+ * on the float64 residual of the record) or maxit iterations.
+ * b, x: device [R][n] float64. info: device, B entries. */
+int bt_solve(const bt_handle* h, const double* b, double* x, double tol,
+             int maxit, bt_info* info, void* stream);
+
+/* Same as bt_solve; the name of the batched entry point. All instances run
+ * in one persistent launch, each converging on its own. */
+int bt_solve_batched(const bt_handle* h, const double* b, double* x,
+                     double tol, int maxit, bt_info* info, void* stream);
+
+/* Adjoint of x = A^{-1} b for an upstream gradient g = dL/dx:
+ * lambda = A^{-1} g (same preconditioned solve; A is symmetric),
+ * dL/db = lambda, dL/dD_k = -lambda_k x_k^T,
+ * dL/dO_k = -(lambda_k x_{k+1}^T + x_k lambda_{k+1}^T).
+ * x, g, lambda: device [R][n]; dD: device [R][n][n]; dO: device
+ * [R-B][n][n]; all float64. dD or dO may be NULL to skip them. */
+int bt_solve_adjoint(const bt_handle* h, const double* x, const double* g,
+                     double* lambda, double* dD, double* dO, double tol,
+                     int maxit, bt_info* info, void* stream);
+
+/* Kernel configurations for the solve (workgroup size x vector elements per
+ * thread), for the autotuner. bt_kernel_config_count() entries; entry i has
+ * threads nt[i], elements per thread s[i] and iteration precision prec[i].
+ * bt_set_kernel_config selects entry i for a handle (-1: automatic); it fails
+ * with BT_EINVAL when the entry cannot hold the handle's largest instance or
+ * has another precision. */
+int bt_kernel_config_count(void);
+int bt_kernel_config(int i, int* nt, int* s, int* prec);
+int bt_set_kernel_config(bt_handle* h, int i);
+int bt_get_kernel_config(const bt_handle* h);
+
+void bt_destroy(bt_handle* h);
+const char* bt_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* BTPCG_H */

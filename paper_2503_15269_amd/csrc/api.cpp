@@ -1,0 +1,347 @@
+// C-ABI of the btpcg library: argument validation, workspace layout, kernel
+// selection and launches. All device memory belongs to the caller.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <vector>
+
+#include "internal.h"
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool params_ok(const bt_params* p) {
+  if (!p) return false;
+  if (!(std::isfinite(p->a) && std::isfinite(p->b))) return false;
+  // admissible set C_g: 2a + b = 1, a >= 0, b >= -1
+  if (std::fabs(2.0 * p->a + p->b - 1.0) > 1e-12) return false;
+  if (p->a < 0.0 || p->b < -1.0 - 1e-12) return false;
+  if (p->m < 1 || p->m > BT_MAX_M) return false;
+  if (p->pc != BT_PC_POLY && p->pc != BT_PC_NONE) return false;
+  if (p->prec != BT_F64 && p->prec != BT_F32 && p->prec != BT_F32_IR)
+    return false;
+  for (int i = 1; i < p->m; ++i)
+    if (!std::isfinite(p->alpha[i])) return false;
+  if (p->prec == BT_F32_IR) {
+    if (p->max_outer < 1) return false;
+    if (!(p->inner_tol > 0.0 && p->inner_tol < 1.0)) return false;
+  }
+  return true;
+}
+
+size_t elem_bytes(const bt_params* p) {
+  return p->prec == BT_F64 ? sizeof(double) : sizeof(float);
+}
+
+int kernel_prec(const bt_params* p) {
+  return p->prec == BT_F64 ? BT_F64 : BT_F32;
+}
+
+// Validate offsets; returns total rows R (or -1) and the largest horizon.
+int64_t check_offsets(int B, const int64_t* off, int* maxN) {
+  if (B < 1 || !off || off[0] != 0) return -1;
+  int64_t mx = 0;
+  for (int i = 0; i < B; ++i) {
+    int64_t Ni = off[i + 1] - off[i];
+    if (Ni < 1 || Ni > (int64_t)1 << 30) return -1;
+    mx = std::max(mx, Ni);
+  }
+  *maxN = (int)mx;
+  return off[B];
+}
+
+struct Layout {
+  size_t off, order, ctr, fail, F, L, Li, total;
+};
+
+Layout layout(int B, int64_t R, int n, size_t es) {
+  Layout l{};
+  size_t at = 0;
+  l.off = at; at += align_up(sizeof(int64_t) * (B + 1));
+  l.order = at; at += align_up(sizeof(int32_t) * B);
+  l.ctr = at; at += align_up(sizeof(int32_t) * 64);
+  l.fail = at; at += align_up(sizeof(int32_t) * B);
+  const size_t blk = align_up(es * (size_t)R * n * n);
+  l.F = at; at += blk;
+  l.L = at; at += blk;
+  l.Li = at; at += blk;
+  l.total = at;
+  return l;
+}
+
+// Smallest configuration of the right precision whose capacity holds the
+// largest system; ties go to the smaller workgroup.
+int auto_config(int prec, int64_t maxP) {
+  int best = -1;
+  int64_t bestcap = 0;
+  for (int i = 0; i < bt_num_kernel_configs(); ++i) {
+    const KernelConfig& c = bt_kernel_config_at(i);
+    if (c.prec != prec) continue;
+    const int64_t cap = (int64_t)c.nt * c.s;
+    if (cap < maxP) continue;
+    if (best < 0 || cap < bestcap ||
+        (cap == bestcap && c.nt < bt_kernel_config_at(best).nt)) {
+      best = i;
+      bestcap = cap;
+    }
+  }
+  return best;
+}
+
+int config_for(const bt_handle* h) {
+  if (h->cfg >= 0) return h->cfg;
+  return auto_config(kernel_prec(&h->p), (int64_t)h->maxN * h->n);
+}
+
+int hip_status(hipError_t e) { return e == hipSuccess ? BT_OK : BT_EHIP; }
+
+int launch_setup(bt_handle* h, hipStream_t s) {
+  hipError_t e = bt_launch_setup_init(h->B, h->fail, h->ctr, s);
+  if (e != hipSuccess) return BT_EHIP;
+  SetupArgs a{};
+  a.B = h->B;
+  a.n = h->n;
+  a.dtype = h->dtype;
+  a.prec = h->p.prec;
+  a.R = h->R;
+  a.off = h->off;
+  a.D = h->D;
+  a.O = h->O;
+  a.fail = h->fail;
+  a.F = h->F;
+  a.L = h->L;
+  a.Li = h->Li;
+  return hip_status(bt_launch_setup(a, s));
+}
+
+SolveArgs base_args(const bt_handle* h) {
+  SolveArgs a{};
+  a.B = h->B;
+  a.n = h->n;
+  a.dtype = h->dtype;
+  a.ir = h->p.prec == BT_F32_IR;
+  a.pc = h->p.pc;
+  a.m = h->p.m;
+  a.a = h->p.a;
+  for (int i = 0; i < BT_MAX_M; ++i) a.alpha[i] = i == 0 ? 1.0 : h->p.alpha[i];
+  a.inner_tol = h->p.inner_tol;
+  a.max_outer = h->p.max_outer;
+  a.off = h->off;
+  a.order = h->order;
+  a.ctr = h->ctr;
+  a.fail = h->fail;
+  a.F = h->F;
+  a.L = h->L;
+  a.Li = h->Li;
+  a.D = h->D;
+  a.O = h->O;
+  return a;
+}
+
+int run(const bt_handle* h, SolveArgs& a, hipStream_t s) {
+  const int cfg = config_for(h);
+  if (cfg < 0) return BT_EINVAL;
+  const int grid = std::max(1, std::min(h->B, bt_solve_max_grid(cfg)));
+  return hip_status(bt_launch_solve(cfg, a, grid, s));
+}
+
+}  // namespace
+
+extern "C" {
+
+void bt_default_params(bt_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->a = 1.0;
+  p->b = -1.0;
+  p->m = 2;
+  p->pc = BT_PC_POLY;
+  for (int i = 0; i < BT_MAX_M; ++i) p->alpha[i] = 1.0;
+  p->alpha[1] = 7.0;
+  p->prec = BT_F64;
+  p->max_outer = 30;
+  p->inner_tol = 1e-4;
+}
+
+const char* bt_strerror(int code) {
+  switch (code) {
+    case BT_OK: return "ok";
+    case BT_NOT_CONVERGED: return "iteration cap reached before the tolerance";
+    case BT_EINVAL: return "invalid argument";
+    case BT_ENOTSPD: return "a diagonal block is not positive definite (A is not SPD)";
+    case BT_EBREAKDOWN: return "PCG breakdown: A or the preconditioner is not positive definite";
+    case BT_ENONFINITE: return "non-finite value";
+    case BT_EHIP: return "HIP runtime error";
+    case BT_ENOSPACE: return "workspace too small";
+    default: return "unknown status";
+  }
+}
+
+size_t bt_workspace_bytes(int B, const int64_t* offsets_host, int n,
+                          const bt_params* p) {
+  int maxN = 0;
+  if (!params_ok(p) || n < 1 || n > 64) return 0;
+  const int64_t R = check_offsets(B, offsets_host, &maxN);
+  if (R < 0) return 0;
+  return layout(B, R, n, elem_bytes(p)).total;
+}
+
+int bt_batch_setup(bt_handle** h, int B, const int64_t* offsets_host, int n,
+                   int dtype, const void* D, const void* O, const bt_params* p,
+                   void* workspace, size_t ws_bytes, void* stream) {
+  if (!h) return BT_EINVAL;
+  *h = nullptr;
+  if (!params_ok(p) || n < 1 || n > 64 || !D || !workspace) return BT_EINVAL;
+  if (dtype != BT_DT_F64 && dtype != BT_DT_F32) return BT_EINVAL;
+  int maxN = 0;
+  const int64_t R = check_offsets(B, offsets_host, &maxN);
+  if (R < 0) return BT_EINVAL;
+  if (R > B && !O) return BT_EINVAL;
+  if (auto_config(kernel_prec(p), (int64_t)maxN * n) < 0) return BT_EINVAL;
+  const Layout l = layout(B, R, n, elem_bytes(p));
+  if (ws_bytes < l.total) return BT_ENOSPACE;
+
+  bt_handle* hh = new (std::nothrow) bt_handle();
+  if (!hh) return BT_EHIP;
+  hh->B = B;
+  hh->n = n;
+  hh->dtype = dtype;
+  hh->maxN = maxN;
+  hh->R = R;
+  hh->p = *p;
+  hh->D = D;
+  hh->O = O;
+  unsigned char* w = (unsigned char*)workspace;
+  hh->off = (int64_t*)(w + l.off);
+  hh->order = (int32_t*)(w + l.order);
+  hh->ctr = (int32_t*)(w + l.ctr);
+  hh->fail = (int32_t*)(w + l.fail);
+  hh->F = w + l.F;
+  hh->L = w + l.L;
+  hh->Li = w + l.Li;
+  hh->off_host.assign(offsets_host, offsets_host + B + 1);
+
+  // longest systems first (longest-processing-time order for the queue)
+  std::vector<int32_t> order(B);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    return offsets_host[x + 1] - offsets_host[x] >
+           offsets_host[y + 1] - offsets_host[y];
+  });
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(hh->off, hh->off_host.data(), sizeof(int64_t) * (B + 1),
+                     hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipMemcpyAsync(hh->order, order.data(), sizeof(int32_t) * B,
+                     hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    delete hh;
+    return BT_EHIP;
+  }
+  const int rc = launch_setup(hh, s);
+  if (rc != BT_OK) {
+    delete hh;
+    return rc;
+  }
+  *h = hh;
+  return BT_OK;
+}
+
+int bt_refactor(bt_handle* h, void* stream) {
+  if (!h) return BT_EINVAL;
+  return launch_setup(h, (hipStream_t)stream);
+}
+
+int bt_setup(bt_handle** h, int N, int n, int dtype, const void* D,
+             const void* O, const bt_params* p, void* workspace,
+             size_t ws_bytes, void* stream) {
+  const int64_t off[2] = {0, (int64_t)N};
+  if (N < 1) {
+    if (h) *h = nullptr;
+    return BT_EINVAL;
+  }
+  return bt_batch_setup(h, 1, off, n, dtype, D, O, p, workspace, ws_bytes,
+                        stream);
+}
+
+int bt_precondition(const bt_handle* h, const double* r, double* z,
+                    void* stream) {
+  if (!h || !r || !z) return BT_EINVAL;
+  SolveArgs a = base_args(h);
+  a.mode = 1;
+  a.b = r;
+  a.x = z;
+  a.info = nullptr;
+  return run(h, a, (hipStream_t)stream);
+}
+
+int bt_solve(const bt_handle* h, const double* b, double* x, double tol,
+             int maxit, bt_info* info, void* stream) {
+  if (!h || !b || !x || !info || !(tol >= 0.0) || maxit < 0) return BT_EINVAL;
+  SolveArgs a = base_args(h);
+  a.mode = 0;
+  a.b = b;
+  a.x = x;
+  a.info = info;
+  a.tol = tol;
+  a.maxit = maxit;
+  return run(h, a, (hipStream_t)stream);
+}
+
+int bt_solve_batched(const bt_handle* h, const double* b, double* x,
+                     double tol, int maxit, bt_info* info, void* stream) {
+  return bt_solve(h, b, x, tol, maxit, info, stream);
+}
+
+int bt_solve_adjoint(const bt_handle* h, const double* x, const double* g,
+                     double* lambda, double* dD, double* dO, double tol,
+                     int maxit, bt_info* info, void* stream) {
+  if (!h || !x || !g || !lambda) return BT_EINVAL;
+  if (dO && h->R == h->B) dO = nullptr;  // no upper blocks at all
+  int rc = bt_solve(h, g, lambda, tol, maxit, info, stream);
+  if (rc != BT_OK) return rc;
+  if (!dD && !dO) return BT_OK;
+  return hip_status(bt_launch_adjoint_outer(h->B, h->n, h->R, h->off, x,
+                                            lambda, dD, dO,
+                                            (hipStream_t)stream));
+}
+
+int bt_kernel_config_count(void) { return bt_num_kernel_configs(); }
+
+int bt_kernel_config(int i, int* nt, int* s, int* prec) {
+  if (i < 0 || i >= bt_num_kernel_configs()) return BT_EINVAL;
+  const KernelConfig& c = bt_kernel_config_at(i);
+  if (nt) *nt = c.nt;
+  if (s) *s = c.s;
+  if (prec) *prec = c.prec;
+  return BT_OK;
+}
+
+int bt_set_kernel_config(bt_handle* h, int i) {
+  if (!h) return BT_EINVAL;
+  if (i < 0) {
+    h->cfg = -1;
+    return BT_OK;
+  }
+  if (i >= bt_num_kernel_configs()) return BT_EINVAL;
+  const KernelConfig& c = bt_kernel_config_at(i);
+  if (c.prec != kernel_prec(&h->p)) return BT_EINVAL;
+  if ((int64_t)c.nt * c.s < (int64_t)h->maxN * h->n) return BT_EINVAL;
+  h->cfg = i;
+  return BT_OK;
+}
+
+int bt_get_kernel_config(const bt_handle* h) {
+  if (!h) return -1;
+  return config_for(h);
+}
+
+void bt_destroy(bt_handle* h) { delete h; }
+
+}  // extern "C"

@@ -1,0 +1,83 @@
+// Internal declarations of the btpcg library (not part of the C-ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "btpcg.h"
+
+#define BT_NO_FAIL 0x7fffffff
+
+// Host-side handle. Device pointers point into the caller's workspace.
+struct bt_handle {
+  int B = 0, n = 0, dtype = 0, maxN = 0;
+  int64_t R = 0;
+  bt_params p{};
+  const void* D = nullptr;
+  const void* O = nullptr;
+  int64_t* off = nullptr;   // [B+1] row offsets
+  int32_t* order = nullptr; // [B] instances, longest first
+  int32_t* ctr = nullptr;   // [64] queue counters of the persistent kernels
+  int32_t* fail = nullptr;  // [B] first failing block row, BT_NO_FAIL if none
+  void* F = nullptr;        // [R][n][n] scaled off-diagonal blocks
+  void* L = nullptr;        // [R][n][n] Cholesky factors of D_k
+  void* Li = nullptr;       // [R][n][n] their inverses
+  int cfg = -1;             // solve-kernel configuration, -1 = automatic
+  std::vector<int64_t> off_host;
+};
+
+// Arguments of the persistent solve kernel (passed by value).
+struct SolveArgs {
+  int B, n, dtype;
+  int mode;          // 0 solve, 1 apply the preconditioner once
+  int ir;            // float inner iteration inside float64 refinement
+  int pc, m;
+  double a;
+  double alpha[BT_MAX_M];
+  double tol, inner_tol;
+  int maxit, max_outer;
+  const int64_t* off;
+  const int32_t* order;
+  int32_t* ctr;
+  const int32_t* fail;
+  const void* F;
+  const void* L;
+  const void* Li;
+  const void* D;     // system of record
+  const void* O;
+  const double* b;   // right-hand side (mode 0) or r (mode 1)
+  double* x;         // solution (mode 0) or z (mode 1)
+  bt_info* info;
+};
+
+// Arguments of the setup kernel.
+struct SetupArgs {
+  int B, n, dtype, prec;
+  int64_t R;
+  const int64_t* off;
+  const void* D;
+  const void* O;
+  int32_t* fail;
+  void* F;
+  void* L;
+  void* Li;
+};
+
+struct KernelConfig {
+  int nt, s, prec;  // prec: BT_F64 for double kernels, BT_F32 for float ones
+};
+
+int bt_num_kernel_configs();
+const KernelConfig& bt_kernel_config_at(int i);
+hipError_t bt_launch_solve(int cfg, const SolveArgs& a, int grid,
+                           hipStream_t s);
+int bt_solve_max_grid(int cfg);
+hipError_t bt_launch_setup(const SetupArgs& a, hipStream_t s);
+hipError_t bt_launch_setup_init(int B, int32_t* fail, int32_t* ctr,
+                                hipStream_t s);
+hipError_t bt_launch_adjoint_outer(int B, int n, int64_t R,
+                                   const int64_t* off, const double* x,
+                                   const double* lam, double* dD, double* dO,
+                                   hipStream_t s);

@@ -22,3 +22,9 @@ def oracle_lib():
     import oracle
     oracle.build(force=False)
     return oracle
+
+
+def pytest_sessionstart(session):
+    # Import torch once up front: on a fresh machine the first import can take
+    # a minute or two, which must not count against a single test's timeout.
+    import torch  # noqa: F401

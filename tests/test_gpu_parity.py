@@ -1,0 +1,227 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 CPU oracle.
+
+FP64: iteration counts equal the oracle's (off by one only when the oracle's
+own stopping test sat within 1e-6 of its threshold) and solutions agree with
+the oracle's PCG iterate to 1e-10 relative. FP32 + FP64 refinement: the
+float64 residual of the record reaches the tolerance and the error against
+the oracle's direct solve stays within the conditioning bound.
+"""
+import numpy as np
+import pytest
+
+import lqrgen
+import oracle as orc
+import paper_2503_15269_amd as bt
+from gpu_util import gpu_solve, iteration_match, oracle_kind, rel, workload
+
+pytestmark = pytest.mark.gpu
+
+VARIANTS = {
+    "polycoeff_m1": bt.Params.polycoeff(1),
+    "polycoeff_m2": bt.Params.polycoeff(2),
+    "polycoeff_m3": bt.Params.polycoeff(3),
+    "polycoeff_m4": bt.Params.polycoeff(4),
+    "opt_m2_alpha1": bt.Params(a=1.0, m=2),
+    "jacobi_m1": bt.Params.block_jacobi(1),
+    "jacobi_m2": bt.Params.block_jacobi(2),
+    "stairs_m2": bt.Params(a=0.5, m=2),
+    "equal_m3": bt.Params(a=1 / 3, m=3),
+    "none": bt.Params(pc="none", m=1),
+}
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu(oracle_lib):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    bt.load_library()
+
+
+def _check_f64(D, O, b, params, tol=1e-10, xtol=1e-10):
+    x, info, _ = gpu_solve(D, O, b, params=params, tol=tol)
+    xr, ri = orc.pcg(D, O, b, tol=tol, maxit=10 * D.shape[0] * D.shape[1],
+                     **oracle_kind(params))
+    assert ri["status"] == orc.OK
+    assert info[0]["status"] == bt.OK, info
+    assert iteration_match(int(info[0]["iters"]), ri), (info, ri)
+    if info[0]["iters"] == ri["iters"]:
+        assert rel(x, xr) <= xtol, rel(x, xr)
+    assert info[0]["relres"] <= tol
+    return x, info, ri
+
+
+@pytest.mark.parametrize("name", sorted(VARIANTS))
+def test_single_n6_f64_all_variants(name):
+    d = workload("single_n6")
+    _check_f64(d["D"], d["O"], d["b"], VARIANTS[name])
+
+
+@pytest.mark.parametrize("name", ["polycoeff_m2", "polycoeff_m3", "jacobi_m1",
+                                  "none"])
+def test_single_n12_f64(name):
+    d = workload("single_n12")
+    _check_f64(d["D"], d["O"], d["b"], VARIANTS[name])
+
+
+def test_single_n12_f32_refinement():
+    d = workload("single_n12")
+    P = bt.Params.polycoeff(2, prec="f32_ir")
+    x, info, _ = gpu_solve(d["D"], d["O"], d["b"], params=P, tol=1e-10)
+    assert info[0]["status"] == bt.OK, info
+    assert info[0]["relres_true"] <= 1e-10
+    r = d["b"] - orc.spmv(d["D"], d["O"], x)
+    assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(d["b"])
+    xd = orc.btchol_solve(d["D"], d["O"], d["b"])
+    assert rel(x, xd) <= 1e-6   # kappa ~ 1.7e4 times 1e-10, with margin
+
+
+def test_single_n12_f32_plain():
+    d = workload("single_n12")
+    P = bt.Params.polycoeff(2, prec="f32")
+    x, info, _ = gpu_solve(d["D"], d["O"], d["b"], params=P, tol=1e-6)
+    assert info[0]["status"] == bt.OK, info
+    xd = orc.btchol_solve(d["D"], d["O"], d["b"])
+    assert rel(x, xd) <= 1e-4
+
+
+@pytest.mark.parametrize("N,n", [(1, 1), (1, 5), (2, 1), (2, 3), (3, 2),
+                                 (7, 1), (17, 4), (64, 12), (70, 16)])
+def test_shapes_and_ragged_tails(N, n):
+    """Sizes spanning several elements per thread and ragged tails."""
+    d = lqrgen.lqr_instance(N, n, max(1, n // 3), 4242, N * 100 + n)
+    _check_f64(d["D"], d["O"], d["b"], bt.Params.polycoeff(2))
+
+
+def test_batch_f64_per_instance_parity():
+    B = 24
+    data = lqrgen.lqr_batch(B, (1, 40), 5, 2, seed=77)
+    P = bt.Params.polycoeff(2)
+    x, info, _ = gpu_solve(data["D"], data["O"], data["b"], data["offsets"], P)
+    for i, rows, oblk in orc.batch_slices(data["offsets"]):
+        xr, ri = orc.pcg(data["D"][rows], data["O"][oblk], data["b"][rows],
+                         m=2, alpha=orc.polycoeff(2))
+        assert info[i]["status"] == bt.OK
+        assert iteration_match(int(info[i]["iters"]), ri), (i, info[i], ri)
+        if info[i]["iters"] == ri["iters"]:
+            assert rel(x[rows], xr) <= 1e-10
+
+
+def test_batch_f32_refinement_small():
+    B = 64
+    data = lqrgen.lqr_batch(B, (16, 64), 12, 4, seed=91, record="f32")
+    P = bt.Params.polycoeff(2, prec="f32_ir")
+    x, info, _ = gpu_solve(data["D"], data["O"], data["b"], data["offsets"], P,
+                           record="f32")
+    assert np.all(info["status"] == bt.OK), info
+    assert np.all(info["relres_true"] <= 1e-10)
+    for i, rows, oblk in orc.batch_slices(data["offsets"]):
+        if i % 8:
+            continue
+        xd = orc.btchol_solve(data["D"][rows], data["O"][oblk], data["b"][rows])
+        r = data["b"][rows] - orc.spmv(data["D"][rows], data["O"][oblk], x[rows])
+        assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(data["b"][rows])
+        assert rel(x[rows], xd) <= 1e-5
+
+
+@pytest.mark.parametrize("name", ["polycoeff_m2", "jacobi_m2", "stairs_m2",
+                                  "equal_m3", "none", "polycoeff_m1"])
+def test_precondition_matches_oracle(name):
+    import torch
+    d = lqrgen.lqr_instance(20, 6, 2, 5, 1)
+    P = VARIANTS[name]
+    h = bt.Handle(torch.tensor(d["D"], device="cuda"),
+                  torch.tensor(d["O"], device="cuda"), None, P)
+    r = np.random.default_rng(3).standard_normal((20, 6))
+    z = h.precondition(torch.tensor(r.reshape(-1), device="cuda"))
+    zr = orc.precond(d["D"], d["O"], r, **oracle_kind(P))
+    assert rel(z.cpu().numpy().reshape(20, 6), zr) <= 1e-12
+
+
+def test_precondition_f32():
+    import torch
+    d = lqrgen.lqr_instance(20, 6, 2, 5, 1)
+    P = bt.Params.polycoeff(2, prec="f32_ir")
+    h = bt.Handle(torch.tensor(d["D"], device="cuda", dtype=torch.float32),
+                  torch.tensor(d["O"], device="cuda", dtype=torch.float32),
+                  None, P)
+    r = np.random.default_rng(3).standard_normal((20, 6))
+    z = h.precondition(torch.tensor(r.reshape(-1), device="cuda"))
+    D32 = d["D"].astype(np.float32).astype(np.float64)
+    O32 = d["O"].astype(np.float32).astype(np.float64)
+    zr = orc.precond(D32, O32, r, m=2, alpha=orc.polycoeff(2))
+    assert rel(z.cpu().numpy().reshape(20, 6), zr) <= 1e-4
+
+
+# ------------------------------------------------------------- edge cases
+def test_zero_rhs_and_single_block():
+    d = lqrgen.lqr_instance(1, 4, 2, 1, 0)
+    x, info, _ = gpu_solve(d["D"], d["O"], np.zeros((1, 4)),
+                           params=bt.Params.polycoeff(2))
+    assert info[0]["status"] == bt.OK and info[0]["iters"] == 0
+    assert not np.any(x)
+    x, info, _ = gpu_solve(d["D"], d["O"], d["b"], params=bt.Params.polycoeff(2))
+    assert info[0]["iters"] == 1
+    assert rel(x, np.linalg.solve(d["D"][0], d["b"][0])[None]) <= 1e-13
+
+
+def test_not_spd_block_reported():
+    data = lqrgen.lqr_batch(3, 6, 3, 1, seed=3)
+    D = data["D"].copy()
+    D[6 + 4] = -np.eye(3)          # instance 1, block row 4
+    x, info, _ = gpu_solve(D, data["O"], data["b"], data["offsets"],
+                           bt.Params.polycoeff(2))
+    assert info[1]["status"] == bt.ENOTSPD and info[1]["fail_index"] == 4
+    assert info[0]["status"] == bt.OK and info[2]["status"] == bt.OK
+
+
+def test_iteration_cap_and_nonfinite():
+    d = lqrgen.lqr_instance(32, 6, 3, 9, 0)
+    x, info, _ = gpu_solve(d["D"], d["O"], d["b"], params=bt.Params(pc="none",
+                                                                     m=1),
+                           maxit=5)
+    assert info[0]["status"] == bt.NOT_CONVERGED and info[0]["iters"] == 5
+    xr, ri = orc.pcg(d["D"], d["O"], d["b"], kind=orc.PC_NONE, maxit=5)
+    assert rel(x, xr) <= 1e-11
+    b = d["b"].copy()
+    b[3, 2] = np.nan
+    x, info, _ = gpu_solve(d["D"], d["O"], b, params=bt.Params.polycoeff(2))
+    assert info[0]["status"] == bt.ENONFINITE
+
+
+def test_indefinite_system_breaks_down():
+    """A with SPD diagonal blocks but indefinite as a whole (upper blocks
+    placed untransposed in the LQR recipe, large enough to lose SPD)."""
+    D = np.stack([np.eye(1)] * 2)
+    O = np.array([[[2.0]]])
+    x, info, _ = gpu_solve(D, O, np.array([[1.0], [-1.0]]),
+                           params=bt.Params(pc="none", m=1))
+    assert info[0]["status"] == bt.EBREAKDOWN
+
+
+def test_deterministic_repeat():
+    d = workload("single_n12")
+    x1, i1, _ = gpu_solve(d["D"], d["O"], d["b"], params=bt.Params.polycoeff(2))
+    x2, i2, _ = gpu_solve(d["D"], d["O"], d["b"], params=bt.Params.polycoeff(2))
+    assert np.array_equal(x1, x2) and i1[0]["iters"] == i2[0]["iters"]
+
+
+# ---------------------------------------------------------------- adjoint
+def test_adjoint_matches_oracle_gradient():
+    import torch
+    data = lqrgen.lqr_batch(3, (6, 12), 4, 2, seed=12, with_target=True)
+    D, O, b, t = data["D"], data["O"], data["b"], data["t"]
+    Dt = torch.tensor(D, device="cuda", requires_grad=True)
+    Ot = torch.tensor(O, device="cuda", requires_grad=True)
+    bt_ = torch.tensor(b, device="cuda", requires_grad=True)
+    tt = torch.tensor(t, device="cuda")
+    x = bt.bt_solve(Dt, Ot, bt_, data["offsets"], bt.Params.polycoeff(2),
+                    tol=1e-13)
+    loss = ((x - tt) ** 2).sum()
+    loss.backward()
+    for i, rows, oblk in orc.batch_slices(data["offsets"]):
+        xo = orc.btchol_solve(D[rows], O[oblk], b[rows])
+        lam, dD, dO = orc.adjoint(D[rows], O[oblk], xo, 2 * (xo - t[rows]))
+        assert rel(bt_.grad[rows].cpu().numpy(), lam) <= 1e-9
+        assert rel(Dt.grad[rows].cpu().numpy(), dD) <= 1e-9
+        assert rel(Ot.grad[oblk].cpu().numpy(), dO) <= 1e-9
