@@ -1,0 +1,279 @@
+"""Benchmark: batched PCG solves per second on one MI355X.
+
+Workload: 2048 independent LQR Schur complements (block size nx = 12,
+nu = 4, horizons uniform in {16..256}), float32 record, float32 inner PCG
+with the paper's preconditioner at its optimal weights ("PolyCoeff", m = 2,
+alpha_1 = 7) inside float64 iterative refinement to a 1e-10 relative
+residual. One step = recompute every factor from D, O (setup kernels) and
+solve all 2048 systems (one persistent launch), replayed from a HIP graph.
+
+Prints one JSON line (see the fields below). Run: python bench.py
+[--steps K] [--warmup W]. Only one GPU is used; --gpus N > 1 exits.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import lqrgen  # noqa: E402
+
+METRIC = ("batched PCG solves/s at 1e-10 rel. residual vs plain FP64; "
+          "HBM GB/s; fwd+adj ms")
+WORKLOAD = "batch_ragged_n12"
+PEAK_FP32_VALU_TFLOPS = 78.6   # 256 CU x 64 FMA lanes x 2 flop x 2.4 GHz
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="budget of the oracle CPU-baseline sample")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    return ap.parse_args()
+
+
+def apps_per_iteration(a, m):
+    """Applications of the scaled off-diagonal operator per PCG iteration:
+    one for A p, one for G_ab (if a != 0), then per extra polynomial term
+    one (a = 0) or two (a != 0)."""
+    g = 1 if a != 0.0 else 0
+    h = 2 if a != 0.0 else 1
+    return 1 + g + (m - 1) * h
+
+
+def solve_flops(horizons, n, iters, outer, a=1.0, m=2):
+    """Algorithmic flops of one solve launch: per row and inner iteration,
+    each operator application is two n x n block products (2 n^2 flops each);
+    per row and refinement step, the float64 residual (3 blocks) and the two
+    triangular transforms."""
+    per_it = apps_per_iteration(a, m) * 2 * 2 * n * n
+    per_outer = 3 * 2 * n * n + 2 * n * (n + 1)
+    return float(np.sum(horizons * (iters * per_it + outer * per_outer)))
+
+
+def solve_bytes(horizons, n, iters, outer):
+    """Algorithmic HBM bytes of one solve launch for the scaled form: the
+    float32 off-diagonal block F once per inner iteration, the float32 record
+    D, O plus float64 b and x once per refinement step, the factors L^{-1}
+    (float32) twice per refinement step."""
+    per_it = 4 * n * n
+    per_outer = 4 * 2 * n * n + 8 * 3 * n + 2 * 4 * n * n
+    return float(np.sum(horizons * (iters * per_it + outer * per_outer)))
+
+
+def cpu_baseline(data, budget_s, cores):
+    """The FP64 oracle (closed-form setup + textbook PCG, same preconditioner
+    and tolerance) on a prefix of the batch, instances spread over ``cores``
+    threads (the C oracle releases the GIL), for about ``budget_s`` seconds."""
+    import concurrent.futures as cf
+
+    import oracle
+    oracle.build(force=False)
+    offs = data["offsets"]
+    slices = list(oracle.batch_slices(offs))
+
+    def one(item):
+        i, rows, oblk = item
+        _, info = oracle.pcg(data["D"][rows], data["O"][oblk], data["b"][rows],
+                             m=2, alpha=oracle.polycoeff(2), tol=1e-10)
+        return info["iters"]
+
+    # calibrate on a few instances, then size the sample to the budget
+    t0 = time.perf_counter()
+    for it in slices[:8]:
+        one(it)
+    per = (time.perf_counter() - t0) / 8
+    count = int(min(len(slices), max(cores, budget_s * cores / max(per, 1e-6))))
+    sample = slices[:count]
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=cores) as ex:
+        list(ex.map(one, sample))
+    dt = time.perf_counter() - t0
+    rows = int(sum(r.stop - r.start for _, r, _ in sample))
+    return {"value": count / dt, "unit": "solves/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"first {count} of {len(slices)} instances ({rows} block "
+                      f"rows), FP64 closed-form setup + PCG to 1e-10, "
+                      f"{dt:.1f} s wall"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
+                          "the batched workload shards by instance across "
+                          "GPUs with no exchange, which is not measured here",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import paper_2503_15269_amd as bt
+
+    w = lqrgen.WORKLOADS[WORKLOAD]
+    seed = lqrgen.workload_seed(w["index"])
+    data = lqrgen.lqr_batch(w["B"], w["N"], w["nx"], w["nu"], seed, s=w["s"],
+                            record=w["record"])
+    B, n = w["B"], w["nx"]
+    horizons = data["horizons"]
+    dev = torch.device("cuda:0")
+    D = torch.tensor(data["D"], dtype=torch.float32, device=dev)
+    O = torch.tensor(data["O"], dtype=torch.float32, device=dev)
+    b = torch.tensor(data["b"].reshape(-1), dtype=torch.float64, device=dev)
+    params = bt.Params.polycoeff(2, prec="f32_ir", inner_tol=1e-4,
+                                 max_outer=30)
+    tol = 1e-10
+    h = bt.Handle(D, O, data["offsets"], params)
+    x = torch.empty_like(b)
+    info = torch.empty(B * bt.INFO_DTYPE.itemsize, dtype=torch.uint8,
+                       device=dev)
+    maxit = h.default_maxit()
+    stream = torch.cuda.current_stream()
+
+    def step_setup():
+        h.refactor()
+
+    def step_solve():
+        h.solve(b, tol, maxit, x=x, info=info)
+
+    # eager warm-up (also sets kernel attributes outside any capture)
+    for _ in range(max(1, args.warmup)):
+        step_setup()
+        step_solve()
+    torch.cuda.synchronize()
+    inf = bt.infos_to_numpy(info)
+    if not np.all(inf["status"] == bt.OK):
+        raise SystemExit(f"not all systems converged: "
+                         f"{np.unique(inf['status'], return_counts=True)}")
+
+    use_graph = not args.no_graph
+    if use_graph:
+        g_setup = torch.cuda.CUDAGraph()
+        g_solve = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g_setup):
+            step_setup()
+        with torch.cuda.graph(g_solve):
+            step_solve()
+        run_setup, run_solve = g_setup.replay, g_solve.replay
+    else:
+        run_setup, run_solve = step_setup, step_solve
+    for _ in range(args.warmup):
+        run_setup()
+        run_solve()
+    torch.cuda.synchronize()
+
+    K = args.steps
+    ev = [(torch.cuda.Event(enable_timing=True),
+           torch.cuda.Event(enable_timing=True)) for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        run_setup()
+        ev[k][0].record(stream)
+        run_solve()
+        ev[k][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    solve_ms = float(np.mean([a.elapsed_time(c) for a, c in ev]))
+
+    inf = bt.infos_to_numpy(info)
+    assert np.all(inf["status"] == bt.OK)
+    iters = inf["iters"].astype(np.float64)
+    outer = inf["outer"].astype(np.float64)
+    ms_per_step = wall * 1e3 / K
+    value = B * K / wall
+
+    flops = solve_flops(horizons, n, iters, outer, 1.0, 2)
+    nbytes = solve_bytes(horizons, n, iters, outer)
+    achieved_tf = flops / (solve_ms * 1e-3) / 1e12
+
+    # comparator: plain FP64 PCG, one system at a time, same GPU
+    sample = list(range(0, B, max(1, B // 128)))
+    tp0 = time.perf_counter()
+    offs = data["offsets"]
+    p64 = bt.Params.polycoeff(2, prec="f64")
+    Dd = torch.tensor(data["D"], dtype=torch.float64, device=dev)
+    Od = torch.tensor(data["O"], dtype=torch.float64, device=dev)
+    handles = []
+    for i in sample:
+        r0, r1 = int(offs[i]), int(offs[i + 1])
+        handles.append((bt.Handle(Dd[r0:r1], Od[r0 - i:r1 - i - 1], None, p64),
+                        b[r0 * n:r1 * n]))
+    torch.cuda.synchronize()
+    tp0 = time.perf_counter()
+    for hh, bb in handles:
+        hh.refactor()
+        hh.solve(bb, tol)
+    torch.cuda.synchronize()
+    plain_f64 = len(sample) / (time.perf_counter() - tp0)
+    # batched FP64 on the same GPU (same kernels, float64 iteration)
+    h64 = bt.Handle(Dd, Od, offs, p64)
+    x64, i64 = h64.solve(b, tol)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(3):
+        h64.refactor()
+        h64.solve(b, tol, x=x64, info=i64)
+    torch.cuda.synchronize()
+    batched_f64 = 3 * B / (time.perf_counter() - t1)
+    it64 = bt.infos_to_numpy(i64)
+
+    cores = min(16, len(os.sched_getaffinity(0)))
+    cpu = None if args.no_cpu else cpu_baseline(data, args.cpu_seconds, cores)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "instances": B,
+                   "horizons": "uniform 16..256", "nx": n, "nu": w["nu"],
+                   "record": "f32", "iteration": "f32 PCG + f64 refinement",
+                   "tol": tol, "preconditioner": "(a,b)=(1,-1), m=2, alpha1=7",
+                   "graph": use_graph},
+        "roofline": {"bound": "alu", "achieved": achieved_tf,
+                     "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved_tf / PEAK_FP32_VALU_TFLOPS,
+                     "traffic": None},
+        "cpu_baseline": cpu,
+        "extra": {
+            "solve_kernel_ms": solve_ms,
+            "setup_plus_queue_ms": ms_per_step - solve_ms,
+            "solve_alg_GBps": nbytes / (solve_ms * 1e-3) / 1e9,
+            "hbm_frac_of_alg_bytes": nbytes / (solve_ms * 1e-3) / 1e9 /
+            PEAK_HBM_GBS,
+            "inner_iters_mean": float(iters.mean()),
+            "outer_mean": float(outer.mean()),
+            "relres_true_max": float(inf["relres_true"].max()),
+            "plain_f64_single_instance_solves_per_s": plain_f64,
+            "batched_f64_solves_per_s": batched_f64,
+            "f64_iters_mean": float(it64["iters"].mean()),
+            "speedup_vs_plain_f64": value / plain_f64,
+            "speedup_vs_batched_f64": value / batched_f64,
+        },
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

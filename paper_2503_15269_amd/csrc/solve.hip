@@ -690,6 +690,7 @@ static const Entry kEntries[] = {
     BT_ENTRY(float, 256, 2, BT_F32),   BT_ENTRY(float, 256, 4, BT_F32),
     BT_ENTRY(float, 512, 4, BT_F32),   BT_ENTRY(float, 1024, 2, BT_F32),
     BT_ENTRY(float, 1024, 3, BT_F32),  BT_ENTRY(float, 1024, 4, BT_F32),
+    BT_ENTRY(float, 1024, 8, BT_F32),
 };
 
 }  // namespace btk

@@ -37,10 +37,13 @@ def oracle_kind(params):
     return dict(kind=kind, a=a, b=b, m=params.m, alpha=params.alpha)
 
 
-def iteration_match(gpu_it, ref_info, margin=1e-6):
+def iteration_match(gpu_it, ref_info, margin=1e-6, slack=0):
     """Equal iteration counts, or off by one only when the oracle's stopping
-    test was within ``margin`` of its threshold at the last two iterates."""
-    if gpu_it == ref_info["iters"]:
+    test was within ``margin`` of its threshold at the last two iterates.
+    ``slack`` widens this for runs longer than the dimension of the system
+    (plain CG without preconditioner), where CG has lost finite termination
+    and the count depends on the rounding order of its dot products."""
+    if abs(gpu_it - ref_info["iters"]) <= slack:
         return True
     near = (abs(ref_info["ratio_last"] - 1) < margin or
             abs(ref_info["ratio_prev"] - 1) < margin)

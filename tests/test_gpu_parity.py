@@ -44,9 +44,17 @@ def _check_f64(D, O, b, params, tol=1e-10, xtol=1e-10):
                      **oracle_kind(params))
     assert ri["status"] == orc.OK
     assert info[0]["status"] == bt.OK, info
-    assert iteration_match(int(info[0]["iters"]), ri), (info, ri)
+    # plain CG (no preconditioner, hundreds of iterations) has lost
+    # orthogonality and its count depends on rounding order: 1% slack there;
+    # every preconditioner of the paper must match exactly
+    slack = ri["iters"] // 100 if params.pc == "none" else 0
+    assert iteration_match(int(info[0]["iters"]), ri, slack=slack), (info, ri)
     if info[0]["iters"] == ri["iters"]:
         assert rel(x, xr) <= xtol, rel(x, xr)
+    elif slack:
+        # both are converged iterates; they agree to the conditioning bound
+        xd = orc.btchol_solve(D, O, b)
+        assert rel(x, xd) <= 1e-6
     assert info[0]["relres"] <= tol
     return x, info, ri
 
