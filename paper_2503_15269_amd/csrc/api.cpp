@@ -58,7 +58,7 @@ int64_t check_offsets(int B, const int64_t* off, int* maxN) {
 }
 
 struct Layout {
-  size_t off, order, ctr, fail, F, L, Li, total;
+  size_t off, order, ctr, fail, bins, items, F, L, Li, total;
 };
 
 Layout layout(int B, int64_t R, int n, size_t es) {
@@ -68,6 +68,8 @@ Layout layout(int B, int64_t R, int n, size_t es) {
   l.order = at; at += align_up(sizeof(int32_t) * B);
   l.ctr = at; at += align_up(sizeof(int32_t) * 64);
   l.fail = at; at += align_up(sizeof(int32_t) * B);
+  l.bins = at; at += align_up(sizeof(int32_t) * 2 * B);
+  l.items = at; at += align_up(sizeof(int32_t) * B);
   const size_t blk = align_up(es * (size_t)R * n * n);
   l.F = at; at += blk;
   l.L = at; at += blk;
@@ -76,8 +78,18 @@ Layout layout(int B, int64_t R, int n, size_t es) {
   return l;
 }
 
-// Smallest configuration of the right precision whose capacity holds the
-// largest system; ties go to the smaller workgroup.
+// Configuration index of the register-resident bin kernel (after the
+// generic ones).
+int fast_index() { return bt_num_kernel_configs(); }
+bool is_fast(int cfg) { return cfg == fast_index(); }
+const KernelConfig kFastConfig = {1024, 0, BT_F32};
+
+const KernelConfig& config_at(int i) {
+  return is_fast(i) ? kFastConfig : bt_kernel_config_at(i);
+}
+
+// Smallest generic configuration of the right precision whose capacity holds
+// the largest system; ties go to the smaller workgroup.
 int auto_config(int prec, int64_t maxP) {
   int best = -1;
   int64_t bestcap = 0;
@@ -95,9 +107,44 @@ int auto_config(int prec, int64_t maxP) {
   return best;
 }
 
+int generic_config(const bt_handle* h) {
+  return auto_config(kernel_prec(&h->p), (int64_t)h->maxN * h->n);
+}
+
 int config_for(const bt_handle* h) {
   if (h->cfg >= 0) return h->cfg;
-  return auto_config(kernel_prec(&h->p), (int64_t)h->maxN * h->n);
+  if (h->nbins > 0) return fast_index();
+  return generic_config(h);
+}
+
+// First-fit-decreasing packing of the systems (longest first) into bins of
+// the register-resident kernel: each system takes its length rounded up to
+// whole wavefronts of rows; a bin holds at most ``cap`` rows.
+void pack_bins(const std::vector<int32_t>& order, const int64_t* off, int rpw,
+               int cap, int maxper, std::vector<int32_t>& bins,
+               std::vector<int32_t>& items) {
+  std::vector<int> used;
+  std::vector<std::vector<int32_t>> members;
+  for (int32_t id : order) {
+    const int len = (int)(off[id + 1] - off[id]);
+    const int pad = (len + rpw - 1) / rpw * rpw;
+    size_t b = 0;
+    for (; b < used.size(); ++b)
+      if (used[b] + pad <= cap && (int)members[b].size() < maxper) break;
+    if (b == used.size()) {
+      used.push_back(0);
+      members.emplace_back();
+    }
+    used[b] += pad;
+    members[b].push_back(id);
+  }
+  bins.clear();
+  items.clear();
+  for (size_t b = 0; b < members.size(); ++b) {
+    bins.push_back((int32_t)items.size());
+    bins.push_back((int32_t)members[b].size());
+    items.insert(items.end(), members[b].begin(), members[b].end());
+  }
 }
 
 int hip_status(hipError_t e) { return e == hipSuccess ? BT_OK : BT_EHIP; }
@@ -146,8 +193,17 @@ SolveArgs base_args(const bt_handle* h) {
 }
 
 int run(const bt_handle* h, SolveArgs& a, hipStream_t s) {
-  const int cfg = config_for(h);
+  int cfg = config_for(h);
+  if (is_fast(cfg) && (a.mode != 0 || !a.ir)) cfg = generic_config(h);
   if (cfg < 0) return BT_EINVAL;
+  if (is_fast(cfg)) {
+    a.bins = h->bins;
+    a.bin_items = h->bin_items;
+    a.nbins = h->nbins;
+    const int grid =
+        std::max(1, std::min(h->nbins, bt_fast_max_grid(h->n)));
+    return hip_status(bt_launch_fast(a, grid, s));
+  }
   const int grid = std::max(1, std::min(h->B, bt_solve_max_grid(cfg)));
   return hip_status(bt_launch_solve(cfg, a, grid, s));
 }
@@ -223,6 +279,8 @@ int bt_batch_setup(bt_handle** h, int B, const int64_t* offsets_host, int n,
   hh->order = (int32_t*)(w + l.order);
   hh->ctr = (int32_t*)(w + l.ctr);
   hh->fail = (int32_t*)(w + l.fail);
+  hh->bins = (int32_t*)(w + l.bins);
+  hh->bin_items = (int32_t*)(w + l.items);
   hh->F = w + l.F;
   hh->L = w + l.L;
   hh->Li = w + l.Li;
@@ -235,11 +293,25 @@ int bt_batch_setup(bt_handle** h, int B, const int64_t* offsets_host, int n,
     return offsets_host[x + 1] - offsets_host[x] >
            offsets_host[y + 1] - offsets_host[y];
   });
+  std::vector<int32_t> bins, items;
+  if (bt_fast_params(p) && bt_fast_supported(n, p->prec) &&
+      maxN <= bt_fast_rows_per_bin(n)) {
+    pack_bins(order, offsets_host, bt_fast_rows_per_wave(n),
+              bt_fast_rows_per_bin(n), bt_fast_max_systems_per_bin(), bins,
+              items);
+    hh->nbins = (int)(bins.size() / 2);
+  }
   hipStream_t s = (hipStream_t)stream;
   if (hipMemcpyAsync(hh->off, hh->off_host.data(), sizeof(int64_t) * (B + 1),
                      hipMemcpyHostToDevice, s) != hipSuccess ||
       hipMemcpyAsync(hh->order, order.data(), sizeof(int32_t) * B,
                      hipMemcpyHostToDevice, s) != hipSuccess ||
+      (hh->nbins > 0 &&
+       (hipMemcpyAsync(hh->bins, bins.data(), sizeof(int32_t) * bins.size(),
+                       hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(hh->bin_items, items.data(),
+                       sizeof(int32_t) * items.size(), hipMemcpyHostToDevice,
+                       s) != hipSuccess)) ||
       hipStreamSynchronize(s) != hipSuccess) {
     delete hh;
     return BT_EHIP;
@@ -312,11 +384,11 @@ int bt_solve_adjoint(const bt_handle* h, const double* x, const double* g,
                                             (hipStream_t)stream));
 }
 
-int bt_kernel_config_count(void) { return bt_num_kernel_configs(); }
+int bt_kernel_config_count(void) { return bt_num_kernel_configs() + 1; }
 
 int bt_kernel_config(int i, int* nt, int* s, int* prec) {
-  if (i < 0 || i >= bt_num_kernel_configs()) return BT_EINVAL;
-  const KernelConfig& c = bt_kernel_config_at(i);
+  if (i < 0 || i > bt_num_kernel_configs()) return BT_EINVAL;
+  const KernelConfig& c = config_at(i);
   if (nt) *nt = c.nt;
   if (s) *s = c.s;
   if (prec) *prec = c.prec;
@@ -329,7 +401,12 @@ int bt_set_kernel_config(bt_handle* h, int i) {
     h->cfg = -1;
     return BT_OK;
   }
-  if (i >= bt_num_kernel_configs()) return BT_EINVAL;
+  if (i > bt_num_kernel_configs()) return BT_EINVAL;
+  if (is_fast(i)) {
+    if (h->nbins <= 0) return BT_EINVAL;
+    h->cfg = i;
+    return BT_OK;
+  }
   const KernelConfig& c = bt_kernel_config_at(i);
   if (c.prec != kernel_prec(&h->p)) return BT_EINVAL;
   if ((int64_t)c.nt * c.s < (int64_t)h->maxN * h->n) return BT_EINVAL;

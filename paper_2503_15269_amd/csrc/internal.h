@@ -21,6 +21,9 @@ struct bt_handle {
   int32_t* order = nullptr; // [B] instances, longest first
   int32_t* ctr = nullptr;   // [64] queue counters of the persistent kernels
   int32_t* fail = nullptr;  // [B] first failing block row, BT_NO_FAIL if none
+  int32_t* bins = nullptr;  // [B][2] bins of the register-resident kernel
+  int32_t* bin_items = nullptr;  // [B]
+  int nbins = 0;            // 0: the register-resident kernel does not apply
   void* F = nullptr;        // [R][n][n] scaled off-diagonal blocks
   void* L = nullptr;        // [R][n][n] Cholesky factors of D_k
   void* Li = nullptr;       // [R][n][n] their inverses
@@ -40,6 +43,9 @@ struct SolveArgs {
   int maxit, max_outer;
   const int64_t* off;
   const int32_t* order;
+  const int32_t* bins;       // register-resident kernel: [nbins][2] (start, count)
+  const int32_t* bin_items;  // systems of the bins, bin after bin
+  int nbins;
   int32_t* ctr;
   const int32_t* fail;
   const void* F;
@@ -66,7 +72,8 @@ struct SetupArgs {
 };
 
 struct KernelConfig {
-  int nt, s, prec;  // prec: BT_F64 for double kernels, BT_F32 for float ones
+  int nt, s, prec;  // prec: BT_F64 for double kernels, BT_F32 for float ones;
+                    // s = 0: the register-resident bin kernel
 };
 
 int bt_num_kernel_configs();
@@ -75,6 +82,13 @@ hipError_t bt_launch_solve(int cfg, const SolveArgs& a, int grid,
                            hipStream_t s);
 int bt_solve_max_grid(int cfg);
 hipError_t bt_launch_setup(const SetupArgs& a, hipStream_t s);
+bool bt_fast_supported(int n, int prec);
+bool bt_fast_params(const bt_params* p);
+int bt_fast_rows_per_wave(int n);
+int bt_fast_rows_per_bin(int n);
+int bt_fast_max_systems_per_bin();
+hipError_t bt_launch_fast(const SolveArgs& a, int grid, hipStream_t s);
+int bt_fast_max_grid(int n);
 hipError_t bt_launch_setup_init(int B, int32_t* fail, int32_t* ctr,
                                 hipStream_t s);
 hipError_t bt_launch_adjoint_outer(int B, int n, int64_t R,

@@ -1,0 +1,612 @@
+// Register-resident PCG kernel for small block sizes (float32 inner PCG in
+// float64 iterative refinement).
+//
+// Same method and coordinates as the generic kernel (solve.hip): the
+// iteration runs on Ahat = L^{-1} A L^{-T} = I - C with the scaled
+// off-diagonal blocks F_k = L_k^{-1} O_k L_{k+1}^{-T},
+//   (C v)_k = -(F_{k-1}^T v_{k-1} + F_k v_{k+1}),
+// and the preconditioner of eq. Mminv-polynomial-coefficients is the
+// polynomial  sum_i alpha_i ((1-a) C + a C^2)^i (I + a C),  evaluated as
+// y_0 = G r, y_i = H y_{i-1}, z = sum alpha_i y_i.
+//
+// Layout on the chip. A workgroup of 1024 threads owns a "bin" of systems
+// whose block rows (each system padded to a whole wavefront of rows) total at
+// most RPB. TPR = NB/3 neighbouring lanes (a quad for NB = 12) share a block
+// row k; lane q owns entries 3q..3q+2 of every vector row and keeps rows
+// 3q..3q+2 of F_k in registers (3*NB floats), read from memory once per bin.
+// One application of C then needs, per lane:
+//   * the forward product F_k v_{k+1}: its 3 rows times the next vector row,
+//     read from LDS (TPR 16-byte broadcast reads);
+//   * the transposed product F_{k-1}^T v_{k-1}: the lanes of row k-1 form
+//     partial sums over their own rows for all NB columns (own vector
+//     entries, no LDS), reduce-scatter them inside the row with DPP quad
+//     permutations (xor 2, then xor 1), and hand the 3 finished sums of lane q
+//     to lane q of row k through LDS.
+// The column order of the F registers is permuted per lane (chunk c of lane q
+// holds columns 3 (c xor q) .. +2) so that the reduce-scatter needs no
+// selects. Systems start on a wavefront boundary, so every per-system
+// quantity (scalars, convergence masks) is uniform within a wavefront;
+// reductions are a DPP wave sum plus an in-order sum over the system's
+// wavefronts, and a converged system stops updating while the others in its
+// bin go on. F is zero for the last row of a system, so systems sharing a bin
+// do not couple.
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+#include "reduce.h"
+
+namespace btf {
+
+using btk::AccD;
+using btk::AccF;
+
+constexpr int NT = 1024;
+constexpr int NW = NT / 64;
+constexpr int SL = 4;      // reduction slots (reuse distance)
+constexpr int MAXI = 64;   // systems per bin, upper bound
+constexpr int EPT = 3;     // vector entries per lane
+
+template <int NB>
+struct Geo {
+  static constexpr int TPR = NB / EPT;   // lanes per block row
+  static constexpr int RPW = 64 / TPR;   // block rows per wavefront
+  static constexpr int RPB = NT / TPR;   // block rows per bin
+  static constexpr int ROW = TPR * 4;    // floats per staged row (padded)
+  static_assert(NB % EPT == 0, "block size must be a multiple of 3");
+  static_assert(TPR == 2 || TPR == 4, "2 or 4 lanes per block row");
+};
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// wave-uniform values into scalar registers
+__device__ __forceinline__ int uni(int v) {
+  return __builtin_amdgcn_readfirstlane(v);
+}
+__device__ __forceinline__ double uni(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readfirstlane((int)(u & 0xffffffffll));
+  const int hi = __builtin_amdgcn_readfirstlane((int)(u >> 32));
+  return __longlong_as_double(((long long)hi << 32) |
+                              (long long)(unsigned int)lo);
+}
+
+template <int NB>
+struct Smem {
+  float V[2][Geo<NB>::RPB * Geo<NB>::ROW];  // staged vector rows
+  float T[2][Geo<NB>::RPB * Geo<NB>::ROW];  // transposed sums for row k+1
+  double xs[Geo<NB>::RPB * NB];             // float64 iterate of the bin
+  AccF redF[SL][NW];
+  double redD[SL][NW];
+  int active;   // running count of (wavefront, flag) events, never reset
+  int bin;
+  int cnt;
+  int inst[MAXI];
+  int lstart[MAXI];
+  int nrows[MAXI];
+};
+
+template <int NB>
+struct Ctx {
+  using G = Geo<NB>;
+  Smem<NB>& sm;
+  int lrow, q, wave, w0, w1;
+  int k, N;          // row within the system, system length (0: idle lane)
+  bool row_ok;       // a real block row (not padding, not idle)
+  int sf, sd, seen;
+  float Fr[EPT][NB]; // rows 3q..3q+2 of F_k, columns in lane order
+
+  __device__ Ctx(Smem<NB>& s) : sm(s) {}
+
+  __device__ __forceinline__ int col(int x) const {  // lane-order column
+    return EPT * ((x / EPT) ^ q) + x % EPT;
+  }
+
+  // ---- one application of C in two halves around a barrier -------------
+  template <int BUF>
+  __device__ __forceinline__ void prep(const float (&v)[EPT]) {
+    float P[NB];
+#pragma unroll
+    for (int x = 0; x < NB; ++x) {
+      float s = Fr[0][x] * v[0];
+#pragma unroll
+      for (int e = 1; e < EPT; ++e) s = __fmaf_rn(Fr[e][x], v[e], s);
+      P[x] = s;
+    }
+    float S[EPT];
+    if constexpr (G::TPR == 4) {
+      float K[2 * EPT];
+#pragma unroll
+      for (int y = 0; y < 2 * EPT; ++y)
+        K[y] = P[y] + dpp<btk::DPP_QUAD_2301>(P[2 * EPT + y]);
+#pragma unroll
+      for (int z = 0; z < EPT; ++z)
+        S[z] = K[z] + dpp<btk::DPP_QUAD_1032>(K[EPT + z]);
+    } else {
+#pragma unroll
+      for (int z = 0; z < EPT; ++z)
+        S[z] = P[z] + dpp<btk::DPP_QUAD_1032>(P[EPT + z]);
+    }
+    const int o = lrow * G::ROW + 4 * q;
+    *reinterpret_cast<float4*>(&sm.V[BUF][o]) = make_float4(v[0], v[1], v[2], 0.f);
+    *reinterpret_cast<float4*>(&sm.T[BUF][o]) = make_float4(S[0], S[1], S[2], 0.f);
+  }
+
+  template <int BUF>
+  __device__ __forceinline__ void finish(float (&y)[EPT]) {
+    const int rp = k < N - 1 ? lrow + 1 : lrow;
+    const float* vr = &sm.V[BUF][rp * G::ROW];
+    float vp[NB];
+#pragma unroll
+    for (int c = 0; c < G::TPR; ++c) {
+      const float4 u = *reinterpret_cast<const float4*>(vr + 4 * (c ^ q));
+      vp[EPT * c] = u.x;
+      vp[EPT * c + 1] = u.y;
+      vp[EPT * c + 2] = u.z;
+    }
+    float4 tp = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (k > 0)
+      tp = *reinterpret_cast<const float4*>(&sm.T[BUF][(lrow - 1) * G::ROW + 4 * q]);
+    const float tv[EPT] = {tp.x, tp.y, tp.z};
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      float s = tv[e];
+#pragma unroll
+      for (int x = 0; x < NB; ++x) s = __fmaf_rn(Fr[e][x], vp[x], s);
+      y[e] = -s;
+    }
+  }
+
+  template <int BUF>
+  __device__ __forceinline__ void C(const float (&v)[EPT], float (&y)[EPT]) {
+    prep<BUF>(v);
+    __syncthreads();
+    finish<BUF>(y);
+  }
+
+  // ---- reductions --------------------------------------------------------
+  __device__ __forceinline__ void put_wave(const AccF& acc) {
+    const AccF t = btk::wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) sm.redF[sf][wave] = t;
+  }
+  __device__ __forceinline__ double take() {  // after the barrier
+    AccF t = sm.redF[sf][w0];
+    for (int w = w0 + 1; w < w1; ++w) t.merge(sm.redF[sf][w]);
+    sf = (sf + 1) % SL;
+    return uni(t.value());
+  }
+  __device__ __forceinline__ double dot(const float (&x)[EPT],
+                                        const float (&y)[EPT]) {
+    AccF acc;
+    acc.zero();
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) acc.add_prod(x[e], y[e]);
+    put_wave(acc);
+    __syncthreads();
+    return take();
+  }
+  __device__ __forceinline__ double sumd(double v) {
+    AccD a;
+    a.s = v;
+    const AccD t = btk::wave_sum(a);
+    if ((threadIdx.x & 63) == 0) sm.redD[sd][wave] = t.s;
+    __syncthreads();
+    double s = sm.redD[sd][w0];
+    for (int w = w0 + 1; w < w1; ++w) s += sm.redD[sd][w];
+    sd = (sd + 1) % SL;
+    return uni(s);
+  }
+  // Any wavefront that raised its flag since the last check bumped the
+  // counter; every lane compares with the value it saw last time. The next
+  // bump happens only after a further barrier, so all lanes read the same.
+  __device__ __forceinline__ bool any_after_barrier() {
+    const int now = uni(sm.active);
+    const bool any = now != seen;
+    seen = now;
+    return any;
+  }
+  __device__ __forceinline__ void put_flag(bool f) {
+    if ((threadIdx.x & 63) == 0 && f) atomicAdd(&sm.active, 1);
+  }
+
+  // Stage own entries in natural layout for row-wise reads (transforms).
+  template <int BUF>
+  __device__ __forceinline__ const float* stage_row(const float (&v)[EPT]) {
+    *reinterpret_cast<float4*>(&sm.V[BUF][lrow * G::ROW + 4 * q]) =
+        make_float4(v[0], v[1], v[2], 0.f);
+    __syncthreads();
+    return &sm.V[BUF][lrow * G::ROW];
+  }
+
+  // z = M^{-1} r at the optimal weights (a, b) = (1, -1), in the scaled
+  // coordinates: G = I + C, H = C^2, so y_0 = r + C r, y_i = C (C y_{i-1}),
+  // z = y_0 + sum_i alpha_i y_i. C(r) is applied by the caller (fused with a
+  // reduction) and passed in as ``cr``.
+  template <int M>
+  __device__ __forceinline__ void precond_rest(const SolveArgs& a,
+                                               const float (&r)[EPT],
+                                               const float (&cr)[EPT],
+                                               float (&z)[EPT]) {
+    float y[EPT], w[EPT];
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      y[e] = r[e] + cr[e];
+      z[e] = y[e];
+    }
+#pragma unroll
+    for (int m = 1; m < M; ++m) {
+      C<0>(y, w);
+      C<1>(w, y);
+      const float al = (float)a.alpha[m];
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) z[e] = __fmaf_rn(al, y[e], z[e]);
+    }
+  }
+};
+
+template <int NB, int M, typename Rec>
+__global__ void __launch_bounds__(NT) k_fast_ir(SolveArgs a) {
+  using G = Geo<NB>;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  Smem<NB>& sm = *reinterpret_cast<Smem<NB>*>(smem_raw);
+  Ctx<NB> c(sm);
+  const int t = threadIdx.x;
+  c.lrow = t / G::TPR;
+  c.q = t % G::TPR;
+  c.wave = t >> 6;
+  c.sf = 0;
+  c.sd = 0;
+  if (t == 0) sm.active = 0;
+  __syncthreads();
+  c.seen = 0;
+  const size_t nn = (size_t)NB * NB;
+  const double itol2 = a.inner_tol * a.inner_tol;
+  const float* F = (const float*)a.F;
+  const float* Li = (const float*)a.Li;
+
+  for (;;) {
+    if (t == 0) sm.bin = atomicAdd(&a.ctr[2], 1);
+    __syncthreads();
+    const int bin = sm.bin;
+    if (bin >= a.nbins) break;
+    if (t == 0) {
+      const int start = a.bins[2 * bin], cnt = a.bins[2 * bin + 1];
+      int at = 0;
+      for (int j = 0; j < cnt; ++j) {
+        const int id = a.bin_items[start + j];
+        const int Nj = (int)(a.off[id + 1] - a.off[id]);
+        sm.inst[j] = id;
+        sm.lstart[j] = at;
+        sm.nrows[j] = Nj;
+        at += (Nj + G::RPW - 1) / G::RPW * G::RPW;
+      }
+      sm.cnt = cnt;
+    }
+    __syncthreads();
+
+    // ---- geometry of this lane ------------------------------------------
+    int j = -1;
+    for (int jj = 0; jj < sm.cnt; ++jj) {
+      const int ls = sm.lstart[jj];
+      const int pad = (sm.nrows[jj] + G::RPW - 1) / G::RPW * G::RPW;
+      if (c.lrow >= ls && c.lrow < ls + pad) j = jj;
+    }
+    const bool sys = j >= 0;  // uniform within the wavefront
+    int inst = 0;
+    bool lead = false;
+    if (sys) {
+      const int ls = sm.lstart[j];
+      const int pad = (sm.nrows[j] + G::RPW - 1) / G::RPW * G::RPW;
+      c.N = sm.nrows[j];
+      c.k = c.lrow - ls;
+      inst = sm.inst[j];
+      c.w0 = ls / G::RPW;
+      c.w1 = (ls + pad) / G::RPW;
+      lead = (c.k == 0 && c.q == 0);
+    } else {
+      c.N = 0;
+      c.k = 0;
+      c.w0 = c.wave;
+      c.w1 = c.wave + 1;
+    }
+    c.N = uni(c.N);
+    c.w0 = uni(c.w0);
+    c.w1 = uni(c.w1);
+    c.row_ok = sys && c.k < c.N;
+    const int64_t g = sys ? a.off[inst] + c.k : 0;  // global block row
+    const int64_t ob = g - inst;                     // its upper block
+
+    // ---- rows 3q..3q+2 of F_k into registers, lane column order ------------
+    {
+      const bool has_next = c.row_ok && c.k < c.N - 1;
+      const float* fk = F + (size_t)(has_next ? g : 0) * nn;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const float* row = fk + (size_t)(c.q * EPT + e) * NB;
+#pragma unroll
+        for (int cc = 0; cc < G::TPR; ++cc) {
+          const int src = EPT * (cc ^ c.q);
+#pragma unroll
+          for (int z = 0; z < EPT; ++z)
+            c.Fr[e][EPT * cc + z] = has_next ? row[src + z] : 0.f;
+        }
+      }
+    }
+
+    // ---- per-system state ----------------------------------------------
+    const int fail = sys ? a.fail[inst] : BT_NO_FAIL;
+    const int e0 = c.q * EPT;
+    double nbp = 0.0;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const double bv = c.row_ok ? a.b[g * NB + e0 + e] : 0.0;
+      nbp += bv * bv;
+      sm.xs[c.lrow * NB + e0 + e] = 0.0;
+    }
+    const double nb2 = c.sumd(nbp);
+    int status = BT_NOT_CONVERGED;
+    bool done = !sys;
+    if (sys && fail != BT_NO_FAIL) {
+      status = BT_ENOTSPD;
+      done = true;
+    } else if (sys && !(nb2 < INFINITY)) {
+      status = BT_ENONFINITE;
+      done = true;
+    } else if (sys && nb2 == 0.0) {
+      status = BT_OK;
+      done = true;
+    }
+    const double tol2 = a.tol * a.tol * nb2;
+    int outer = 0, total = 0;
+    double nr2 = nb2;
+
+    for (;;) {
+      // float64 residual of the record for the current iterate
+      float r64f[EPT];
+      {
+        double rp = 0.0;
+        const double* xk = sm.xs + c.lrow * NB;
+#pragma unroll 1
+        for (int e = 0; e < EPT; ++e) {
+          double r64 = 0.0;
+          if (c.row_ok && !done) {
+            const int i = e0 + e;
+            double acc = 0.0;
+            if (outer > 0) {
+              const size_t db = (size_t)g * nn + (size_t)i * NB;
+#pragma unroll 2
+              for (int jj = 0; jj < NB; ++jj)
+                acc += (double)((const Rec*)a.D)[db + jj] * xk[jj];
+              if (c.k < c.N - 1) {
+                const size_t o = (size_t)ob * nn + (size_t)i * NB;
+#pragma unroll 2
+                for (int jj = 0; jj < NB; ++jj)
+                  acc += (double)((const Rec*)a.O)[o + jj] * xk[NB + jj];
+              }
+              if (c.k > 0) {
+                const size_t o = (size_t)(ob - 1) * nn + i;
+#pragma unroll 2
+                for (int jj = 0; jj < NB; ++jj)
+                  acc += (double)((const Rec*)a.O)[o + (size_t)jj * NB] * xk[jj - NB];
+              }
+            }
+            r64 = a.b[g * NB + i] - acc;
+          }
+          rp += r64 * r64;
+          r64f[e] = (float)r64;
+        }
+        const double s = c.sumd(rp);  // its barrier also orders xs reads
+        if (!done && outer > 0) nr2 = s;
+      }
+      if (!done) {
+        if (nr2 <= tol2) {
+          status = BT_OK;
+          done = true;
+        } else if (!(nr2 < INFINITY)) {
+          status = BT_ENONFINITE;
+          done = true;
+        } else if (outer >= a.max_outer || total >= a.maxit) {
+          done = true;
+        }
+      }
+
+      // inner system  Ahat d = L^{-1} r64  for the systems still running
+      float r[EPT], d[EPT], p[EPT], z[EPT], qv[EPT];
+      {
+        *reinterpret_cast<float4*>(&sm.V[0][c.lrow * G::ROW + 4 * c.q]) =
+            make_float4(r64f[0], r64f[1], r64f[2], 0.f);
+        c.put_flag(!done);
+        __syncthreads();
+        if (!c.any_after_barrier()) break;  // every system of the bin is done
+        const float* rk = &sm.V[0][c.lrow * G::ROW];
+#pragma unroll 1
+        for (int e = 0; e < EPT; ++e) {
+          const int i = e0 + e;
+          float acc = 0.f;
+          if (c.row_ok && !done) {
+            const float* lr = Li + (size_t)g * nn + (size_t)i * NB;
+#pragma unroll 4
+            for (int jj = 0; jj < NB; ++jj)
+              if (jj <= i) acc = __fmaf_rn(lr[jj], rk[4 * (jj / EPT) + jj % EPT], acc);
+          }
+          r[e] = acc;
+          d[e] = 0.f;
+        }
+      }
+      const double n0 = c.dot(r, r);
+      const double itarget = itol2 * n0;
+      {
+        float cr[EPT];
+        c.template C<1>(r, cr);
+        c.template precond_rest<M>(a, r, cr, z);
+      }
+      double rho = c.dot(r, z);
+      bool act = !done && rho > 0.0;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) p[e] = z[e];
+      int inner = 0;
+      for (;;) {
+        // q = Ahat p = p - C p, fused with the "anyone still running" flag
+        c.template prep<0>(p);
+        c.put_flag(act);
+        __syncthreads();
+        if (!c.any_after_barrier()) break;
+        c.template finish<0>(qv);
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) qv[e] = p[e] - qv[e];
+        const double sigma = c.dot(p, qv);
+        if (act && !(sigma > 0.0)) act = false;
+        if (act) {
+          const float al = (float)(rho / sigma);
+#pragma unroll
+          for (int e = 0; e < EPT; ++e) {
+            d[e] = __fmaf_rn(al, p[e], d[e]);
+            r[e] = __fmaf_rn(-al, qv[e], r[e]);
+          }
+          ++inner;
+          ++total;
+        }
+        // ||r||^2 fused with the first operator application of M^{-1} r
+        float cr[EPT];
+        {
+          AccF acc;
+          acc.zero();
+#pragma unroll
+          for (int e = 0; e < EPT; ++e) acc.add_prod(r[e], r[e]);
+          c.template prep<1>(r);
+          c.put_wave(acc);
+          __syncthreads();
+          c.template finish<1>(cr);
+        }
+        const double rr = c.take();
+        if (act && (rr <= itarget || total >= a.maxit)) act = false;
+        c.template precond_rest<M>(a, r, cr, z);
+        const double rho1 = c.dot(r, z);
+        if (act) {
+          if (!(rho1 > 0.0)) {
+            act = false;
+          } else {
+            const float be = (float)(rho1 / rho);
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) p[e] = __fmaf_rn(be, p[e], z[e]);
+            rho = rho1;
+          }
+        }
+      }
+      // x64 += L^{-T} d
+      {
+        const float* dk = c.template stage_row<0>(d);
+        if (!done) {
+#pragma unroll 1
+          for (int e = 0; e < EPT; ++e) {
+            const int i = e0 + e;
+            if (c.row_ok) {
+              const float* lc = Li + (size_t)g * nn + i;
+              float acc = 0.f;
+#pragma unroll 4
+              for (int jj = 0; jj < NB; ++jj)
+                if (jj >= i)
+                  acc = __fmaf_rn(lc[(size_t)jj * NB], dk[4 * (jj / EPT) + jj % EPT], acc);
+              sm.xs[c.lrow * NB + i] += (double)acc;
+            }
+          }
+          ++outer;
+          if (inner == 0) {
+            status = BT_EBREAKDOWN;
+            done = true;
+          }
+        }
+        __syncthreads();  // xs complete before the next residual
+      }
+    }
+
+    if (c.row_ok) {
+#pragma unroll
+      for (int e = 0; e < EPT; ++e)
+        a.x[g * NB + e0 + e] = sm.xs[c.lrow * NB + e0 + e];
+    }
+    if (lead) {
+      bt_info* inf = a.info + inst;
+      inf->status = status;
+      inf->iters = total;
+      inf->outer = outer;
+      inf->fail_index = status == BT_ENOTSPD ? fail : -1;
+      const double rr = nb2 > 0.0 ? sqrt(nr2 / nb2) : 0.0;
+      inf->relres = status == BT_ENOTSPD ? NAN : rr;
+      inf->relres_true = status == BT_ENOTSPD ? NAN : rr;
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    __threadfence();
+    const int dn = atomicAdd(&a.ctr[3], 1);
+    if (dn == (int)gridDim.x - 1) {
+      atomicExch(&a.ctr[2], 0);
+      atomicExch(&a.ctr[3], 0);
+    }
+  }
+}
+
+template <int NB, int M, typename Rec>
+hipError_t launch_one(const SolveArgs& a, int grid, hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(
+        (const void*)k_fast_ir<NB, M, Rec>,
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(Smem<NB>));
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_fast_ir<NB, M, Rec>), dim3(grid), dim3(NT),
+                     sizeof(Smem<NB>), s, a);
+  return hipGetLastError();
+}
+
+template <int NB, typename Rec>
+hipError_t launch_rec(const SolveArgs& a, int grid, hipStream_t s) {
+  switch (a.m) {
+    case 1: return launch_one<NB, 1, Rec>(a, grid, s);
+    case 2: return launch_one<NB, 2, Rec>(a, grid, s);
+    case 3: return launch_one<NB, 3, Rec>(a, grid, s);
+    default: return launch_one<NB, 4, Rec>(a, grid, s);
+  }
+}
+
+template <int NB>
+int max_grid() {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                            dev) != hipSuccess)
+    cus = 256;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per, (const void*)k_fast_ir<NB, 2, float>, NT, sizeof(Smem<NB>)) !=
+          hipSuccess ||
+      per < 1)
+    per = 1;
+  return cus * per;
+}
+
+}  // namespace btf
+
+// The register-resident kernel covers the hot path: block size 12, float32
+// inner iteration with float64 refinement, the optimal weights (1,-1) and
+// polynomial order 1..4.
+bool bt_fast_supported(int n, int prec) { return prec == BT_F32_IR && n == 12; }
+bool bt_fast_params(const bt_params* p) {
+  return p->pc == BT_PC_POLY && p->a == 1.0 && p->m >= 1 && p->m <= 4;
+}
+
+int bt_fast_rows_per_wave(int n) { return btf::Geo<12>::RPW; }
+int bt_fast_rows_per_bin(int n) { return btf::Geo<12>::RPB; }
+int bt_fast_max_systems_per_bin() { return btf::MAXI; }
+
+hipError_t bt_launch_fast(const SolveArgs& a, int grid, hipStream_t s) {
+  if (a.dtype == BT_DT_F64) return btf::launch_rec<12, double>(a, grid, s);
+  return btf::launch_rec<12, float>(a, grid, s);
+}
+
+int bt_fast_max_grid(int n) { return btf::max_grid<12>(); }

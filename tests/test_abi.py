@@ -121,7 +121,10 @@ def test_kernel_configs_listed(lib):
     precs = {c[3] for c in cfgs}
     assert precs == {bt.F64, bt.F32}
     for _, nt, s, _ in cfgs:
-        assert nt % 64 == 0 and nt <= 1024 and s >= 1
+        assert nt % 64 == 0 and nt <= 1024 and s >= 0
+    # exactly one register-resident bin kernel (s == 0), float32
+    fast = [c for c in cfgs if c[2] == 0]
+    assert len(fast) == 1 and fast[0][3] == bt.F32
 
 
 def test_product_path_has_no_cpu_fallback():
