@@ -131,6 +131,149 @@ __global__ void __launch_bounds__(NT) k_setup(SetupArgs a) {
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Small block sizes: one lane per block row, everything in registers.
+// ---------------------------------------------------------------------------
+template <int NB>
+__device__ __forceinline__ constexpr int tri(int i, int j) {
+  return i * (i + 1) / 2 + j;  // packed lower triangle, row-major
+}
+
+// L_g = chol(D_g) and Li_g = L_g^{-1} (in place, row by row), float64.
+template <int NB, typename T, typename Rec>
+__global__ void __launch_bounds__(64) k_factor_lane(SetupArgs a) {
+  const int64_t g = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  if (g >= a.R) return;
+  constexpr int NL = NB * (NB + 1) / 2;
+  constexpr int NN = NB * NB;
+  double M[NL];
+  const Rec* D = (const Rec*)a.D + (size_t)g * NN;
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j <= i; ++j) M[tri<NB>(i, j)] = (double)D[i * NB + j];
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    double s = M[tri<NB>(j, j)];
+#pragma unroll
+    for (int p = 0; p < j; ++p) s -= M[tri<NB>(j, p)] * M[tri<NB>(j, p)];
+    if (!(s > 0.0 && s < INFINITY)) {
+      ok = false;
+      s = 1.0;
+    }
+    const double d = sqrt(s);
+    const double rd = 1.0 / d;
+    M[tri<NB>(j, j)] = d;
+#pragma unroll
+    for (int i = j + 1; i < NB; ++i) {
+      double t = M[tri<NB>(i, j)];
+#pragma unroll
+      for (int p = 0; p < j; ++p) t -= M[tri<NB>(i, p)] * M[tri<NB>(j, p)];
+      M[tri<NB>(i, j)] = t * rd;
+    }
+  }
+  if (!ok) {
+    const int inst = find_instance(a.off, a.B, g);
+    atomicMin(&a.fail[inst], (int)(g - a.off[inst]));
+  }
+  T* L = (T*)a.L + (size_t)g * NN;
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) L[i * NB + j] = (T)(j <= i ? M[tri<NB>(i, j)] : 0.0);
+  // X = L^{-1}: X[i][j] = -(1/L[i][i]) sum_{k=j}^{i-1} L[i][k] X[k][j];
+  // row i overwrites its own L entries in increasing j, each of which is
+  // read for the last time by the step that overwrites it.
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const double di = 1.0 / M[tri<NB>(i, i)];
+#pragma unroll
+    for (int j = 0; j < i; ++j) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = j; k < i; ++k) s += M[tri<NB>(i, k)] * M[tri<NB>(k, j)];
+      M[tri<NB>(i, j)] = -s * di;
+    }
+    M[tri<NB>(i, i)] = di;
+  }
+  T* Li = (T*)a.Li + (size_t)g * NN;
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) Li[i * NB + j] = (T)(j <= i ? M[tri<NB>(i, j)] : 0.0);
+}
+
+// F_g = Li_g O_g Li_{g+1}^T for rows with a successor; one wavefront per row,
+// operands staged in LDS as float64.
+template <int NB, typename T, typename Rec>
+__global__ void __launch_bounds__(256) k_scaled_offdiag(SetupArgs a) {
+  constexpr int NN = NB * NB;
+  __shared__ double sm[4][4][NN];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int64_t g = (int64_t)blockIdx.x * 4 + w;
+  bool valid = g < a.R;
+  int inst = 0;
+  if (valid) {
+    inst = find_instance(a.off, a.B, g);
+    valid = g + 1 < a.off[inst + 1];
+  }
+  double* Lg = sm[w][0];
+  double* Om = sm[w][1];
+  double* Ln = sm[w][2];
+  double* Tm = sm[w][3];
+  if (valid) {
+    const T* lig = (const T*)a.Li + (size_t)g * NN;
+    const Rec* og = (const Rec*)a.O + (size_t)(g - inst) * NN;
+    for (int e = l; e < NN; e += 64) {
+      Lg[e] = (double)lig[e];
+      Ln[e] = (double)lig[NN + e];
+      Om[e] = (double)og[e];
+    }
+  }
+  __syncthreads();
+  if (valid) {
+    for (int e = l; e < NN; e += 64) {
+      const int i = e / NB, j = e - (e / NB) * NB;
+      double t = 0.0;
+      for (int p = 0; p <= i; ++p) t += Lg[i * NB + p] * Om[p * NB + j];
+      Tm[e] = t;
+    }
+  }
+  __syncthreads();
+  if (valid) {
+    T* F = (T*)a.F + (size_t)g * NN;
+    for (int e = l; e < NN; e += 64) {
+      const int i = e / NB, j = e - (e / NB) * NB;
+      double t = 0.0;
+      for (int q = 0; q <= j; ++q) t += Tm[i * NB + q] * Ln[j * NB + q];
+      F[e] = (T)t;
+    }
+  }
+}
+
+template <int NB, typename T, typename Rec>
+hipError_t launch_lane(const SetupArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_factor_lane<NB, T, Rec>), dim3((a.R + 63) / 64),
+                     dim3(64), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_scaled_offdiag<NB, T, Rec>), dim3((a.R + 3) / 4),
+                     dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+template <int NB>
+hipError_t launch_lane_nb(const SetupArgs& a, hipStream_t s) {
+  const bool f64 = a.prec == BT_F64;
+  const bool r64 = a.dtype == BT_DT_F64;
+  if (f64) return r64 ? launch_lane<NB, double, double>(a, s)
+                      : launch_lane<NB, double, float>(a, s);
+  return r64 ? launch_lane<NB, float, double>(a, s)
+             : launch_lane<NB, float, float>(a, s);
+}
+
 __global__ void k_setup_init(int B, int32_t* fail, int32_t* ctr) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < B) fail[t] = BT_NO_FAIL;
@@ -159,6 +302,8 @@ __global__ void __launch_bounds__(256)
 
 hipError_t bt_launch_setup(const SetupArgs& a, hipStream_t s) {
   if (a.R <= 0) return hipSuccess;
+  if (a.n == 12) return btk::launch_lane_nb<12>(a, s);
+  if (a.n == 6) return btk::launch_lane_nb<6>(a, s);
   const size_t sm = 4 * sizeof(double) * (size_t)a.n * a.n;
   const bool f64 = a.prec == BT_F64;
   const bool big = a.n > 16;
