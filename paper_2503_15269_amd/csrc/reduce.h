@@ -128,6 +128,16 @@ template <typename T> struct AccOf;
 template <> struct AccOf<double> { using type = AccD; };
 template <> struct AccOf<float> { using type = AccF; };
 
+// Sum over the 16 lanes of each DPP row; every lane of a row returns it.
+template <typename A>
+__device__ __forceinline__ A row16_sum(A v) {
+  v.merge(v.template moved<DPP_QUAD_1032>());
+  v.merge(v.template moved<DPP_QUAD_2301>());
+  v.merge(v.template moved<DPP_ROW_HALF_MIRROR>());
+  v.merge(v.template moved<DPP_ROW_MIRROR>());
+  return v;
+}
+
 // Sum over the 64 lanes of a wave; every lane returns the same value.
 template <typename A>
 __device__ __forceinline__ A wave_sum(A v) {

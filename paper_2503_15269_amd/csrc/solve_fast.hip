@@ -41,7 +41,8 @@ using btk::AccD;
 using btk::AccF;
 
 constexpr int NT = 1024;
-constexpr int NW = NT / 64;
+constexpr int NW = NT / 64;  // 16: one DPP row of partials
+static_assert(NW == 16, "cross-wave sums use one 16-lane DPP row");
 constexpr int SL = 4;      // reduction slots (reuse distance)
 constexpr int MAXI = 64;   // systems per bin, upper bound
 constexpr int EPT = 3;     // vector entries per lane
@@ -172,11 +173,16 @@ struct Ctx {
     const AccF t = btk::wave_sum(acc);
     if ((threadIdx.x & 63) == 0) sm.redF[sf][wave] = t;
   }
+  // Sum of the system's wavefront partials: lane l of every wavefront reads
+  // slot l (one LDS load), slots outside the system are zeroed, a DPP row
+  // reduction adds the 16 and lane 0 broadcasts. Fixed tree: deterministic.
   __device__ __forceinline__ double take() {  // after the barrier
-    AccF t = sm.redF[sf][w0];
-    for (int w = w0 + 1; w < w1; ++w) t.merge(sm.redF[sf][w]);
+    const int l = threadIdx.x & (NW - 1);
+    AccF v = sm.redF[sf][l];
+    if (!(l >= w0 && l < w1)) v.zero();
+    v = btk::row16_sum(v);
     sf = (sf + 1) % SL;
-    return uni(t.value());
+    return uni(v.lane(0).value());
   }
   __device__ __forceinline__ double dot(const float (&x)[EPT],
                                         const float (&y)[EPT]) {
@@ -194,10 +200,12 @@ struct Ctx {
     const AccD t = btk::wave_sum(a);
     if ((threadIdx.x & 63) == 0) sm.redD[sd][wave] = t.s;
     __syncthreads();
-    double s = sm.redD[sd][w0];
-    for (int w = w0 + 1; w < w1; ++w) s += sm.redD[sd][w];
+    const int l = threadIdx.x & (NW - 1);
+    AccD v2;
+    v2.s = (l >= w0 && l < w1) ? sm.redD[sd][l] : 0.0;
+    v2 = btk::row16_sum(v2);
     sd = (sd + 1) % SL;
-    return uni(s);
+    return uni(v2.lane(0).s);
   }
   // Any wavefront that raised its flag since the last check bumped the
   // counter; every lane compares with the value it saw last time. The next
@@ -322,7 +330,8 @@ __global__ void __launch_bounds__(NT) k_fast_ir(SolveArgs a) {
     // ---- rows 3q..3q+2 of F_k into registers, lane column order ------------
     {
       const bool has_next = c.row_ok && c.k < c.N - 1;
-      const float* fk = F + (size_t)(has_next ? g : 0) * nn;
+      const float keep = has_next ? 1.f : 0.f;
+      const float* fk = F + (size_t)(has_next ? g : 0) * nn;  // always valid
 #pragma unroll
       for (int e = 0; e < EPT; ++e) {
         const float* row = fk + (size_t)(c.q * EPT + e) * NB;
@@ -330,8 +339,7 @@ __global__ void __launch_bounds__(NT) k_fast_ir(SolveArgs a) {
         for (int cc = 0; cc < G::TPR; ++cc) {
           const int src = EPT * (cc ^ c.q);
 #pragma unroll
-          for (int z = 0; z < EPT; ++z)
-            c.Fr[e][EPT * cc + z] = has_next ? row[src + z] : 0.f;
+          for (int z = 0; z < EPT; ++z) c.Fr[e][EPT * cc + z] = keep * row[src + z];
         }
       }
     }
@@ -377,18 +385,18 @@ __global__ void __launch_bounds__(NT) k_fast_ir(SolveArgs a) {
             double acc = 0.0;
             if (outer > 0) {
               const size_t db = (size_t)g * nn + (size_t)i * NB;
-#pragma unroll 2
+#pragma unroll
               for (int jj = 0; jj < NB; ++jj)
                 acc += (double)((const Rec*)a.D)[db + jj] * xk[jj];
               if (c.k < c.N - 1) {
                 const size_t o = (size_t)ob * nn + (size_t)i * NB;
-#pragma unroll 2
+#pragma unroll
                 for (int jj = 0; jj < NB; ++jj)
                   acc += (double)((const Rec*)a.O)[o + jj] * xk[NB + jj];
               }
               if (c.k > 0) {
                 const size_t o = (size_t)(ob - 1) * nn + i;
-#pragma unroll 2
+#pragma unroll
                 for (int jj = 0; jj < NB; ++jj)
                   acc += (double)((const Rec*)a.O)[o + (size_t)jj * NB] * xk[jj - NB];
               }
@@ -428,7 +436,7 @@ __global__ void __launch_bounds__(NT) k_fast_ir(SolveArgs a) {
           float acc = 0.f;
           if (c.row_ok && !done) {
             const float* lr = Li + (size_t)g * nn + (size_t)i * NB;
-#pragma unroll 4
+#pragma unroll
             for (int jj = 0; jj < NB; ++jj)
               if (jj <= i) acc = __fmaf_rn(lr[jj], rk[4 * (jj / EPT) + jj % EPT], acc);
           }
@@ -506,7 +514,7 @@ __global__ void __launch_bounds__(NT) k_fast_ir(SolveArgs a) {
             if (c.row_ok) {
               const float* lc = Li + (size_t)g * nn + i;
               float acc = 0.f;
-#pragma unroll 4
+#pragma unroll
               for (int jj = 0; jj < NB; ++jj)
                 if (jj >= i)
                   acc = __fmaf_rn(lc[(size_t)jj * NB], dk[4 * (jj / EPT) + jj % EPT], acc);
