@@ -444,27 +444,57 @@ __global__ void __launch_bounds__(NT) k_fast_ir(SolveArgs a) {
           d[e] = 0.f;
         }
       }
-      const double n0 = c.dot(r, r);
-      const double itarget = itol2 * n0;
+      // z = M^{-1} r for the inner right-hand side
       {
         float cr[EPT];
         c.template C<1>(r, cr);
         c.template precond_rest<M>(a, r, cr, z);
       }
-      double rho = c.dot(r, z);
-      bool act = !done && rho > 0.0;
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) p[e] = z[e];
+      // Inner PCG, arranged so that each iteration has two reductions and
+      // five barriers: rho = r'z shares its barrier with the staging of z,
+      // q = Ahat p follows from Ahat z by q = Ahat z + beta q, and the inner
+      // solve stops when r'z (the squared residual in the M^{-1} norm) fell
+      // by inner_tol^2.
+      bool act = !done;
+      bool first = true;
+      double rho = 0.0, rho0 = 0.0;
       int inner = 0;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {  // beta = 0 at the first step: p = z
+        p[e] = 0.f;
+        qv[e] = 0.f;
+      }
       for (;;) {
-        // q = Ahat p = p - C p, fused with the "anyone still running" flag
-        c.template prep<0>(p);
+        AccF acc;
+        acc.zero();
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) acc.add_prod(r[e], z[e]);
+        c.template prep<0>(z);
+        c.put_wave(acc);
         c.put_flag(act);
         __syncthreads();
+        const double rho1 = c.take();
         if (!c.any_after_barrier()) break;
-        c.template finish<0>(qv);
+        if (act) {
+          if (!(rho1 > 0.0)) act = false;
+          else if (first) rho0 = rho1;
+          else if (rho1 <= itol2 * rho0) act = false;
+          if (total >= a.maxit) act = false;
+        }
+        float u[EPT];
+        c.template finish<0>(u);
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) qv[e] = p[e] - qv[e];
+        for (int e = 0; e < EPT; ++e) u[e] = z[e] - u[e];
+        if (act) {
+          const float be = first ? 0.f : (float)(rho1 / rho);
+#pragma unroll
+          for (int e = 0; e < EPT; ++e) {
+            p[e] = __fmaf_rn(be, p[e], z[e]);
+            qv[e] = __fmaf_rn(be, qv[e], u[e]);
+          }
+          rho = rho1;
+        }
+        first = false;
         const double sigma = c.dot(p, qv);
         if (act && !(sigma > 0.0)) act = false;
         if (act) {
@@ -477,32 +507,9 @@ __global__ void __launch_bounds__(NT) k_fast_ir(SolveArgs a) {
           ++inner;
           ++total;
         }
-        // ||r||^2 fused with the first operator application of M^{-1} r
         float cr[EPT];
-        {
-          AccF acc;
-          acc.zero();
-#pragma unroll
-          for (int e = 0; e < EPT; ++e) acc.add_prod(r[e], r[e]);
-          c.template prep<1>(r);
-          c.put_wave(acc);
-          __syncthreads();
-          c.template finish<1>(cr);
-        }
-        const double rr = c.take();
-        if (act && (rr <= itarget || total >= a.maxit)) act = false;
+        c.template C<1>(r, cr);
         c.template precond_rest<M>(a, r, cr, z);
-        const double rho1 = c.dot(r, z);
-        if (act) {
-          if (!(rho1 > 0.0)) {
-            act = false;
-          } else {
-            const float be = (float)(rho1 / rho);
-#pragma unroll
-            for (int e = 0; e < EPT; ++e) p[e] = __fmaf_rn(be, p[e], z[e]);
-            rho = rho1;
-          }
-        }
       }
       // x64 += L^{-T} d
       {
