@@ -42,7 +42,56 @@ def parse():
                     help="budget of the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times "
+                         "(calibrates the HBM byte counters of the profiler)")
     return ap.parse_args()
+
+
+KERNEL_SOURCES = ("paper_2503_15269_amd/csrc/solve_fast.hip",
+                  "paper_2503_15269_amd/csrc/reduce.h",
+                  "paper_2503_15269_amd/csrc/internal.h")
+TRAFFIC_FILE = "profiles/traffic_k_fast_ir_batch_ragged_n12.md"
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None when the kernel's sources changed since it was taken."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line and line.strip().startswith("- "):
+                k, v = line.strip()[2:].split(":", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_probe(mib):
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes_each_way": n * 4, "launches": 3}))
 
 
 def apps_per_iteration(a, m):
@@ -112,6 +161,9 @@ def cpu_baseline(data, budget_s, cores):
 
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; "
                           "the batched workload shards by instance across "
@@ -254,10 +306,11 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved_tf,
                      "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tf / PEAK_FP32_VALU_TFLOPS,
-                     "traffic": None},
+                     "traffic": measured_traffic()},
         "cpu_baseline": cpu,
         "extra": {
             "solve_kernel_ms": solve_ms,
+            "solve_kernel_source": kernel_source_hash(),
             "setup_plus_queue_ms": ms_per_step - solve_ms,
             "solve_alg_GBps": nbytes / (solve_ms * 1e-3) / 1e9,
             "hbm_frac_of_alg_bytes": nbytes / (solve_ms * 1e-3) / 1e9 /
