@@ -42,6 +42,11 @@ def parse():
                     help="budget of the oracle CPU-baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (inner_tol 1e-4, default kernel)")
+    ap.add_argument("--inner-tol", type=float, default=None,
+                    help="inner tolerance of the refinement (default: the "
+                         "autotuned value)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times "
                          "(calibrates the HBM byte counters of the profiler)")
@@ -63,9 +68,10 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(inner_tol):
     """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, or None when the kernel's sources changed since it was taken."""
+    summary, or None when the kernel's sources (or the inner tolerance, which
+    sets the number of refinement passes) differ from the measured run."""
     path = os.path.join(ROOT, TRAFFIC_FILE)
     if not os.path.exists(path):
         return None
@@ -76,6 +82,11 @@ def measured_traffic():
                 k, v = line.strip()[2:].split(":", 1)
                 vals[k.strip()] = v.strip().strip("`")
     if vals.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    try:
+        if float(vals.get("inner_tol", "nan")) != float(inner_tol):
+            return None
+    except ValueError:
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])
@@ -184,10 +195,19 @@ def main():
     D = torch.tensor(data["D"], dtype=torch.float32, device=dev)
     O = torch.tensor(data["O"], dtype=torch.float32, device=dev)
     b = torch.tensor(data["b"].reshape(-1), dtype=torch.float64, device=dev)
-    params = bt.Params.polycoeff(2, prec="f32_ir", inner_tol=1e-4,
+    params = bt.Params.polycoeff(2, prec="f32_ir",
+                                 inner_tol=args.inner_tol or 1e-4,
                                  max_outer=30)
     tol = 1e-10
+    tuned = None
+    if not args.no_tune and args.inner_tol is None:
+        from paper_2503_15269_amd import autotune
+        tuned = autotune.tune(D, O, data["offsets"], b, params, tol, reps=3,
+                              use_cache=False)
+        params = tuned["params"]
     h = bt.Handle(D, O, data["offsets"], params)
+    if tuned is not None:
+        h.set_kernel_config(tuned["kernel_config"])
     x = torch.empty_like(b)
     info = torch.empty(B * bt.INFO_DTYPE.itemsize, dtype=torch.uint8,
                        device=dev)
@@ -302,11 +322,13 @@ def main():
                    "horizons": "uniform 16..256", "nx": n, "nu": w["nu"],
                    "record": "f32", "iteration": "f32 PCG + f64 refinement",
                    "tol": tol, "preconditioner": "(a,b)=(1,-1), m=2, alpha1=7",
-                   "graph": use_graph},
+                   "graph": use_graph, "inner_tol": params.inner_tol,
+                   "kernel_config": h.kernel_config(),
+                   "autotuned": tuned is not None},
         "roofline": {"bound": "alu", "achieved": achieved_tf,
                      "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tf / PEAK_FP32_VALU_TFLOPS,
-                     "traffic": measured_traffic()},
+                     "traffic": measured_traffic(params.inner_tol)},
         "cpu_baseline": cpu,
         "extra": {
             "solve_kernel_ms": solve_ms,

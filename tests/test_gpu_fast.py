@@ -126,3 +126,27 @@ def test_fast_deterministic():
     x2, i2, _ = run(data, P)
     assert np.array_equal(x1, x2)
     assert np.array_equal(i1["iters"], i2["iters"])
+
+
+def test_autotune_picks_a_converging_config(tmp_path, monkeypatch):
+    import torch
+    from paper_2503_15269_amd import autotune
+    monkeypatch.setenv("BTPCG_TUNE_CACHE", str(tmp_path / "tune.json"))
+    data = lqrgen.lqr_batch(32, (16, 200), 12, 4, seed=44, record="f32")
+    D = to_dev(data["D"], torch.float32)
+    O = to_dev(data["O"], torch.float32)
+    b = to_dev(data["b"].reshape(-1), torch.float64)
+    P = bt.Params.polycoeff(2, prec="f32_ir")
+    res = autotune.tune(D, O, data["offsets"], b, P, 1e-10, reps=1,
+                        inner_tols=(1e-4, 3e-6))
+    assert res["ms"] > 0 and not res["cached"]
+    assert res["params"].inner_tol in (1e-4, 3e-6)
+    again = autotune.tune(D, O, data["offsets"], b, P, 1e-10, reps=1,
+                          inner_tols=(1e-4, 3e-6))
+    assert again["cached"] and again["kernel_config"] == res["kernel_config"]
+    h = bt.Handle(D, O, data["offsets"], res["params"])
+    h.set_kernel_config(res["kernel_config"])
+    x, info = h.solve(b, 1e-10)
+    torch.cuda.synchronize()
+    inf = bt.infos_to_numpy(info)
+    assert np.all(inf["status"] == bt.OK) and np.all(inf["relres_true"] <= 1e-10)
