@@ -65,6 +65,11 @@ extern "C" {
                         compensated dot products; no refinement */
 #define BT_F32_IR 2  /* float32 inner PCG inside a float64 iterative
                         refinement on the system of record */
+#define BT_BF16X2_IR 3 /* as BT_F32_IR; in addition the off-diagonal blocks are
+                        kept split as bfloat16 pairs (hi + lo) for the
+                        many-right-hand-side solve, whose block products run
+                        on the matrix cores (hi*hi + hi*lo + lo*hi, float32
+                        accumulation) */
 
 /* Storage type of D and O. */
 #define BT_DT_F64 0
@@ -166,6 +171,22 @@ int bt_solve_batched(const bt_handle* h, const double* b, double* x,
 int bt_solve_adjoint(const bt_handle* h, const double* x, const double* g,
                      double* lambda, double* dD, double* dO, double tol,
                      int maxit, bt_info* info, void* stream);
+
+/* Many right-hand sides (the block products with many right-hand sides of
+ * the task's precision pattern): solve A X = B for ``nrhs`` columns at once,
+ * each column an independent PCG with the handle's preconditioner, the
+ * operator applied to the whole [n][nrhs] panel of a block row with matrix-
+ * core products. Requires a handle set up with prec BT_BF16X2_IR, B = 1,
+ * n in {16, 32, 48, 64}, a = 1, m in {1, 2}; nrhs a multiple of 64, at most
+ * 256. b, x: device [R][n][nrhs] float64 (right-hand-side index fastest).
+ * info: device, nrhs entries. scratch: device, >= bt_mrhs_workspace_bytes.
+ * Unlike the other calls this one waits on the stream between refinement
+ * steps (convergence checks), so it cannot be captured into a graph.
+ * Errors: BT_EINVAL, BT_ENOSPACE, BT_EHIP. */
+size_t bt_mrhs_workspace_bytes(const bt_handle* h, int nrhs);
+int bt_solve_mrhs(const bt_handle* h, int nrhs, const double* b, double* x,
+                  double tol, int maxit, bt_info* info, void* scratch,
+                  size_t scratch_bytes, void* stream);
 
 /* Kernel configurations for the solve (workgroup size x vector elements per
  * thread), for the autotuner. bt_kernel_config_count() entries; entry i has

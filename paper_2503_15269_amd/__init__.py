@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libbtpcg.so")
 
 OK, NOT_CONVERGED, EINVAL, ENOTSPD, EBREAKDOWN, ENONFINITE, EHIP, ENOSPACE = \
     0, 1, -1, -2, -3, -4, -5, -6
-F64, F32, F32_IR = 0, 1, 2
+F64, F32, F32_IR, BF16X2_IR = 0, 1, 2, 3
 DT_F64, DT_F32 = 0, 1
 PC_POLY, PC_NONE = 0, 1
 MAX_M = 8
@@ -71,6 +71,8 @@ def load_library(path: str = LIB_PATH):
         "bt_solve": (I, [P, P, P, Dd, I, P, P]),
         "bt_solve_batched": (I, [P, P, P, Dd, I, P, P]),
         "bt_solve_adjoint": (I, [P, P, P, P, P, P, Dd, I, P, P]),
+        "bt_mrhs_workspace_bytes": (Sz, [P, I]),
+        "bt_solve_mrhs": (I, [P, I, P, P, Dd, I, P, P, Sz, P]),
         "bt_kernel_config_count": (I, []),
         "bt_kernel_config": (I, [I, ctypes.POINTER(I), ctypes.POINTER(I),
                                  ctypes.POINTER(I)]),
@@ -91,6 +93,7 @@ def exported_symbols():
     return ["bt_default_params", "bt_strerror", "bt_workspace_bytes",
             "bt_batch_setup", "bt_setup", "bt_refactor", "bt_precondition",
             "bt_solve", "bt_solve_batched", "bt_solve_adjoint",
+            "bt_mrhs_workspace_bytes", "bt_solve_mrhs",
             "bt_kernel_config_count", "bt_kernel_config",
             "bt_set_kernel_config", "bt_get_kernel_config", "bt_destroy"]
 
@@ -146,7 +149,8 @@ class Params:
         for i in range(MAX_M):
             p.alpha[i] = al[i]
         p.pc = {"poly": PC_POLY, "none": PC_NONE}[self.pc]
-        p.prec = {"f64": F64, "f32": F32, "f32_ir": F32_IR}[self.prec]
+        p.prec = {"f64": F64, "f32": F32, "f32_ir": F32_IR,
+                  "bf16x2_ir": BF16X2_IR}[self.prec]
         p.max_outer = int(self.max_outer)
         p.inner_tol = float(self.inner_tol)
         return p
@@ -292,6 +296,32 @@ class Handle:
                                              _stream(torch, stream))
         _check(rc, "bt_solve_batched")
         return x, info
+
+    def solve_mrhs(self, B, tol: float = 1e-10, maxit: Optional[int] = None,
+                   X=None, stream=None):
+        """X = A^{-1} B for a panel of right-hand sides B [R, n, nrhs]
+        (float64, cuda). Needs prec "bf16x2_ir". Returns (X, info[nrhs])."""
+        torch = _torch()
+        if B.dim() != 3 or B.shape[0] != self.R or B.shape[1] != self.n:
+            raise ValueError("B must be [R, n, nrhs]")
+        if B.dtype != torch.float64 or not B.is_contiguous() or not B.is_cuda:
+            raise ValueError("B must be a contiguous float64 cuda tensor")
+        nrhs = int(B.shape[2])
+        lib = load_library()
+        nbytes = lib.bt_mrhs_workspace_bytes(self._h, nrhs)
+        if nbytes == 0:
+            raise BtError(EINVAL, "bt_mrhs_workspace_bytes")
+        scratch = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if X is None:
+            X = torch.empty_like(B)
+        info = torch.empty(nrhs * INFO_DTYPE.itemsize, dtype=torch.uint8,
+                           device=self.device)
+        maxit = self.default_maxit() if maxit is None else int(maxit)
+        rc = lib.bt_solve_mrhs(self._h, nrhs, _ptr(B), _ptr(X), float(tol),
+                               maxit, _ptr(info), _ptr(scratch), nbytes,
+                               _stream(torch, stream))
+        _check(rc, "bt_solve_mrhs")
+        return X, info
 
     def precondition(self, r, z=None, stream=None):
         torch = _torch()

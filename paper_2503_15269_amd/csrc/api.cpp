@@ -25,11 +25,12 @@ bool params_ok(const bt_params* p) {
   if (p->a < 0.0 || p->b < -1.0 - 1e-12) return false;
   if (p->m < 1 || p->m > BT_MAX_M) return false;
   if (p->pc != BT_PC_POLY && p->pc != BT_PC_NONE) return false;
-  if (p->prec != BT_F64 && p->prec != BT_F32 && p->prec != BT_F32_IR)
+  if (p->prec != BT_F64 && p->prec != BT_F32 && p->prec != BT_F32_IR &&
+      p->prec != BT_BF16X2_IR)
     return false;
   for (int i = 1; i < p->m; ++i)
     if (!std::isfinite(p->alpha[i])) return false;
-  if (p->prec == BT_F32_IR) {
+  if (p->prec == BT_F32_IR || p->prec == BT_BF16X2_IR) {
     if (p->max_outer < 1) return false;
     if (!(p->inner_tol > 0.0 && p->inner_tol < 1.0)) return false;
   }
@@ -58,10 +59,10 @@ int64_t check_offsets(int B, const int64_t* off, int* maxN) {
 }
 
 struct Layout {
-  size_t off, order, ctr, fail, bins, items, F, L, Li, total;
+  size_t off, order, ctr, fail, bins, items, F, L, Li, Fhi, Flo, total;
 };
 
-Layout layout(int B, int64_t R, int n, size_t es) {
+Layout layout(int B, int64_t R, int n, size_t es, bool split) {
   Layout l{};
   size_t at = 0;
   l.off = at; at += align_up(sizeof(int64_t) * (B + 1));
@@ -74,6 +75,9 @@ Layout layout(int B, int64_t R, int n, size_t es) {
   l.F = at; at += blk;
   l.L = at; at += blk;
   l.Li = at; at += blk;
+  const size_t hblk = split ? align_up(2 * (size_t)R * n * n) : 0;
+  l.Fhi = at; at += hblk;
+  l.Flo = at; at += hblk;
   l.total = at;
   return l;
 }
@@ -165,7 +169,12 @@ int launch_setup(bt_handle* h, hipStream_t s) {
   a.F = h->F;
   a.L = h->L;
   a.Li = h->Li;
-  return hip_status(bt_launch_setup(a, s));
+  if (a.prec == BT_BF16X2_IR) a.prec = BT_F32_IR;  // float32 factors first
+  if (bt_launch_setup(a, s) != hipSuccess) return BT_EHIP;
+  if (h->Fhi)
+    return hip_status(bt_mrhs_split((const float*)h->F, h->Fhi, h->Flo,
+                                    (size_t)h->R * h->n * h->n, s));
+  return BT_OK;
 }
 
 SolveArgs base_args(const bt_handle* h) {
@@ -173,7 +182,7 @@ SolveArgs base_args(const bt_handle* h) {
   a.B = h->B;
   a.n = h->n;
   a.dtype = h->dtype;
-  a.ir = h->p.prec == BT_F32_IR;
+  a.ir = h->p.prec == BT_F32_IR || h->p.prec == BT_BF16X2_IR;
   a.pc = h->p.pc;
   a.m = h->p.m;
   a.a = h->p.a;
@@ -246,7 +255,7 @@ size_t bt_workspace_bytes(int B, const int64_t* offsets_host, int n,
   if (!params_ok(p) || n < 1 || n > 64) return 0;
   const int64_t R = check_offsets(B, offsets_host, &maxN);
   if (R < 0) return 0;
-  return layout(B, R, n, elem_bytes(p)).total;
+  return layout(B, R, n, elem_bytes(p), p->prec == BT_BF16X2_IR).total;
 }
 
 int bt_batch_setup(bt_handle** h, int B, const int64_t* offsets_host, int n,
@@ -261,7 +270,7 @@ int bt_batch_setup(bt_handle** h, int B, const int64_t* offsets_host, int n,
   if (R < 0) return BT_EINVAL;
   if (R > B && !O) return BT_EINVAL;
   if (auto_config(kernel_prec(p), (int64_t)maxN * n) < 0) return BT_EINVAL;
-  const Layout l = layout(B, R, n, elem_bytes(p));
+  const Layout l = layout(B, R, n, elem_bytes(p), p->prec == BT_BF16X2_IR);
   if (ws_bytes < l.total) return BT_ENOSPACE;
 
   bt_handle* hh = new (std::nothrow) bt_handle();
@@ -284,6 +293,10 @@ int bt_batch_setup(bt_handle** h, int B, const int64_t* offsets_host, int n,
   hh->F = w + l.F;
   hh->L = w + l.L;
   hh->Li = w + l.Li;
+  if (p->prec == BT_BF16X2_IR) {
+    hh->Fhi = (unsigned short*)(w + l.Fhi);
+    hh->Flo = (unsigned short*)(w + l.Flo);
+  }
   hh->off_host.assign(offsets_host, offsets_host + B + 1);
 
   // longest systems first (longest-processing-time order for the queue)
@@ -382,6 +395,29 @@ int bt_solve_adjoint(const bt_handle* h, const double* x, const double* g,
   return hip_status(bt_launch_adjoint_outer(h->B, h->n, h->R, h->off, x,
                                             lambda, dD, dO,
                                             (hipStream_t)stream));
+}
+
+size_t bt_mrhs_workspace_bytes(const bt_handle* h, int nrhs) {
+  if (!h || nrhs < 1) return 0;
+  return bt_mrhs_scratch_bytes(h->R, h->n, nrhs);
+}
+
+int bt_solve_mrhs(const bt_handle* h, int nrhs, const double* b, double* x,
+                  double tol, int maxit, bt_info* info, void* scratch,
+                  size_t scratch_bytes, void* stream) {
+  if (!h || !b || !x || !info || !scratch || !(tol >= 0.0) || maxit < 0)
+    return BT_EINVAL;
+  if (h->p.prec != BT_BF16X2_IR || h->B != 1 || h->p.pc != BT_PC_POLY ||
+      h->p.a != 1.0 || h->p.m > 2)
+    return BT_EINVAL;
+  if (!(h->n == 16 || h->n == 32 || h->n == 48 || h->n == 64)) return BT_EINVAL;
+  if (nrhs < 64 || nrhs > 256 || nrhs % 64 != 0) return BT_EINVAL;
+  if (scratch_bytes < bt_mrhs_scratch_bytes(h->R, h->n, nrhs))
+    return BT_ENOSPACE;
+  return bt_mrhs_run(h->R, h->n, nrhs, h->Fhi, h->Flo, (const float*)h->Li,
+                     h->D, h->O, h->dtype, b, x, tol, maxit, h->p.max_outer,
+                     h->p.inner_tol, h->p.m, h->p.m > 1 ? h->p.alpha[1] : 0.0,
+                     scratch, info, (hipStream_t)stream);
 }
 
 int bt_kernel_config_count(void) { return bt_num_kernel_configs() + 1; }

@@ -27,6 +27,8 @@ struct bt_handle {
   void* F = nullptr;        // [R][n][n] scaled off-diagonal blocks
   void* L = nullptr;        // [R][n][n] Cholesky factors of D_k
   void* Li = nullptr;       // [R][n][n] their inverses
+  unsigned short* Fhi = nullptr;  // BT_BF16X2_IR: F split into bfloat16 pairs
+  unsigned short* Flo = nullptr;
   int cfg = -1;             // solve-kernel configuration, -1 = automatic
   std::vector<int64_t> off_host;
 };
@@ -91,6 +93,14 @@ hipError_t bt_launch_fast(const SolveArgs& a, int grid, hipStream_t s);
 int bt_fast_max_grid(int n);
 hipError_t bt_launch_setup_init(int B, int32_t* fail, int32_t* ctr,
                                 hipStream_t s);
+size_t bt_mrhs_scratch_bytes(int64_t R, int n, int nrhs);
+hipError_t bt_mrhs_split(const float* F, unsigned short* hi, unsigned short* lo,
+                         size_t N, hipStream_t s);
+int bt_mrhs_run(int64_t R, int n, int nrhs, const unsigned short* Fhi,
+                const unsigned short* Flo, const float* Li, const void* D,
+                const void* O, int dtype, const double* b, double* x,
+                double tol, int maxit, int max_outer, double inner_tol, int m,
+                double alpha1, void* scratch, bt_info* info, hipStream_t s);
 hipError_t bt_launch_adjoint_outer(int B, int n, int64_t R,
                                    const int64_t* off, const double* x,
                                    const double* lam, double* dD, double* dO,

@@ -1,0 +1,597 @@
+// Many right-hand sides at once: X = A^{-1} B for an [R][n][nrhs] panel of
+// right-hand sides (one system, n a multiple of 16).
+//
+// Each right-hand side runs its own PCG (own alpha, beta, convergence), but
+// the operator is applied to the whole panel, so each application of the
+// scaled off-diagonal operator C (see solve.hip for the scaled form of the
+// paper's preconditioner) is a pair of dense n x n by n x nrhs products per
+// block row:  (C V)_k = -(F_{k-1}^T V_{k-1} + F_k V_{k+1}).
+// These run on the matrix cores: v_mfma_f32_16x16x16_bf16 with the blocks
+// stored split as F = Fhi + Flo (two bfloat16 arrays) and the panel split the
+// same way on the fly; the product is hi*hi + hi*lo + lo*hi with float32
+// accumulation (relative error ~1e-5), and the float64 refinement on the
+// record removes what the inner float32 solve leaves.
+//
+// One inner iteration (m = 2 shown; the polynomial follows eq. Mminv-poly-
+// nomial-coefficients at a = 1: y_0 = r + C r, y_i = C(C y_{i-1}))
+//   p = z + beta p                          k_mr_axpy_p
+//   q = p - C p,  sigma = p'q partials      k_mr_app<EPI_Q>
+//   alpha = rho / sigma                     k_mr_colsum<SIGMA>
+//   d += alpha p, r -= alpha q              k_mr_axpy_dr
+//   y0 = r + C r                            k_mr_app<EPI_Y0>
+//   w = C y0                                k_mr_app<EPI_W>
+//   z = y0 + alpha_1 C w, rho = r'z parts   k_mr_app<EPI_Z>
+//   beta, stopping test                     k_mr_colsum<RHO>
+// Converged right-hand sides keep being carried through the products but no
+// longer update. The host checks every few iterations whether any is left.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "internal.h"
+
+namespace btm {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int WG = 256;       // 4 wavefronts, 16 right-hand sides each
+constexpr int CPW = 16;       // columns per wavefront
+constexpr int CPB = 64;       // columns per workgroup
+
+__device__ __forceinline__ unsigned short f2bf(float x) {
+  unsigned u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (unsigned short)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short h) {
+  return __uint_as_float((unsigned)h << 16);
+}
+
+enum { EPI_Q = 0, EPI_Y0 = 1, EPI_W = 2, EPI_Z = 3 };
+
+struct MrArgs {
+  int R, n, nrhs;
+  const unsigned short* Fhi;  // [R][n][n]
+  const unsigned short* Flo;
+  const float* Li;            // [R][n][n]
+  const void* D;              // record
+  const void* O;
+  int dtype;
+  const double* b;            // [R][n][nrhs]
+  double* x;
+  float *p, *q, *r, *d, *y0, *w, *z;  // panels [R][n][nrhs]
+  double* part;               // [R][nrhs] per-row partial sums
+  // per right-hand-side state
+  double *rho, *rho0, *alpha, *beta, *nb2, *nr2;
+  int *act, *done, *first, *inner, *total, *outer, *status;
+  double alpha1;              // polynomial coefficient of the second term
+  int m;
+  double tol, itol2;
+  int maxit;
+};
+
+// ---------------------------------------------------------------------------
+// Y = C V on the matrix cores, with an epilogue. Grid (R, nrhs / 64).
+// ---------------------------------------------------------------------------
+template <int NB, int EPI>
+__global__ void __launch_bounds__(WG) k_mr_app(MrArgs a, const float* V,
+                                              const float* aux, float* out) {
+  constexpr int MT = NB / 16;
+  __shared__ unsigned short sFk[2][NB * NB];   // hi, lo of F_k
+  __shared__ unsigned short sFm[2][NB * NB];   // hi, lo of F_{k-1}
+  const int k = blockIdx.x;
+  const int t = threadIdx.x;
+  const int wv = t >> 6, l = t & 63;
+  const int c0 = blockIdx.y * CPB + wv * CPW;
+  const int col = c0 + (l & 15);
+  const int kq = 4 * (l >> 4);                 // k-offset of this lane
+  const bool has_prev = k > 0, has_next = k < a.R - 1;
+  const size_t nn = (size_t)NB * NB;
+  for (int e = t; e < NB * NB; e += WG) {
+    if (has_next) {
+      sFk[0][e] = a.Fhi[(size_t)k * nn + e];
+      sFk[1][e] = a.Flo[(size_t)k * nn + e];
+    }
+    if (has_prev) {
+      sFm[0][e] = a.Fhi[(size_t)(k - 1) * nn + e];
+      sFm[1][e] = a.Flo[(size_t)(k - 1) * nn + e];
+    }
+  }
+  __syncthreads();
+  const int ld = a.nrhs;
+  f32x4 acc[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ks = 0; ks < MT; ++ks) {
+    const int kr = 16 * ks + kq;  // first of the 4 K rows of this lane
+    if (has_next) {
+      bf16x4 bh, bl;
+      const float* vp = V + ((size_t)(k + 1) * NB + kr) * ld + col;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float v = vp[(size_t)i * ld];
+        const unsigned short h = f2bf(v);
+        bh[i] = (short)h;
+        bl[i] = (short)f2bf(v - bf2f(h));
+      }
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const int row = 16 * mt + (l & 15);
+        bf16x4 ah, al;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          ah[i] = (short)sFk[0][row * NB + kr + i];
+          al[i] = (short)sFk[1][row * NB + kr + i];
+        }
+        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[mt], 0, 0, 0);
+        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[mt], 0, 0, 0);
+        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[mt], 0, 0, 0);
+      }
+    }
+    if (has_prev) {
+      bf16x4 bh, bl;
+      const float* vm = V + ((size_t)(k - 1) * NB + kr) * ld + col;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float v = vm[(size_t)i * ld];
+        const unsigned short h = f2bf(v);
+        bh[i] = (short)h;
+        bl[i] = (short)f2bf(v - bf2f(h));
+      }
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        const int mcol = 16 * mt + (l & 15);   // row of F^T = column of F
+        bf16x4 ah, al;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          ah[i] = (short)sFm[0][(kr + i) * NB + mcol];
+          al[i] = (short)sFm[1][(kr + i) * NB + mcol];
+        }
+        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[mt], 0, 0, 0);
+        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[mt], 0, 0, 0);
+        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[mt], 0, 0, 0);
+      }
+    }
+  }
+  // epilogue: lane holds rows 16 mt + kq + i of column ``col``; C V = -acc
+  double dp = 0.0;
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = 16 * mt + kq + i;
+      const size_t idx = ((size_t)k * NB + row) * ld + col;
+      const float cv = -acc[mt][i];
+      float o;
+      if constexpr (EPI == EPI_Q) {
+        const float pv = V[idx];
+        o = pv - cv;                     // q = p - C p
+        dp += (double)pv * (double)o;    // sigma = p'q
+      } else if constexpr (EPI == EPI_Y0) {
+        o = aux[idx] + cv;               // y0 = r + C r
+      } else if constexpr (EPI == EPI_W) {
+        o = cv;                          // w = C y0
+      } else {
+        o = aux[idx] + (float)a.alpha1 * cv;  // z = y0 + alpha_1 C w
+        dp += (double)a.r[idx] * (double)o;   // rho = r'z
+      }
+      out[idx] = o;
+    }
+  }
+  if constexpr (EPI == EPI_Q || EPI == EPI_Z) {
+    dp += __shfl_xor(dp, 16);
+    dp += __shfl_xor(dp, 32);
+    if (l < 16) a.part[(size_t)k * ld + col] = dp;
+  }
+}
+
+// p = z + beta p for the right-hand sides still iterating.
+__global__ void k_mr_axpy_p(MrArgs a) {
+  const size_t N = (size_t)a.R * a.n * a.nrhs;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)(i % a.nrhs);
+    if (a.act[c]) a.p[i] = __fmaf_rn((float)a.beta[c], a.p[i], a.z[i]);
+  }
+}
+
+// d += alpha p, r -= alpha q.
+__global__ void k_mr_axpy_dr(MrArgs a) {
+  const size_t N = (size_t)a.R * a.n * a.nrhs;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)(i % a.nrhs);
+    if (a.act[c]) {
+      const float al = (float)a.alpha[c];
+      a.d[i] = __fmaf_rn(al, a.p[i], a.d[i]);
+      a.r[i] = __fmaf_rn(-al, a.q[i], a.r[i]);
+    }
+  }
+}
+
+// Per right-hand side: sum of the per-row partials in a fixed order, then
+// the scalar step. One workgroup per right-hand side.
+enum { SUM_SIGMA = 0, SUM_RHO = 1, SUM_RES = 2 };
+
+template <int KIND>
+__global__ void __launch_bounds__(256) k_mr_colsum(MrArgs a) {
+  __shared__ double s[256];
+  const int c = blockIdx.x;
+  double v = 0.0;
+  for (int k = threadIdx.x; k < a.R; k += 256) v += a.part[(size_t)k * a.nrhs + c];
+  s[threadIdx.x] = v;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double tot = s[0];
+  if constexpr (KIND == SUM_SIGMA) {
+    if (a.act[c]) {
+      if (!(tot > 0.0)) {
+        a.act[c] = 0;
+        a.alpha[c] = 0.0;
+      } else {
+        a.alpha[c] = a.rho[c] / tot;
+        a.inner[c] += 1;
+        a.total[c] += 1;
+      }
+    }
+  } else if constexpr (KIND == SUM_RHO) {
+    if (a.act[c]) {
+      if (!(tot > 0.0)) {
+        a.act[c] = 0;
+      } else if (a.first[c]) {
+        a.rho0[c] = tot;
+      } else if (tot <= a.itol2 * a.rho0[c]) {
+        a.act[c] = 0;
+      }
+      if (a.total[c] >= a.maxit) a.act[c] = 0;
+      a.beta[c] = a.first[c] ? 0.0 : tot / a.rho[c];
+      a.rho[c] = tot;
+      a.first[c] = 0;
+    }
+  } else {  // SUM_RES: float64 residual of the record
+    a.nr2[c] = tot;
+    if (!a.done[c]) {
+      const double t2 = a.tol * a.tol * a.nb2[c];
+      if (tot <= t2) {
+        a.status[c] = BT_OK;
+        a.done[c] = 1;
+      } else if (!(tot < INFINITY)) {
+        a.status[c] = BT_ENONFINITE;
+        a.done[c] = 1;
+      } else if (a.total[c] >= a.maxit) {
+        a.done[c] = 1;
+      }
+    }
+    a.act[c] = a.done[c] ? 0 : 1;
+    a.first[c] = 1;
+    a.inner[c] = 0;
+  }
+}
+
+// ||b||^2 per right-hand side into part (then summed by SUM_RES-like code).
+__global__ void k_mr_bnorm(MrArgs a) {
+  const int k = blockIdx.x;
+  for (int c = threadIdx.x; c < a.nrhs; c += blockDim.x) {
+    double s = 0.0;
+    for (int i = 0; i < a.n; ++i) {
+      const double v = a.b[((size_t)k * a.n + i) * a.nrhs + c];
+      s += v * v;
+    }
+    a.part[(size_t)k * a.nrhs + c] = s;
+  }
+}
+
+__global__ void k_mr_init_cols(MrArgs a) {
+  __shared__ double s[256];
+  const int c = blockIdx.x;
+  double v = 0.0;
+  for (int k = threadIdx.x; k < a.R; k += 256) v += a.part[(size_t)k * a.nrhs + c];
+  s[threadIdx.x] = v;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double nb = s[0];
+    a.nb2[c] = nb;
+    a.nr2[c] = nb;
+    a.total[c] = 0;
+    a.outer[c] = 0;
+    a.status[c] = BT_NOT_CONVERGED;
+    a.done[c] = 0;
+    if (!(nb < INFINITY)) {
+      a.status[c] = BT_ENONFINITE;
+      a.done[c] = 1;
+    } else if (nb == 0.0) {
+      a.status[c] = BT_OK;
+      a.done[c] = 1;
+    }
+  }
+}
+
+__device__ __forceinline__ double rec(const void* P, size_t i, int dtype) {
+  return dtype == BT_DT_F64 ? ((const double*)P)[i]
+                            : (double)((const float*)P)[i];
+}
+
+// r64 = b - A x in float64 (x = 0 on the first pass: r64 = b); its squared
+// column norms go to part; r = L^{-1} r64 (float) is formed by k_mr_tohat.
+// One workgroup per block row, threads over (i, c).
+__global__ void __launch_bounds__(256) k_mr_resid(MrArgs a, double* r64,
+                                                  int first) {
+  const int k = blockIdx.x, n = a.n, L = a.nrhs;
+  const size_t pn = (size_t)n * L, nn = (size_t)n * n;
+  const bool hp = k > 0, hn = k < a.R - 1;
+  const double* xk = a.x + (size_t)k * pn;
+  for (size_t e = threadIdx.x; e < pn; e += 256) {
+    const int i = (int)(e / L), c = (int)(e % L);
+    double acc = 0.0;
+    if (!first && !a.done[c]) {
+      for (int j = 0; j < n; ++j)
+        acc += rec(a.D, (size_t)k * nn + (size_t)i * n + j, a.dtype) *
+               xk[(size_t)j * L + c];
+      if (hn)
+        for (int j = 0; j < n; ++j)
+          acc += rec(a.O, (size_t)k * nn + (size_t)i * n + j, a.dtype) *
+                 xk[pn + (size_t)j * L + c];
+      if (hp)
+        for (int j = 0; j < n; ++j)
+          acc += rec(a.O, (size_t)(k - 1) * nn + (size_t)j * n + i, a.dtype) *
+                 xk[(size_t)j * L + c - pn];
+    }
+    r64[(size_t)k * pn + e] = a.done[c] ? 0.0 : a.b[(size_t)k * pn + e] - acc;
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < L; c += 256) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) {
+      const double v = r64[(size_t)k * pn + (size_t)i * L + c];
+      s += v * v;
+    }
+    a.part[(size_t)k * L + c] = s;
+  }
+}
+
+// r = L^{-1} r64 (float), d = 0 for running columns.
+__global__ void __launch_bounds__(256) k_mr_tohat(MrArgs a, const double* r64) {
+  const int k = blockIdx.x, n = a.n, L = a.nrhs;
+  const size_t pn = (size_t)n * L, nn = (size_t)n * n;
+  for (size_t e = threadIdx.x; e < pn; e += 256) {
+    const int i = (int)(e / L), c = (int)(e % L);
+    float acc = 0.f;
+    if (a.act[c]) {
+      const float* row = a.Li + (size_t)k * nn + (size_t)i * n;
+      for (int j = 0; j <= i; ++j)
+        acc = __fmaf_rn(row[j], (float)r64[(size_t)k * pn + (size_t)j * L + c], acc);
+    }
+    a.r[(size_t)k * pn + e] = acc;
+    a.d[(size_t)k * pn + e] = 0.f;
+    a.p[(size_t)k * pn + e] = 0.f;  // beta = 0 at the first step: p = z
+  }
+}
+
+// x += L^{-T} d for the columns that ran an inner solve.
+__global__ void __launch_bounds__(256) k_mr_xupd(MrArgs a) {
+  const int k = blockIdx.x, n = a.n, L = a.nrhs;
+  const size_t pn = (size_t)n * L, nn = (size_t)n * n;
+  for (size_t e = threadIdx.x; e < pn; e += 256) {
+    const int i = (int)(e / L), c = (int)(e % L);
+    if (a.done[c]) continue;
+    float acc = 0.f;
+    for (int j = i; j < n; ++j)
+      acc = __fmaf_rn(a.Li[(size_t)k * nn + (size_t)j * n + i],
+                      a.d[(size_t)k * pn + (size_t)j * L + c], acc);
+    a.x[(size_t)k * pn + e] += (double)acc;
+  }
+}
+
+__global__ void k_mr_outer_done(MrArgs a) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.nrhs || a.done[c]) return;
+  a.outer[c] += 1;
+  if (a.inner[c] == 0) {
+    a.status[c] = BT_EBREAKDOWN;
+    a.done[c] = 1;
+  }
+}
+
+__global__ void k_mr_zero_x(MrArgs a) {
+  const size_t N = (size_t)a.R * a.n * a.nrhs;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (size_t)gridDim.x * blockDim.x)
+    a.x[i] = 0.0;
+}
+
+__global__ void k_mr_info(MrArgs a, bt_info* info) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.nrhs) return;
+  const double nb = a.nb2[c];
+  info[c].status = a.status[c];
+  info[c].iters = a.total[c];
+  info[c].outer = a.outer[c];
+  info[c].fail_index = -1;
+  const double rr = nb > 0.0 ? sqrt(a.nr2[c] / nb) : 0.0;
+  info[c].relres = rr;
+  info[c].relres_true = rr;
+}
+
+// F (float32) -> Fhi + Flo (bfloat16 pair).
+__global__ void k_mr_split(const float* F, unsigned short* hi,
+                           unsigned short* lo, size_t N) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const float v = F[i];
+    const unsigned short h = f2bf(v);
+    hi[i] = h;
+    lo[i] = f2bf(v - bf2f(h));
+  }
+}
+
+template <int NB, int EPI>
+hipError_t app(const MrArgs& a, const float* V, const float* aux, float* out,
+               hipStream_t s) {
+  hipLaunchKernelGGL((k_mr_app<NB, EPI>), dim3(a.R, a.nrhs / CPB), dim3(WG), 0,
+                     s, a, V, aux, out);
+  return hipGetLastError();
+}
+
+template <int NB>
+hipError_t inner_iteration(const MrArgs& a, hipStream_t s, int grid_ew) {
+  hipLaunchKernelGGL(k_mr_axpy_p, dim3(grid_ew), dim3(256), 0, s, a);
+  hipError_t e = app<NB, EPI_Q>(a, a.p, nullptr, a.q, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_mr_colsum<SUM_SIGMA>), dim3(a.nrhs), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_mr_axpy_dr, dim3(grid_ew), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// z = M^{-1} r at a = 1: y0 = r + C r, then per extra term y = C(C y),
+// z = y0 + alpha_1 y (m <= 2 on this path).
+template <int NB>
+hipError_t precond(const MrArgs& a, hipStream_t s) {
+  hipError_t e = app<NB, EPI_Y0>(a, a.r, a.r, a.y0, s);
+  if (e != hipSuccess) return e;
+  if (a.m == 1) {
+    // z = y0 and rho = r'y0: reuse the Z epilogue with alpha_1 = 0
+    MrArgs b = a;
+    b.alpha1 = 0.0;
+    e = app<NB, EPI_W>(b, a.y0, nullptr, a.w, s);
+    if (e != hipSuccess) return e;
+    return app<NB, EPI_Z>(b, a.w, a.y0, a.z, s);
+  }
+  e = app<NB, EPI_W>(a, a.y0, nullptr, a.w, s);
+  if (e != hipSuccess) return e;
+  return app<NB, EPI_Z>(a, a.w, a.y0, a.z, s);
+}
+
+template <int NB>
+int solve(const MrArgs& a0, double* r64, int max_outer, bt_info* info,
+          hipStream_t s) {
+  MrArgs a = a0;
+  const size_t N = (size_t)a.R * a.n * a.nrhs;
+  const int grid_ew = (int)std::min<size_t>((N + 255) / 256, 4096);
+  int hany = 0;
+  std::vector<int> flags(a.nrhs);
+  // any right-hand side still running (its flag, read back after a sync)
+  auto read_any = [&](int* out) -> bool {
+    if (hipMemcpyAsync(flags.data(), a.act, sizeof(int) * a.nrhs,
+                       hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return false;
+    int o = 0;
+    for (int v : flags) o |= v;
+    *out = o;
+    return true;
+  };
+  hipLaunchKernelGGL(k_mr_zero_x, dim3(grid_ew), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_mr_bnorm, dim3(a.R), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(k_mr_init_cols, dim3(a.nrhs), dim3(256), 0, s, a);
+  for (int outer = 0;; ++outer) {
+    hipLaunchKernelGGL(k_mr_resid, dim3(a.R), dim3(256), 0, s, a, r64,
+                       outer == 0 ? 1 : 0);
+    hipLaunchKernelGGL((k_mr_colsum<SUM_RES>), dim3(a.nrhs), dim3(256), 0, s, a);
+    if (!read_any(&hany)) return BT_EHIP;
+    if (hany == 0 || outer >= max_outer) break;
+    hipLaunchKernelGGL(k_mr_tohat, dim3(a.R), dim3(256), 0, s, a, r64);
+    if (precond<NB>(a, s) != hipSuccess) return BT_EHIP;
+    hipLaunchKernelGGL((k_mr_colsum<SUM_RHO>), dim3(a.nrhs), dim3(256), 0, s, a);
+    for (int it = 0;; ++it) {
+      if ((it & 7) == 7) {
+        if (!read_any(&hany)) return BT_EHIP;
+        if (hany == 0) break;
+      }
+      if (inner_iteration<NB>(a, s, grid_ew) != hipSuccess) return BT_EHIP;
+      if (precond<NB>(a, s) != hipSuccess) return BT_EHIP;
+      hipLaunchKernelGGL((k_mr_colsum<SUM_RHO>), dim3(a.nrhs), dim3(256), 0, s, a);
+    }
+    hipLaunchKernelGGL(k_mr_xupd, dim3(a.R), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_mr_outer_done, dim3((a.nrhs + 63) / 64), dim3(64), 0,
+                       s, a);
+  }
+  hipLaunchKernelGGL(k_mr_info, dim3((a.nrhs + 63) / 64), dim3(64), 0, s, a,
+                     info);
+  return hipGetLastError() == hipSuccess ? BT_OK : BT_EHIP;
+}
+
+}  // namespace btm
+
+// Bytes of scratch for a multi-RHS solve: seven float32 panels, the float64
+// residual panel, per-row partial sums and per-column state.
+size_t bt_mrhs_scratch_bytes(int64_t R, int n, int nrhs) {
+  const size_t pn = (size_t)R * n * nrhs;
+  return 7 * pn * sizeof(float) + pn * sizeof(double) +
+         (size_t)R * nrhs * sizeof(double) + 6 * (size_t)nrhs * sizeof(double) +
+         8 * (size_t)nrhs * sizeof(int) + 256;
+}
+
+hipError_t bt_mrhs_split(const float* F, unsigned short* hi, unsigned short* lo,
+                         size_t N, hipStream_t s) {
+  const int grid = (int)std::min<size_t>((N + 255) / 256, 4096);
+  hipLaunchKernelGGL(btm::k_mr_split, dim3(grid), dim3(256), 0, s, F, hi, lo, N);
+  return hipGetLastError();
+}
+
+int bt_mrhs_run(int64_t R, int n, int nrhs, const unsigned short* Fhi,
+                const unsigned short* Flo, const float* Li, const void* D,
+                const void* O, int dtype, const double* b, double* x,
+                double tol, int maxit, int max_outer, double inner_tol, int m,
+                double alpha1, void* scratch, bt_info* info, hipStream_t s) {
+  btm::MrArgs a{};
+  a.R = (int)R;
+  a.n = n;
+  a.nrhs = nrhs;
+  a.Fhi = Fhi;
+  a.Flo = Flo;
+  a.Li = Li;
+  a.D = D;
+  a.O = O;
+  a.dtype = dtype;
+  a.b = b;
+  a.x = x;
+  a.tol = tol;
+  a.itol2 = inner_tol * inner_tol;
+  a.maxit = maxit;
+  a.m = m;
+  a.alpha1 = alpha1;
+  const size_t pn = (size_t)R * n * nrhs;
+  unsigned char* w = (unsigned char*)scratch;
+  float* f = (float*)w;
+  a.p = f;
+  a.q = f + pn;
+  a.r = f + 2 * pn;
+  a.d = f + 3 * pn;
+  a.y0 = f + 4 * pn;
+  a.w = f + 5 * pn;
+  a.z = f + 6 * pn;
+  double* r64 = (double*)(f + 7 * pn);
+  a.part = r64 + pn;
+  double* cs = a.part + (size_t)R * nrhs;
+  a.rho = cs;
+  a.rho0 = cs + nrhs;
+  a.alpha = cs + 2 * nrhs;
+  a.beta = cs + 3 * nrhs;
+  a.nb2 = cs + 4 * nrhs;
+  a.nr2 = cs + 5 * nrhs;
+  int* is = (int*)(cs + 6 * nrhs);
+  a.act = is;
+  a.done = is + nrhs;
+  a.first = is + 2 * nrhs;
+  a.inner = is + 3 * nrhs;
+  a.total = is + 4 * nrhs;
+  a.outer = is + 5 * nrhs;
+  a.status = is + 6 * nrhs;
+  if (n == 48) return btm::solve<48>(a, r64, max_outer, info, s);
+  if (n == 32) return btm::solve<32>(a, r64, max_outer, info, s);
+  if (n == 16) return btm::solve<16>(a, r64, max_outer, info, s);
+  if (n == 64) return btm::solve<64>(a, r64, max_outer, info, s);
+  return BT_EINVAL;
+}

@@ -1,0 +1,85 @@
+"""Many right-hand sides on the matrix cores (BF16 hi/lo split blocks, float32
+accumulation, float64 refinement) against the oracle's direct solve, per
+right-hand side."""
+import numpy as np
+import pytest
+
+import lqrgen
+import oracle as orc
+import paper_2503_15269_amd as bt
+from gpu_util import to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu(oracle_lib):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    bt.load_library()
+
+
+def run_mrhs(N, n, nu, nrhs, seed, s=0.05, tol=1e-10, m=2, record="f32"):
+    import torch
+    d = lqrgen.lqr_instance(N, n, nu, seed, 0, s=s, nrhs=nrhs)
+    D, O, B = d["D"], d["O"], d["b"]
+    if record == "f32":
+        D = D.astype(np.float32).astype(np.float64)
+        O = O.astype(np.float32).astype(np.float64)
+    dt = torch.float32 if record == "f32" else torch.float64
+    h = bt.Handle(to_dev(D, dt), to_dev(O, dt), None,
+                  bt.Params.polycoeff(m, prec="bf16x2_ir", inner_tol=1e-4))
+    X, info = h.solve_mrhs(to_dev(B, torch.float64), tol)
+    torch.cuda.synchronize()
+    return D, O, B, X.cpu().numpy(), bt.infos_to_numpy(info)
+
+
+def check(D, O, B, X, info, tol=1e-10, err_bound=2e-5, cols=None):
+    assert np.all(info["status"] == bt.OK), np.unique(info["status"])
+    assert np.all(info["relres_true"] <= tol)
+    Xd = orc.btchol_solve(D, O, B)
+    for c in (range(B.shape[2]) if cols is None else cols):
+        r = B[:, :, c] - orc.spmv(D, O, X[:, :, c])
+        assert np.linalg.norm(r) <= 1.01 * tol * np.linalg.norm(B[:, :, c]), c
+        err = np.linalg.norm(X[:, :, c] - Xd[:, :, c]) / np.linalg.norm(Xd[:, :, c])
+        assert err <= err_bound, (c, err)
+
+
+@pytest.mark.parametrize("m", [1, 2])
+def test_mrhs_n48_small(m):
+    D, O, B, X, info = run_mrhs(40, 48, 16, 64, seed=5, m=m)
+    check(D, O, B, X, info)
+
+
+def test_mrhs_n16_two_column_blocks():
+    D, O, B, X, info = run_mrhs(33, 16, 5, 128, seed=6, s=0.1)
+    check(D, O, B, X, info)
+
+
+def test_mrhs_f64_record_and_zero_column():
+    import torch
+    d = lqrgen.lqr_instance(20, 32, 8, 8, 0, s=0.1, nrhs=64)
+    B = d["b"].copy()
+    B[:, :, 5] = 0.0
+    h = bt.Handle(to_dev(d["D"], torch.float64), to_dev(d["O"], torch.float64),
+                  None, bt.Params.polycoeff(2, prec="bf16x2_ir"))
+    X, info = h.solve_mrhs(to_dev(B, torch.float64), 1e-10)
+    inf = bt.infos_to_numpy(info)
+    X = X.cpu().numpy()
+    assert inf[5]["status"] == bt.OK and inf[5]["iters"] == 0
+    assert not np.any(X[:, :, 5])
+    check(d["D"], d["O"], B, X, inf, cols=[0, 1, 17, 63])
+
+
+def test_mrhs_argument_checks():
+    import torch
+    d = lqrgen.lqr_instance(8, 16, 4, 1, 0, nrhs=64)
+    Dt, Ot = to_dev(d["D"], torch.float64), to_dev(d["O"], torch.float64)
+    B = to_dev(d["b"], torch.float64)
+    h = bt.Handle(Dt, Ot, None, bt.Params.polycoeff(2, prec="f32_ir"))
+    with pytest.raises(bt.BtError):
+        h.solve_mrhs(B)                      # handle not set up for bf16x2
+    h2 = bt.Handle(Dt, Ot, None, bt.Params.polycoeff(2, prec="bf16x2_ir"))
+    with pytest.raises(bt.BtError):
+        h2.solve_mrhs(B[:, :, :32].contiguous())   # nrhs not a multiple of 64
