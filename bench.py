@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--inner-tol", type=float, default=None,
                     help="inner tolerance of the refinement (default: the "
                          "autotuned value)")
+    ap.add_argument("--no-workloads", action="store_true",
+                    help="skip the secondary measurements of the other "
+                         "standard workloads")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times "
                          "(calibrates the HBM byte counters of the profiler)")
@@ -132,6 +135,164 @@ def solve_bytes(horizons, n, iters, outer):
     per_it = 4 * n * n
     per_outer = 4 * 2 * n * n + 8 * 3 * n + 2 * 4 * n * n
     return float(np.sum(horizons * (iters * per_it + outer * per_outer)))
+
+
+def gemv_count(a, m, pc):
+    """The paper's g_a(m) (Section IV-B): block gemvs per PCG iteration for
+    A p and M^{-1} r; 3 (A p only) without preconditioner."""
+    if pc == "none":
+        return 3
+    if a == 0.0:
+        return 2 * m + 2
+    if a == 1.0:
+        return 3 * m + 3
+    return 5 * m + 1
+
+
+def _events_ms(fn, reps, warmup=2):
+    """Median event time of ``fn`` on the current stream (eager launches)."""
+    import torch
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1))
+    return float(np.median(out))
+
+
+def _graph_ms(fn, reps, warmup=3):
+    """Median event time of one replay of a HIP graph holding ``fn``."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    return _events_ms(g.replay, reps, warmup)
+
+
+def workloads_secondary(bt, torch, dev):
+    """Solve rates and counts on the other standard workloads (a single
+    N = 32 and N = 512 system, the n = 24 differentiable batch, the n = 48
+    system with 64 right-hand sides). Each figure is setup + solve unless
+    named otherwise; all runs are checked for convergence to 1e-10."""
+    tol = 1e-10
+    res = {}
+
+    def one(name):
+        w = lqrgen.WORKLOADS[name]
+        return w, lqrgen.lqr_instance(w["N"], w["nx"], w["nu"],
+                                      lqrgen.workload_seed(w["index"]), 0,
+                                      s=w["s"], nrhs=w["nrhs"])
+
+    # single systems, float64 record: every preconditioner variant, plain
+    # float64 iteration and float32 iteration with float64 refinement
+    variants = [("polycoeff_m2", bt.Params.polycoeff(2)),
+                ("opt_m1", bt.Params(a=1.0, m=1)),
+                ("opt_m2", bt.Params(a=1.0, m=2)),
+                ("block_jacobi_m1", bt.Params.block_jacobi(1)),
+                ("block_jacobi_m2", bt.Params.block_jacobi(2)),
+                ("none", bt.Params(pc="none"))]
+    for name in ("single_n6", "single_n12"):
+        w, d = one(name)
+        D = torch.tensor(d["D"], dtype=torch.float64, device=dev)
+        O = torch.tensor(d["O"], dtype=torch.float64, device=dev)
+        b = torch.tensor(d["b"].reshape(-1), dtype=torch.float64, device=dev)
+        rows = {}
+        for vname, p0 in variants:
+            for prec in ("f64", "f32_ir"):
+                p = bt.Params(a=p0.a, b=p0.b, m=p0.m, alpha=p0.alpha,
+                              pc=p0.pc, prec=prec, inner_tol=1e-4)
+                h = bt.Handle(D, O, None, p)
+                x, info = h.solve(b, tol)
+                torch.cuda.synchronize()
+                inf = bt.infos_to_numpy(info)[0]
+                if inf["status"] != bt.OK:
+                    rows[f"{vname}/{prec}"] = {"status": int(inf["status"])}
+                    continue
+
+                def step(h=h, x=x, info=info):
+                    h.refactor()
+                    h.solve(b, tol, x=x, info=info)
+                ms = _graph_ms(step, 10)
+                rows[f"{vname}/{prec}"] = {
+                    "solves_per_s": 1e3 / ms, "ms": ms,
+                    "iters": int(inf["iters"]), "outer": int(inf["outer"]),
+                    "block_gemvs": int(inf["iters"]) *
+                    gemv_count(p.a, p.m, p.pc),
+                    "relres_true": float(inf["relres_true"])}
+        res[name] = rows
+
+    # differentiable batch: forward solve + adjoint (dL/db, dL/dD, dL/dO)
+    w = lqrgen.WORKLOADS["batch_grad_n24"]
+    d = lqrgen.lqr_batch(w["B"], w["N"], w["nx"], w["nu"],
+                         lqrgen.workload_seed(w["index"]), s=w["s"],
+                         with_target=True, record=w["record"])
+    D = torch.tensor(d["D"], dtype=torch.float32, device=dev)
+    O = torch.tensor(d["O"], dtype=torch.float32, device=dev)
+    b = torch.tensor(d["b"].reshape(-1), dtype=torch.float64, device=dev)
+    t = torch.tensor(d["t"].reshape(-1), dtype=torch.float64, device=dev)
+    from paper_2503_15269_amd import autotune
+    tuned = autotune.tune(D, O, d["offsets"], b,
+                          bt.Params.polycoeff(2, prec="f32_ir"), tol, reps=2,
+                          use_cache=False)
+    h = bt.Handle(D, O, d["offsets"], tuned["params"])
+    h.set_kernel_config(tuned["kernel_config"])
+    x, info = h.solve(b, tol)
+    g = 2 * (x - t)
+    lam, dD, dO, ainfo = h.adjoint(x, g, tol)
+    torch.cuda.synchronize()
+    fi, ai = bt.infos_to_numpy(info), bt.infos_to_numpy(ainfo)
+    assert np.all(fi["status"] == bt.OK) and np.all(ai["status"] == bt.OK)
+
+    def fwd():
+        h.refactor()
+        h.solve(b, tol, x=x, info=info)
+
+    def adj():
+        torch.mul(x - t, 2.0, out=g)
+        h.adjoint(x, g, tol)
+
+    fwd_ms = _events_ms(fwd, 10)
+    adj_ms = _events_ms(adj, 10)
+    fa_ms = _events_ms(lambda: (fwd(), adj()), 10)
+    res["batch_grad_n24"] = {
+        "fwd_adj_ms": fa_ms, "fwd_ms": fwd_ms, "adj_ms": adj_ms,
+        "inner_tol": tuned["params"].inner_tol,
+        "kernel_config": tuned["kernel_config"],
+        "fwd_iters_mean": float(fi["iters"].mean()),
+        "adj_iters_mean": float(ai["iters"].mean()),
+        "relres_true_max": float(max(fi["relres_true"].max(),
+                                     ai["relres_true"].max()))}
+
+    # one system, 64 right-hand sides, BF16 split blocks on the matrix cores
+    w, d = one("multirhs_n48")
+    Dd = d["D"].astype(np.float32)
+    Od = d["O"].astype(np.float32)
+    D = torch.tensor(Dd, device=dev)
+    O = torch.tensor(Od, device=dev)
+    Bm = torch.tensor(d["b"], dtype=torch.float64, device=dev)
+    h = bt.Handle(D, O, None, bt.Params.polycoeff(2, prec="bf16x2_ir",
+                                                  inner_tol=1e-4))
+    X, minfo = h.solve_mrhs(Bm, tol)
+    torch.cuda.synchronize()
+    mi = bt.infos_to_numpy(minfo)
+    assert np.all(mi["status"] == bt.OK)
+    mr_ms = _events_ms(lambda: (h.refactor(), h.solve_mrhs(Bm, tol, X=X)), 5)
+    res["multirhs_n48"] = {
+        "ms": mr_ms, "rhs_solves_per_s": w["nrhs"] * 1e3 / mr_ms,
+        "iters_mean": float(mi["iters"].mean()),
+        "outer_mean": float(mi["outer"].mean()),
+        "relres_true_max": float(mi["relres_true"].max())}
+    return res
 
 
 def cpu_baseline(data, budget_s, cores):
@@ -302,6 +463,9 @@ def main():
     batched_f64 = 3 * B / (time.perf_counter() - t1)
     it64 = bt.infos_to_numpy(i64)
 
+    secondary = (None if args.no_workloads
+                 else workloads_secondary(bt, torch, dev))
+
     cores = min(16, len(os.sched_getaffinity(0)))
     cpu = None if args.no_cpu else cpu_baseline(data, args.cpu_seconds, cores)
 
@@ -345,6 +509,7 @@ def main():
             "f64_iters_mean": float(it64["iters"].mean()),
             "speedup_vs_plain_f64": value / plain_f64,
             "speedup_vs_batched_f64": value / batched_f64,
+            "workloads": secondary,
         },
     }
     print(json.dumps(out), flush=True)

@@ -125,8 +125,11 @@ size_t bt_workspace_bytes(int B, const int64_t* offsets_host, int n,
  * offsets_host: host array, B+1 entries. D, O: device, see the layouts above.
  * The workspace (device, >= bt_workspace_bytes) receives the factors.
  * On success *h receives a new handle. Errors: BT_EINVAL (B < 1, n < 1 or
- * n > 64, an empty instance, an instance too large for one workgroup,
- * parameters outside C_g, m outside 1..BT_MAX_M, NULL pointers),
+ * n > 64, an empty instance, an instance too large for one workgroup
+ * (N_i * n above 8192 elements; allowed with BT_BF16X2_IR, whose
+ * many-right-hand-side solve spans the grid, while the other calls on such
+ * a handle then fail with BT_EINVAL), parameters outside C_g, m outside
+ * 1..BT_MAX_M, NULL pointers),
  * BT_ENOSPACE, BT_EHIP. A non-SPD D_k is reported by the next solve
  * (status BT_ENOTSPD, fail_index). */
 int bt_batch_setup(bt_handle** h, int B, const int64_t* offsets_host, int n,

@@ -69,8 +69,8 @@ Layout layout(int B, int64_t R, int n, size_t es, bool split) {
   l.order = at; at += align_up(sizeof(int32_t) * B);
   l.ctr = at; at += align_up(sizeof(int32_t) * 64);
   l.fail = at; at += align_up(sizeof(int32_t) * B);
-  l.bins = at; at += align_up(sizeof(int32_t) * 2 * B);
-  l.items = at; at += align_up(sizeof(int32_t) * B);
+  l.bins = at; at += BT_FAST_VARIANTS * align_up(sizeof(int32_t) * 2 * B);
+  l.items = at; at += BT_FAST_VARIANTS * align_up(sizeof(int32_t) * B);
   const size_t blk = align_up(es * (size_t)R * n * n);
   l.F = at; at += blk;
   l.L = at; at += blk;
@@ -82,14 +82,17 @@ Layout layout(int B, int64_t R, int n, size_t es, bool split) {
   return l;
 }
 
-// Configuration index of the register-resident bin kernel (after the
-// generic ones).
+// Configuration indices of the register-resident bin kernel variants (after
+// the generic ones).
 int fast_index() { return bt_num_kernel_configs(); }
-bool is_fast(int cfg) { return cfg == fast_index(); }
-const KernelConfig kFastConfig = {1024, 0, BT_F32};
+bool is_fast(int cfg) {
+  return cfg >= fast_index() && cfg < fast_index() + BT_FAST_VARIANTS;
+}
+int num_configs() { return bt_num_kernel_configs() + BT_FAST_VARIANTS; }
+KernelConfig fast_config(int v) { return {bt_fast_threads(v), 0, BT_F32}; }
 
-const KernelConfig& config_at(int i) {
-  return is_fast(i) ? kFastConfig : bt_kernel_config_at(i);
+KernelConfig config_at(int i) {
+  return is_fast(i) ? fast_config(i - fast_index()) : bt_kernel_config_at(i);
 }
 
 // Smallest generic configuration of the right precision whose capacity holds
@@ -117,7 +120,8 @@ int generic_config(const bt_handle* h) {
 
 int config_for(const bt_handle* h) {
   if (h->cfg >= 0) return h->cfg;
-  if (h->nbins > 0) return fast_index();
+  for (int v = 0; v < BT_FAST_VARIANTS; ++v)  // 3 entries per lane first
+    if (h->nbins[v] > 0) return fast_index() + v;
   return generic_config(h);
 }
 
@@ -206,12 +210,13 @@ int run(const bt_handle* h, SolveArgs& a, hipStream_t s) {
   if (is_fast(cfg) && (a.mode != 0 || !a.ir)) cfg = generic_config(h);
   if (cfg < 0) return BT_EINVAL;
   if (is_fast(cfg)) {
-    a.bins = h->bins;
-    a.bin_items = h->bin_items;
-    a.nbins = h->nbins;
+    const int v = cfg - fast_index();
+    a.bins = h->bins[v];
+    a.bin_items = h->bin_items[v];
+    a.nbins = h->nbins[v];
     const int grid =
-        std::max(1, std::min(h->nbins, bt_fast_max_grid(h->n)));
-    return hip_status(bt_launch_fast(a, grid, s));
+        std::max(1, std::min(h->nbins[v], bt_fast_max_grid(h->n, v)));
+    return hip_status(bt_launch_fast(a, v, grid, s));
   }
   const int grid = std::max(1, std::min(h->B, bt_solve_max_grid(cfg)));
   return hip_status(bt_launch_solve(cfg, a, grid, s));
@@ -269,7 +274,11 @@ int bt_batch_setup(bt_handle** h, int B, const int64_t* offsets_host, int n,
   const int64_t R = check_offsets(B, offsets_host, &maxN);
   if (R < 0) return BT_EINVAL;
   if (R > B && !O) return BT_EINVAL;
-  if (auto_config(kernel_prec(p), (int64_t)maxN * n) < 0) return BT_EINVAL;
+  // The single-workgroup solve kernels must hold the largest instance; the
+  // many-right-hand-side solve of a bf16x2 handle spans the grid instead.
+  if (p->prec != BT_BF16X2_IR &&
+      auto_config(kernel_prec(p), (int64_t)maxN * n) < 0)
+    return BT_EINVAL;
   const Layout l = layout(B, R, n, elem_bytes(p), p->prec == BT_BF16X2_IR);
   if (ws_bytes < l.total) return BT_ENOSPACE;
 
@@ -288,8 +297,10 @@ int bt_batch_setup(bt_handle** h, int B, const int64_t* offsets_host, int n,
   hh->order = (int32_t*)(w + l.order);
   hh->ctr = (int32_t*)(w + l.ctr);
   hh->fail = (int32_t*)(w + l.fail);
-  hh->bins = (int32_t*)(w + l.bins);
-  hh->bin_items = (int32_t*)(w + l.items);
+  for (int v = 0; v < BT_FAST_VARIANTS; ++v) {
+    hh->bins[v] = (int32_t*)(w + l.bins + v * align_up(sizeof(int32_t) * 2 * B));
+    hh->bin_items[v] = (int32_t*)(w + l.items + v * align_up(sizeof(int32_t) * B));
+  }
   hh->F = w + l.F;
   hh->L = w + l.L;
   hh->Li = w + l.Li;
@@ -306,26 +317,31 @@ int bt_batch_setup(bt_handle** h, int B, const int64_t* offsets_host, int n,
     return offsets_host[x + 1] - offsets_host[x] >
            offsets_host[y + 1] - offsets_host[y];
   });
-  std::vector<int32_t> bins, items;
-  if (bt_fast_params(p) && bt_fast_supported(n, p->prec) &&
-      maxN <= bt_fast_rows_per_bin(n)) {
-    pack_bins(order, offsets_host, bt_fast_rows_per_wave(n),
-              bt_fast_rows_per_bin(n), bt_fast_max_systems_per_bin(), bins,
-              items);
-    hh->nbins = (int)(bins.size() / 2);
+  std::vector<int32_t> bins[BT_FAST_VARIANTS], items[BT_FAST_VARIANTS];
+  for (int v = 0; v < BT_FAST_VARIANTS; ++v) {
+    if (bt_fast_params(p) && bt_fast_supported(n, p->prec, v) &&
+        maxN <= bt_fast_rows_per_bin(n)) {
+      pack_bins(order, offsets_host, bt_fast_rows_per_wave(n, v),
+                bt_fast_rows_per_bin(n), bt_fast_max_systems_per_bin(),
+                bins[v], items[v]);
+      hh->nbins[v] = (int)(bins[v].size() / 2);
+    }
   }
   hipStream_t s = (hipStream_t)stream;
-  if (hipMemcpyAsync(hh->off, hh->off_host.data(), sizeof(int64_t) * (B + 1),
-                     hipMemcpyHostToDevice, s) != hipSuccess ||
+  bool ok =
+      hipMemcpyAsync(hh->off, hh->off_host.data(), sizeof(int64_t) * (B + 1),
+                     hipMemcpyHostToDevice, s) == hipSuccess &&
       hipMemcpyAsync(hh->order, order.data(), sizeof(int32_t) * B,
-                     hipMemcpyHostToDevice, s) != hipSuccess ||
-      (hh->nbins > 0 &&
-       (hipMemcpyAsync(hh->bins, bins.data(), sizeof(int32_t) * bins.size(),
-                       hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(hh->bin_items, items.data(),
-                       sizeof(int32_t) * items.size(), hipMemcpyHostToDevice,
-                       s) != hipSuccess)) ||
-      hipStreamSynchronize(s) != hipSuccess) {
+                     hipMemcpyHostToDevice, s) == hipSuccess;
+  for (int v = 0; v < BT_FAST_VARIANTS && ok; ++v)
+    if (hh->nbins[v] > 0)
+      ok = hipMemcpyAsync(hh->bins[v], bins[v].data(),
+                          sizeof(int32_t) * bins[v].size(),
+                          hipMemcpyHostToDevice, s) == hipSuccess &&
+           hipMemcpyAsync(hh->bin_items[v], items[v].data(),
+                          sizeof(int32_t) * items[v].size(),
+                          hipMemcpyHostToDevice, s) == hipSuccess;
+  if (!ok || hipStreamSynchronize(s) != hipSuccess) {
     delete hh;
     return BT_EHIP;
   }
@@ -420,11 +436,11 @@ int bt_solve_mrhs(const bt_handle* h, int nrhs, const double* b, double* x,
                      scratch, info, (hipStream_t)stream);
 }
 
-int bt_kernel_config_count(void) { return bt_num_kernel_configs() + 1; }
+int bt_kernel_config_count(void) { return num_configs(); }
 
 int bt_kernel_config(int i, int* nt, int* s, int* prec) {
-  if (i < 0 || i > bt_num_kernel_configs()) return BT_EINVAL;
-  const KernelConfig& c = config_at(i);
+  if (i < 0 || i >= num_configs()) return BT_EINVAL;
+  const KernelConfig c = config_at(i);
   if (nt) *nt = c.nt;
   if (s) *s = c.s;
   if (prec) *prec = c.prec;
@@ -437,9 +453,9 @@ int bt_set_kernel_config(bt_handle* h, int i) {
     h->cfg = -1;
     return BT_OK;
   }
-  if (i > bt_num_kernel_configs()) return BT_EINVAL;
+  if (i >= num_configs()) return BT_EINVAL;
   if (is_fast(i)) {
-    if (h->nbins <= 0) return BT_EINVAL;
+    if (h->nbins[i - fast_index()] <= 0) return BT_EINVAL;
     h->cfg = i;
     return BT_OK;
   }

@@ -9,6 +9,8 @@
 #include "btpcg.h"
 
 #define BT_NO_FAIL 0x7fffffff
+// Variants of the register-resident bin kernel (3, 6, 12 entries per lane).
+#define BT_FAST_VARIANTS 3
 
 // Host-side handle. Device pointers point into the caller's workspace.
 struct bt_handle {
@@ -21,9 +23,11 @@ struct bt_handle {
   int32_t* order = nullptr; // [B] instances, longest first
   int32_t* ctr = nullptr;   // [64] queue counters of the persistent kernels
   int32_t* fail = nullptr;  // [B] first failing block row, BT_NO_FAIL if none
-  int32_t* bins = nullptr;  // [B][2] bins of the register-resident kernel
-  int32_t* bin_items = nullptr;  // [B]
-  int nbins = 0;            // 0: the register-resident kernel does not apply
+  // bins of the register-resident kernel, per variant: [B][2] (start, count)
+  // and the systems of the bins, bin after bin; nbins 0: variant n/a
+  int32_t* bins[BT_FAST_VARIANTS] = {};
+  int32_t* bin_items[BT_FAST_VARIANTS] = {};
+  int nbins[BT_FAST_VARIANTS] = {};
   void* F = nullptr;        // [R][n][n] scaled off-diagonal blocks
   void* L = nullptr;        // [R][n][n] Cholesky factors of D_k
   void* Li = nullptr;       // [R][n][n] their inverses
@@ -84,13 +88,15 @@ hipError_t bt_launch_solve(int cfg, const SolveArgs& a, int grid,
                            hipStream_t s);
 int bt_solve_max_grid(int cfg);
 hipError_t bt_launch_setup(const SetupArgs& a, hipStream_t s);
-bool bt_fast_supported(int n, int prec);
+bool bt_fast_supported(int n, int prec, int variant);
 bool bt_fast_params(const bt_params* p);
-int bt_fast_rows_per_wave(int n);
+int bt_fast_threads(int variant);
+int bt_fast_rows_per_wave(int n, int variant);
 int bt_fast_rows_per_bin(int n);
 int bt_fast_max_systems_per_bin();
-hipError_t bt_launch_fast(const SolveArgs& a, int grid, hipStream_t s);
-int bt_fast_max_grid(int n);
+hipError_t bt_launch_fast(const SolveArgs& a, int variant, int grid,
+                          hipStream_t s);
+int bt_fast_max_grid(int n, int variant);
 hipError_t bt_launch_setup_init(int B, int32_t* fail, int32_t* ctr,
                                 hipStream_t s);
 size_t bt_mrhs_scratch_bytes(int64_t R, int n, int nrhs);

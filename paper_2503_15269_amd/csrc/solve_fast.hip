@@ -9,27 +9,33 @@
 // polynomial  sum_i alpha_i ((1-a) C + a C^2)^i (I + a C),  evaluated as
 // y_0 = G r, y_i = H y_{i-1}, z = sum alpha_i y_i.
 //
-// Layout on the chip. A workgroup of 1024 threads owns a "bin" of systems
-// whose block rows (each system padded to a whole wavefront of rows) total at
-// most RPB. TPR = NB/3 neighbouring lanes (a quad for NB = 12) share a block
-// row k; lane q owns entries 3q..3q+2 of every vector row and keeps rows
-// 3q..3q+2 of F_k in registers (3*NB floats), read from memory once per bin.
-// One application of C then needs, per lane:
-//   * the forward product F_k v_{k+1}: its 3 rows times the next vector row,
-//     read from LDS (TPR 16-byte broadcast reads);
+// Layout on the chip. A workgroup owns a "bin" of systems whose block rows
+// (each system padded to a whole wavefront of rows) total at most RPB (256
+// rows for NB = 12, 128 for NB = 24). TPR = NB / EPT neighbouring lanes share
+// a block row k; lane q owns entries EPT q .. EPT q + EPT - 1 of every vector
+// row and keeps the same rows of F_k in registers (EPT * NB floats), read
+// from memory once per bin. EPT (3, 6 or 12 entries per lane) trades lanes
+// for registers: the workgroup has RPB * TPR threads, and fewer, wider lanes
+// spend fewer instructions on shuffles and reductions per entry but hide
+// less latency; the autotuner picks. One application of C then needs, per
+// lane:
+//   * the forward product F_k v_{k+1}: its EPT rows times the next vector
+//     row, read from LDS (16-byte broadcast reads);
 //   * the transposed product F_{k-1}^T v_{k-1}: the lanes of row k-1 form
 //     partial sums over their own rows for all NB columns (own vector
-//     entries, no LDS), reduce-scatter them inside the row with DPP quad
-//     permutations (xor 2, then xor 1), and hand the 3 finished sums of lane q
-//     to lane q of row k through LDS.
+//     entries, no LDS), reduce-scatter them inside the row with DPP moves
+//     (for eight lanes the half-row mirror, partner q xor 7, first; then the
+//     quad permutations xor 2 and xor 1), and hand the EPT finished sums of
+//     lane q to lane q of row k through LDS.
 // The column order of the F registers is permuted per lane (chunk c of lane q
-// holds columns 3 (c xor q) .. +2) so that the reduce-scatter needs no
-// selects. Systems start on a wavefront boundary, so every per-system
-// quantity (scalars, convergence masks) is uniform within a wavefront;
-// reductions are a DPP wave sum plus an in-order sum over the system's
-// wavefronts, and a converged system stops updating while the others in its
-// bin go on. F is zero for the last row of a system, so systems sharing a bin
-// do not couple.
+// holds columns EPT (c xor q) .. +EPT-1) so that the reduce-scatter needs no
+// selects. In LDS a vector row is stored in 16-byte slots of 3 entries
+// (entry j at 4 (j / 3) + j % 3). Systems start on a wavefront boundary, so
+// every per-system quantity (scalars, convergence masks) is uniform within a
+// wavefront; reductions are a DPP wave sum plus an in-order sum over the
+// system's wavefronts, and a converged system stops updating while the
+// others in its bin go on. F is zero for the last row of a system, so systems
+// sharing a bin do not couple.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
@@ -40,22 +46,27 @@ namespace btf {
 using btk::AccD;
 using btk::AccF;
 
-constexpr int NT = 1024;
-constexpr int NW = NT / 64;  // 16: one DPP row of partials
-static_assert(NW == 16, "cross-wave sums use one 16-lane DPP row");
 constexpr int SL = 4;      // reduction slots (reuse distance)
 constexpr int MAXI = 64;   // systems per bin, upper bound
-constexpr int EPT = 3;     // vector entries per lane
+constexpr int MAXW = 16;   // wavefronts per workgroup, upper bound
 
-template <int NB>
+template <int NB, int EPT>
 struct Geo {
-  static constexpr int TPR = NB / EPT;   // lanes per block row
-  static constexpr int RPW = 64 / TPR;   // block rows per wavefront
-  static constexpr int RPB = NT / TPR;   // block rows per bin
-  static constexpr int ROW = TPR * 4;    // floats per staged row (padded)
-  static_assert(NB % EPT == 0, "block size must be a multiple of 3");
-  static_assert(TPR == 2 || TPR == 4, "2 or 4 lanes per block row");
+  static constexpr int TPR = NB / EPT;            // lanes per block row
+  static constexpr int RPW = 64 / TPR;            // block rows per wavefront
+  static constexpr int RPB = NB == 12 ? 256 : 128;  // block rows per bin
+  static constexpr int NT = RPB * TPR;            // threads per workgroup
+  static constexpr int NW = NT / 64;              // wavefronts
+  static constexpr int SUB = EPT / 3;             // 16-byte slots per lane
+  static constexpr int ROW = NB / 3 * 4;          // floats per staged row
+  static_assert(NB % EPT == 0 && EPT % 3 == 0, "EPT divides NB, 3 | EPT");
+  static_assert(TPR == 1 || TPR == 2 || TPR == 4 || TPR == 8,
+                "1, 2, 4 or 8 lanes per block row");
+  static_assert(NW <= MAXW, "at most 16 wavefronts");
 };
+
+// LDS position of entry j of a staged vector row
+__host__ __device__ constexpr int spos(int j) { return 4 * (j / 3) + j % 3; }
 
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
@@ -75,13 +86,14 @@ __device__ __forceinline__ double uni(double v) {
                               (long long)(unsigned int)lo);
 }
 
-template <int NB>
+template <int NB, int EPT>
 struct Smem {
-  float V[2][Geo<NB>::RPB * Geo<NB>::ROW];  // staged vector rows
-  float T[2][Geo<NB>::RPB * Geo<NB>::ROW];  // transposed sums for row k+1
-  double xs[Geo<NB>::RPB * NB];             // float64 iterate of the bin
-  AccF redF[SL][NW];
-  double redD[SL][NW];
+  using G = Geo<NB, EPT>;
+  float V[2][G::RPB * G::ROW];  // staged vector rows
+  float T[2][G::RPB * G::ROW];  // transposed sums for row k+1
+  double xs[G::RPB * NB];       // float64 iterate of the bin
+  AccF redF[SL][MAXW];
+  double redD[SL][MAXW];
   int active;   // running count of (wavefront, flag) events, never reset
   int bin;
   int cnt;
@@ -90,35 +102,65 @@ struct Smem {
   int nrows[MAXI];
 };
 
-template <int NB>
+template <int NB, int EPT>
 struct Ctx {
-  using G = Geo<NB>;
-  Smem<NB>& sm;
+  using G = Geo<NB, EPT>;
+  Smem<NB, EPT>& sm;
   int lrow, q, wave, w0, w1;
   int k, N;          // row within the system, system length (0: idle lane)
   bool row_ok;       // a real block row (not padding, not idle)
   int sf, sd, seen;
-  float Fr[EPT][NB]; // rows 3q..3q+2 of F_k, columns in lane order
+  float Fr[EPT][NB]; // own rows of F_k, columns in lane order
 
-  __device__ Ctx(Smem<NB>& s) : sm(s) {}
+  __device__ Ctx(Smem<NB, EPT>& s) : sm(s) {}
+
+  // own entries into a staged row (SUB 16-byte slots)
+  __device__ __forceinline__ void put(float* row, const float (&v)[EPT]) const {
+#pragma unroll
+    for (int h = 0; h < G::SUB; ++h)
+      *reinterpret_cast<float4*>(row + 4 * (G::SUB * q + h)) =
+          make_float4(v[3 * h], v[3 * h + 1], v[3 * h + 2], 0.f);
+  }
 
   __device__ __forceinline__ int col(int x) const {  // lane-order column
     return EPT * ((x / EPT) ^ q) + x % EPT;
   }
 
   // ---- one application of C in two halves around a barrier -------------
+  // partial sum of the transposed product for lane-order column x: own rows
+  // of F_k times own entries of v
+  __device__ __forceinline__ float tprod(int x, const float (&v)[EPT]) const {
+    float s = Fr[0][x] * v[0];
+#pragma unroll
+    for (int e = 1; e < EPT; ++e) s = __fmaf_rn(Fr[e][x], v[e], s);
+    return s;
+  }
+
   template <int BUF>
   __device__ __forceinline__ void prep(const float (&v)[EPT]) {
-    float P[NB];
-#pragma unroll
-    for (int x = 0; x < NB; ++x) {
-      float s = Fr[0][x] * v[0];
-#pragma unroll
-      for (int e = 1; e < EPT; ++e) s = __fmaf_rn(Fr[e][x], v[e], s);
-      P[x] = s;
-    }
     float S[EPT];
-    if constexpr (G::TPR == 4) {
+    if constexpr (G::TPR == 8) {
+      // Partner q xor 7 (mirror inside the 8-lane half row), then xor 2, then
+      // xor 1. The upper half of the partial sums is formed first and each
+      // lower slot is folded in as soon as it is formed, which keeps at most
+      // 5 of the 8 column chunks live.
+      float Ph[4 * EPT], K1[4 * EPT], K[2 * EPT];
+#pragma unroll
+      for (int y = 0; y < 4 * EPT; ++y) Ph[y] = tprod(4 * EPT + y, v);
+#pragma unroll
+      for (int y = 0; y < 4 * EPT; ++y)
+        K1[y] = tprod(y, v) + dpp<btk::DPP_ROW_HALF_MIRROR>(
+                                  Ph[EPT * (3 - y / EPT) + y % EPT]);
+#pragma unroll
+      for (int y = 0; y < 2 * EPT; ++y)
+        K[y] = K1[y] + dpp<btk::DPP_QUAD_2301>(K1[2 * EPT + y]);
+#pragma unroll
+      for (int z = 0; z < EPT; ++z)
+        S[z] = K[z] + dpp<btk::DPP_QUAD_1032>(K[EPT + z]);
+    } else if constexpr (G::TPR == 4) {
+      float P[NB];
+#pragma unroll
+      for (int x = 0; x < NB; ++x) P[x] = tprod(x, v);
       float K[2 * EPT];
 #pragma unroll
       for (int y = 0; y < 2 * EPT; ++y)
@@ -126,39 +168,54 @@ struct Ctx {
 #pragma unroll
       for (int z = 0; z < EPT; ++z)
         S[z] = K[z] + dpp<btk::DPP_QUAD_1032>(K[EPT + z]);
-    } else {
+    } else if constexpr (G::TPR == 2) {
+      float P[NB];
+#pragma unroll
+      for (int x = 0; x < NB; ++x) P[x] = tprod(x, v);
 #pragma unroll
       for (int z = 0; z < EPT; ++z)
         S[z] = P[z] + dpp<btk::DPP_QUAD_1032>(P[EPT + z]);
+    } else {
+#pragma unroll
+      for (int z = 0; z < EPT; ++z) S[z] = tprod(z, v);
     }
-    const int o = lrow * G::ROW + 4 * q;
-    *reinterpret_cast<float4*>(&sm.V[BUF][o]) = make_float4(v[0], v[1], v[2], 0.f);
-    *reinterpret_cast<float4*>(&sm.T[BUF][o]) = make_float4(S[0], S[1], S[2], 0.f);
+    put(&sm.V[BUF][lrow * G::ROW], v);
+    put(&sm.T[BUF][lrow * G::ROW], S);
   }
 
   template <int BUF>
   __device__ __forceinline__ void finish(float (&y)[EPT]) {
     const int rp = k < N - 1 ? lrow + 1 : lrow;
     const float* vr = &sm.V[BUF][rp * G::ROW];
-    float vp[NB];
+    float acc[EPT];
+    {
+      const float* tr = &sm.T[BUF][(k > 0 ? lrow - 1 : lrow) * G::ROW];
+      const float keep = k > 0 ? 1.f : 0.f;
+#pragma unroll
+      for (int h = 0; h < G::SUB; ++h) {
+        const float4 u =
+            *reinterpret_cast<const float4*>(tr + 4 * (G::SUB * q + h));
+        acc[3 * h] = keep * u.x;
+        acc[3 * h + 1] = keep * u.y;
+        acc[3 * h + 2] = keep * u.z;
+      }
+    }
 #pragma unroll
     for (int c = 0; c < G::TPR; ++c) {
-      const float4 u = *reinterpret_cast<const float4*>(vr + 4 * (c ^ q));
-      vp[EPT * c] = u.x;
-      vp[EPT * c + 1] = u.y;
-      vp[EPT * c + 2] = u.z;
-    }
-    float4 tp = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (k > 0)
-      tp = *reinterpret_cast<const float4*>(&sm.T[BUF][(lrow - 1) * G::ROW + 4 * q]);
-    const float tv[EPT] = {tp.x, tp.y, tp.z};
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) {
-      float s = tv[e];
+      for (int h = 0; h < G::SUB; ++h) {
+        const float4 u = *reinterpret_cast<const float4*>(
+            vr + 4 * (G::SUB * (c ^ q) + h));
+        const float uc[3] = {u.x, u.y, u.z};
 #pragma unroll
-      for (int x = 0; x < NB; ++x) s = __fmaf_rn(Fr[e][x], vp[x], s);
-      y[e] = -s;
+        for (int e = 0; e < EPT; ++e)
+#pragma unroll
+          for (int z = 0; z < 3; ++z)
+            acc[e] = __fmaf_rn(Fr[e][EPT * c + 3 * h + z], uc[z], acc[e]);
+      }
     }
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) y[e] = -acc[e];
   }
 
   template <int BUF>
@@ -177,9 +234,10 @@ struct Ctx {
   // slot l (one LDS load), slots outside the system are zeroed, a DPP row
   // reduction adds the 16 and lane 0 broadcasts. Fixed tree: deterministic.
   __device__ __forceinline__ double take() {  // after the barrier
-    const int l = threadIdx.x & (NW - 1);
-    AccF v = sm.redF[sf][l];
-    if (!(l >= w0 && l < w1)) v.zero();
+    const int l = threadIdx.x & (MAXW - 1);
+    AccF v;
+    if (l >= w0 && l < w1) v = sm.redF[sf][l];
+    else v.zero();
     v = btk::row16_sum(v);
     sf = (sf + 1) % SL;
     return uni(v.lane(0).value());
@@ -200,7 +258,7 @@ struct Ctx {
     const AccD t = btk::wave_sum(a);
     if ((threadIdx.x & 63) == 0) sm.redD[sd][wave] = t.s;
     __syncthreads();
-    const int l = threadIdx.x & (NW - 1);
+    const int l = threadIdx.x & (MAXW - 1);
     AccD v2;
     v2.s = (l >= w0 && l < w1) ? sm.redD[sd][l] : 0.0;
     v2 = btk::row16_sum(v2);
@@ -223,8 +281,7 @@ struct Ctx {
   // Stage own entries in natural layout for row-wise reads (transforms).
   template <int BUF>
   __device__ __forceinline__ const float* stage_row(const float (&v)[EPT]) {
-    *reinterpret_cast<float4*>(&sm.V[BUF][lrow * G::ROW + 4 * q]) =
-        make_float4(v[0], v[1], v[2], 0.f);
+    put(&sm.V[BUF][lrow * G::ROW], v);
     __syncthreads();
     return &sm.V[BUF][lrow * G::ROW];
   }
@@ -255,12 +312,12 @@ struct Ctx {
   }
 };
 
-template <int NB, int M, typename Rec>
-__global__ void __launch_bounds__(NT) k_fast_ir(SolveArgs a) {
-  using G = Geo<NB>;
+template <int NB, int EPT, int M, typename Rec>
+__global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
+  using G = Geo<NB, EPT>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  Smem<NB>& sm = *reinterpret_cast<Smem<NB>*>(smem_raw);
-  Ctx<NB> c(sm);
+  Smem<NB, EPT>& sm = *reinterpret_cast<Smem<NB, EPT>*>(smem_raw);
+  Ctx<NB, EPT> c(sm);
   const int t = threadIdx.x;
   c.lrow = t / G::TPR;
   c.q = t % G::TPR;
@@ -327,7 +384,7 @@ __global__ void __launch_bounds__(NT) k_fast_ir(SolveArgs a) {
     const int64_t g = sys ? a.off[inst] + c.k : 0;  // global block row
     const int64_t ob = g - inst;                     // its upper block
 
-    // ---- rows 3q..3q+2 of F_k into registers, lane column order ------------
+    // ---- own rows of F_k into registers, lane column order ----------------
     {
       const bool has_next = c.row_ok && c.k < c.N - 1;
       const float keep = has_next ? 1.f : 0.f;
@@ -424,8 +481,7 @@ __global__ void __launch_bounds__(NT) k_fast_ir(SolveArgs a) {
       // inner system  Ahat d = L^{-1} r64  for the systems still running
       float r[EPT], d[EPT], p[EPT], z[EPT], qv[EPT];
       {
-        *reinterpret_cast<float4*>(&sm.V[0][c.lrow * G::ROW + 4 * c.q]) =
-            make_float4(r64f[0], r64f[1], r64f[2], 0.f);
+        c.put(&sm.V[0][c.lrow * G::ROW], r64f);
         c.put_flag(!done);
         __syncthreads();
         if (!c.any_after_barrier()) break;  // every system of the bin is done
@@ -438,7 +494,7 @@ __global__ void __launch_bounds__(NT) k_fast_ir(SolveArgs a) {
             const float* lr = Li + (size_t)g * nn + (size_t)i * NB;
 #pragma unroll
             for (int jj = 0; jj < NB; ++jj)
-              if (jj <= i) acc = __fmaf_rn(lr[jj], rk[4 * (jj / EPT) + jj % EPT], acc);
+              if (jj <= i) acc = __fmaf_rn(lr[jj], rk[spos(jj)], acc);
           }
           r[e] = acc;
           d[e] = 0.f;
@@ -524,7 +580,7 @@ __global__ void __launch_bounds__(NT) k_fast_ir(SolveArgs a) {
 #pragma unroll
               for (int jj = 0; jj < NB; ++jj)
                 if (jj >= i)
-                  acc = __fmaf_rn(lc[(size_t)jj * NB], dk[4 * (jj / EPT) + jj % EPT], acc);
+                  acc = __fmaf_rn(lc[(size_t)jj * NB], dk[spos(jj)], acc);
               sm.xs[c.lrow * NB + i] += (double)acc;
             }
           }
@@ -565,63 +621,91 @@ __global__ void __launch_bounds__(NT) k_fast_ir(SolveArgs a) {
   }
 }
 
-template <int NB, int M, typename Rec>
+template <int NB, int EPT, int M, typename Rec>
 hipError_t launch_one(const SolveArgs& a, int grid, hipStream_t s) {
+  using G = Geo<NB, EPT>;
   static bool attr = false;
   if (!attr) {
     hipError_t e = hipFuncSetAttribute(
-        (const void*)k_fast_ir<NB, M, Rec>,
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(Smem<NB>));
+        (const void*)k_fast_ir<NB, EPT, M, Rec>,
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(Smem<NB, EPT>));
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL((k_fast_ir<NB, M, Rec>), dim3(grid), dim3(NT),
-                     sizeof(Smem<NB>), s, a);
+  hipLaunchKernelGGL((k_fast_ir<NB, EPT, M, Rec>), dim3(grid), dim3(G::NT),
+                     sizeof(Smem<NB, EPT>), s, a);
   return hipGetLastError();
 }
 
-template <int NB, typename Rec>
+template <int NB, int EPT, typename Rec>
 hipError_t launch_rec(const SolveArgs& a, int grid, hipStream_t s) {
   switch (a.m) {
-    case 1: return launch_one<NB, 1, Rec>(a, grid, s);
-    case 2: return launch_one<NB, 2, Rec>(a, grid, s);
-    case 3: return launch_one<NB, 3, Rec>(a, grid, s);
-    default: return launch_one<NB, 4, Rec>(a, grid, s);
+    case 1: return launch_one<NB, EPT, 1, Rec>(a, grid, s);
+    case 2: return launch_one<NB, EPT, 2, Rec>(a, grid, s);
+    case 3: return launch_one<NB, EPT, 3, Rec>(a, grid, s);
+    default: return launch_one<NB, EPT, 4, Rec>(a, grid, s);
   }
 }
 
-template <int NB>
+template <int NB, int EPT>
+hipError_t launch_ept(const SolveArgs& a, int grid, hipStream_t s) {
+  if (a.dtype == BT_DT_F64) return launch_rec<NB, EPT, double>(a, grid, s);
+  return launch_rec<NB, EPT, float>(a, grid, s);
+}
+
+template <int NB, int EPT>
 int max_grid() {
+  using G = Geo<NB, EPT>;
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 256;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
                             dev) != hipSuccess)
     cus = 256;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per, (const void*)k_fast_ir<NB, 2, float>, NT, sizeof(Smem<NB>)) !=
-          hipSuccess ||
+          &per, (const void*)k_fast_ir<NB, EPT, 2, float>, G::NT,
+          sizeof(Smem<NB, EPT>)) != hipSuccess ||
       per < 1)
     per = 1;
   return cus * per;
 }
 
+// entries per lane of each variant (the variant index is the public one)
+constexpr int kEpt[BT_FAST_VARIANTS] = {3, 6, 12};
+
 }  // namespace btf
 
-// The register-resident kernel covers the hot path: block size 12, float32
-// inner iteration with float64 refinement, the optimal weights (1,-1) and
-// polynomial order 1..4.
-bool bt_fast_supported(int n, int prec) { return prec == BT_F32_IR && n == 12; }
+// The register-resident kernel covers block sizes 12 (3, 6 or 12 entries per
+// lane) and 24 (6 entries per lane) with float32 inner iteration and float64
+// refinement, the optimal weights (1,-1) and polynomial order 1..4.
+bool bt_fast_supported(int n, int prec, int v) {
+  if (prec != BT_F32_IR || v < 0 || v >= BT_FAST_VARIANTS) return false;
+  if (n == 12) return true;
+  if (n == 24) return btf::kEpt[v] == 6;
+  return false;
+}
 bool bt_fast_params(const bt_params* p) {
   return p->pc == BT_PC_POLY && p->a == 1.0 && p->m >= 1 && p->m <= 4;
 }
 
-int bt_fast_rows_per_wave(int n) { return btf::Geo<12>::RPW; }
-int bt_fast_rows_per_bin(int n) { return btf::Geo<12>::RPB; }
+int bt_fast_threads(int v) { return 3072 / btf::kEpt[v]; }
+int bt_fast_rows_per_wave(int n, int v) { return 64 / (n / btf::kEpt[v]); }
+int bt_fast_rows_per_bin(int n) { return n == 24 ? 128 : 256; }
 int bt_fast_max_systems_per_bin() { return btf::MAXI; }
 
-hipError_t bt_launch_fast(const SolveArgs& a, int grid, hipStream_t s) {
-  if (a.dtype == BT_DT_F64) return btf::launch_rec<12, double>(a, grid, s);
-  return btf::launch_rec<12, float>(a, grid, s);
+hipError_t bt_launch_fast(const SolveArgs& a, int v, int grid, hipStream_t s) {
+  if (a.n == 24) return btf::launch_ept<24, 6>(a, grid, s);
+  switch (btf::kEpt[v]) {
+    case 3: return btf::launch_ept<12, 3>(a, grid, s);
+    case 6: return btf::launch_ept<12, 6>(a, grid, s);
+    default: return btf::launch_ept<12, 12>(a, grid, s);
+  }
 }
 
-int bt_fast_max_grid(int n) { return btf::max_grid<12>(); }
+int bt_fast_max_grid(int n, int v) {
+  if (n == 24) return btf::max_grid<24, 6>();
+  switch (btf::kEpt[v]) {
+    case 3: return btf::max_grid<12, 3>();
+    case 6: return btf::max_grid<12, 6>();
+    default: return btf::max_grid<12, 12>();
+  }
+}

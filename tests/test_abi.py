@@ -122,9 +122,12 @@ def test_kernel_configs_listed(lib):
     assert precs == {bt.F64, bt.F32}
     for _, nt, s, _ in cfgs:
         assert nt % 64 == 0 and nt <= 1024 and s >= 0
-    # exactly one register-resident bin kernel (s == 0), float32
+    # the register-resident bin kernel variants (s == 0): float32, 3, 6 and
+    # 12 entries per lane, i.e. 1024, 512 and 256 threads, listed last
     fast = [c for c in cfgs if c[2] == 0]
-    assert len(fast) == 1 and fast[0][3] == bt.F32
+    assert [c[1] for c in fast] == [1024, 512, 256]
+    assert all(c[3] == bt.F32 for c in fast)
+    assert [c[0] for c in fast] == list(range(len(cfgs) - 3, len(cfgs)))
 
 
 def test_product_path_has_no_cpu_fallback():

@@ -1,5 +1,5 @@
-"""The register-resident bin kernel (block size 12, float32 inner PCG with
-float64 refinement, optimal weights) against the oracle and against the
+"""The register-resident bin kernel (block sizes 12 and 24, float32 inner PCG
+with float64 refinement, optimal weights) against the oracle and against the
 generic kernel on the same inputs."""
 import numpy as np
 import pytest
@@ -20,8 +20,32 @@ def _gpu(oracle_lib):
     bt.load_library()
 
 
-def fast_index():
-    return [c[0] for c in bt.kernel_configs() if c[2] == 0][0]
+# largest horizon a bin of the register-resident kernel holds, per block size
+BIN_ROWS = {12: 256, 24: 128}
+
+
+def batch(n, B, horizons, seed, record="f32"):
+    """Seeded LQR batch with nu = n / 3; horizons (lo, hi), hi capped at the
+    bin capacity for block size n."""
+    lo, hi = horizons
+    hi = min(hi, BIN_ROWS[n])
+    return lqrgen.lqr_batch(B, (min(lo, hi), hi), n, n // 3, seed=seed,
+                            record=record)
+
+
+def fast_indices():
+    """Configuration index per variant of the register-resident kernel."""
+    return [c[0] for c in bt.kernel_configs() if c[2] == 0]
+
+
+# (block size, variant): 3, 6 or 12 entries per lane for n = 12, 6 for n = 24
+CASES = [(12, 0), (12, 1), (12, 2), (24, 1)]
+CASE_IDS = ["n12-ept3", "n12-ept6", "n12-ept12", "n24-ept6"]
+case_param = pytest.mark.parametrize("n,v", CASES, ids=CASE_IDS)
+
+
+def default_variant(n):
+    return fast_indices()[0 if n == 12 else 1]
 
 
 def run(data, params, record="f32", cfg=None, tol=1e-10, maxit=None):
@@ -33,7 +57,8 @@ def run(data, params, record="f32", cfg=None, tol=1e-10, maxit=None):
         h.set_kernel_config(cfg)
     x, info = h.solve(to_dev(data["b"].reshape(-1), torch.float64), tol, maxit)
     torch.cuda.synchronize()
-    return x.cpu().numpy().reshape(-1, 12), bt.infos_to_numpy(info), h
+    n = data["D"].shape[1]
+    return x.cpu().numpy().reshape(-1, n), bt.infos_to_numpy(info), h
 
 
 def check_against_oracle(data, x, info, every=1, tol=1e-10):
@@ -49,60 +74,84 @@ def check_against_oracle(data, x, info, every=1, tol=1e-10):
         assert rel(x[rows], xd) <= 1e-5, (i, rel(x[rows], xd))
 
 
-def test_fast_kernel_is_selected():
-    data = lqrgen.lqr_batch(8, (16, 40), 12, 4, seed=1, record="f32")
+@pytest.mark.parametrize("n", [12, 24])
+def test_fast_kernel_is_selected(n):
+    data = batch(n, 8, (16, 40), seed=1)
     _, _, h = run(data, bt.Params.polycoeff(2, prec="f32_ir"))
-    assert h.kernel_config() == fast_index()
+    assert h.kernel_config() == default_variant(n)
+    # variants that do not apply to the block size are refused
+    for v, idx in enumerate(fast_indices()):
+        if (n, v) not in CASES:
+            with pytest.raises(bt.BtError):
+                h.set_kernel_config(idx)
 
 
+@case_param
 @pytest.mark.parametrize("m", [1, 2, 3, 4])
-def test_fast_polycoeff_orders(m):
-    data = lqrgen.lqr_batch(48, (16, 256), 12, 4, seed=100 + m, record="f32")
-    x, info, _ = run(data, bt.Params.polycoeff(m, prec="f32_ir"))
+def test_fast_polycoeff_orders(m, n, v):
+    data = batch(n, 48, (16, 256), seed=100 + m)
+    x, info, h = run(data, bt.Params.polycoeff(m, prec="f32_ir"),
+                     cfg=fast_indices()[v])
+    assert h.kernel_config() == fast_indices()[v]
     check_against_oracle(data, x, info, every=4)
 
 
-def test_fast_vs_generic_same_batch():
-    data = lqrgen.lqr_batch(40, (16, 256), 12, 4, seed=7, record="f32")
+@case_param
+def test_fast_vs_generic_same_batch(n, v):
+    data = batch(n, 40, (16, 256), seed=7)
     P = bt.Params.polycoeff(2, prec="f32_ir")
-    xf, inf_f, hf = run(data, P)
-    assert hf.kernel_config() == fast_index()
+    xf, inf_f, hf = run(data, P, cfg=fast_indices()[v])
     generic = [c[0] for c in bt.kernel_configs()
-               if c[3] == bt.F32 and c[2] > 0 and c[1] * c[2] >= 256 * 12][0]
+               if c[3] == bt.F32 and c[2] > 0 and
+               c[1] * c[2] >= BIN_ROWS[n] * n][0]
     xg, inf_g, hg = run(data, P, cfg=generic)
     check_against_oracle(data, xf, inf_f, every=3)
     check_against_oracle(data, xg, inf_g, every=3)
     for i, rows, _ in orc.batch_slices(data["offsets"]):
         assert rel(xf[rows], xg[rows]) <= 1e-6
+    # the fast kernel refuses systems longer than its bins
+    over = lqrgen.lqr_batch(2, BIN_ROWS[n] + 1, n, n // 3, seed=8,
+                            record="f32")
+    _, inf_o, ho = run(over, P)
+    assert ho.kernel_config() not in fast_indices()
+    assert np.all(inf_o["status"] == bt.OK)
+    with pytest.raises(bt.BtError):
+        ho.set_kernel_config(fast_indices()[v])
 
 
-def test_fast_packs_tiny_and_mixed_systems():
+@case_param
+def test_fast_packs_tiny_and_mixed_systems(n, v):
     """Bins holding many short systems next to long ones (ragged tails,
-    horizons 1..20 plus a few of 200..256)."""
-    short = lqrgen.lqr_batch(60, (1, 20), 12, 4, seed=21, record="f32")
-    x, info, _ = run(short, bt.Params.polycoeff(2, prec="f32_ir"))
+    horizons 1..20, and 1 up to the bin capacity)."""
+    short = batch(n, 60, (1, 20), seed=21)
+    cfg = fast_indices()[v]
+    x, info, _ = run(short, bt.Params.polycoeff(2, prec="f32_ir"), cfg=cfg)
     check_against_oracle(short, x, info)
-    mixed = lqrgen.lqr_batch(30, (1, 256), 12, 4, seed=22, record="f32")
-    x, info, _ = run(mixed, bt.Params.polycoeff(2, prec="f32_ir"))
+    mixed = batch(n, 30, (1, 256), seed=22)
+    x, info, _ = run(mixed, bt.Params.polycoeff(2, prec="f32_ir"), cfg=cfg)
     check_against_oracle(mixed, x, info)
 
 
-def test_fast_f64_record():
-    data = lqrgen.lqr_batch(24, (16, 128), 12, 4, seed=5, record="f64")
-    x, info, _ = run(data, bt.Params.polycoeff(2, prec="f32_ir"), record="f64")
+@case_param
+def test_fast_f64_record(n, v):
+    data = batch(n, 24, (16, 128), seed=5, record="f64")
+    x, info, _ = run(data, bt.Params.polycoeff(2, prec="f32_ir"), record="f64",
+                     cfg=fast_indices()[v])
     check_against_oracle(data, x, info)
 
 
-def test_fast_failures_and_zero_rhs():
-    data = lqrgen.lqr_batch(6, (20, 40), 12, 4, seed=9, record="f32")
+@case_param
+def test_fast_failures_and_zero_rhs(n, v):
+    data = batch(n, 6, (20, 40), seed=9)
     D = data["D"].copy()
     r0 = int(data["offsets"][2])
-    D[r0 + 5] = -np.eye(12)                      # system 2, row 5
+    D[r0 + 5] = -np.eye(n)                       # system 2, row 5
     b = data["b"].copy()
     b[int(data["offsets"][3]):int(data["offsets"][4])] = 0.0   # system 3
     b[int(data["offsets"][4]) + 1, 3] = np.inf   # system 4
     d2 = dict(data, D=D, b=b)
-    x, info, _ = run(d2, bt.Params.polycoeff(2, prec="f32_ir"))
+    x, info, _ = run(d2, bt.Params.polycoeff(2, prec="f32_ir"),
+                     cfg=fast_indices()[v])
     assert info[2]["status"] == bt.ENOTSPD and info[2]["fail_index"] == 5
     assert info[3]["status"] == bt.OK and info[3]["iters"] == 0
     assert info[4]["status"] == bt.ENONFINITE
@@ -112,18 +161,21 @@ def test_fast_failures_and_zero_rhs():
     assert not np.any(x[rows3])
 
 
-def test_fast_iteration_cap():
-    data = lqrgen.lqr_batch(4, (100, 120), 12, 4, seed=3, record="f32")
-    x, info, _ = run(data, bt.Params.polycoeff(2, prec="f32_ir"), maxit=7)
+@case_param
+def test_fast_iteration_cap(n, v):
+    data = batch(n, 4, (100, 120), seed=3)
+    x, info, _ = run(data, bt.Params.polycoeff(2, prec="f32_ir"), maxit=7,
+                     cfg=fast_indices()[v])
     assert np.all(info["status"] == bt.NOT_CONVERGED)
     assert np.all(info["iters"] <= 7)
 
 
-def test_fast_deterministic():
-    data = lqrgen.lqr_batch(32, (16, 256), 12, 4, seed=11, record="f32")
+@case_param
+def test_fast_deterministic(n, v):
+    data = batch(n, 32, (16, 256), seed=11)
     P = bt.Params.polycoeff(2, prec="f32_ir")
-    x1, i1, _ = run(data, P)
-    x2, i2, _ = run(data, P)
+    x1, i1, _ = run(data, P, cfg=fast_indices()[v])
+    x2, i2, _ = run(data, P, cfg=fast_indices()[v])
     assert np.array_equal(x1, x2)
     assert np.array_equal(i1["iters"], i2["iters"])
 
