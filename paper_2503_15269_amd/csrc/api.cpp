@@ -157,7 +157,8 @@ void pack_bins(const std::vector<int32_t>& order, const int64_t* off, int rpw,
 
 int hip_status(hipError_t e) { return e == hipSuccess ? BT_OK : BT_EHIP; }
 
-int launch_setup(bt_handle* h, hipStream_t s) {
+// full: also L (read by every kernel but the register-resident one).
+int launch_setup(const bt_handle* h, hipStream_t s, bool full) {
   hipError_t e = bt_launch_setup_init(h->B, h->fail, h->ctr, s);
   if (e != hipSuccess) return BT_EHIP;
   SetupArgs a{};
@@ -171,10 +172,12 @@ int launch_setup(bt_handle* h, hipStream_t s) {
   a.O = h->O;
   a.fail = h->fail;
   a.F = h->F;
-  a.L = h->L;
+  a.L = full ? h->L : nullptr;
   a.Li = h->Li;
   if (a.prec == BT_BF16X2_IR) a.prec = BT_F32_IR;  // float32 factors first
+  h->full_valid = false;
   if (bt_launch_setup(a, s) != hipSuccess) return BT_EHIP;
+  h->full_valid = full;
   if (h->Fhi)
     return hip_status(bt_mrhs_split((const float*)h->F, h->Fhi, h->Flo,
                                     (size_t)h->R * h->n * h->n, s));
@@ -209,6 +212,10 @@ int run(const bt_handle* h, SolveArgs& a, hipStream_t s) {
   int cfg = config_for(h);
   if (is_fast(cfg) && (a.mode != 0 || !a.ir)) cfg = generic_config(h);
   if (cfg < 0) return BT_EINVAL;
+  if (!is_fast(cfg) && !h->full_valid) {  // first use of L
+    const int rc = launch_setup(h, s, true);
+    if (rc != BT_OK) return rc;
+  }
   if (is_fast(cfg)) {
     const int v = cfg - fast_index();
     a.bins = h->bins[v];
@@ -345,7 +352,7 @@ int bt_batch_setup(bt_handle** h, int B, const int64_t* offsets_host, int n,
     delete hh;
     return BT_EHIP;
   }
-  const int rc = launch_setup(hh, s);
+  const int rc = launch_setup(hh, s, !is_fast(config_for(hh)));
   if (rc != BT_OK) {
     delete hh;
     return rc;
@@ -356,7 +363,7 @@ int bt_batch_setup(bt_handle** h, int B, const int64_t* offsets_host, int n,
 
 int bt_refactor(bt_handle* h, void* stream) {
   if (!h) return BT_EINVAL;
-  return launch_setup(h, (hipStream_t)stream);
+  return launch_setup(h, (hipStream_t)stream, !is_fast(config_for(h)));
 }
 
 int bt_setup(bt_handle** h, int N, int n, int dtype, const void* D,

@@ -34,6 +34,9 @@ struct bt_handle {
   unsigned short* Fhi = nullptr;  // BT_BF16X2_IR: F split into bfloat16 pairs
   unsigned short* Flo = nullptr;
   int cfg = -1;             // solve-kernel configuration, -1 = automatic
+  // L is current (the register-resident kernel does not read it; for the
+  // other kernels it is computed on first use)
+  mutable bool full_valid = false;
   std::vector<int64_t> off_host;
 };
 
@@ -64,7 +67,7 @@ struct SolveArgs {
   bt_info* info;
 };
 
-// Arguments of the setup kernel.
+// Arguments of the setup kernel. L or F null: not computed.
 struct SetupArgs {
   int B, n, dtype, prec;
   int64_t R;

@@ -11,6 +11,8 @@
 // The results are stored in the iteration's precision.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "internal.h"
 
 namespace btk {
@@ -102,10 +104,10 @@ __global__ void __launch_bounds__(NT) k_setup(SetupArgs a) {
   trinv_lds<NT>(M0, M1, n);
   for (int e = threadIdx.x; e < nn; e += NT) {
     const int i = e / n, j = e - (e / n) * n;
-    store<T>(a.L, gb + e, j <= i ? M0[e] : 0.0);
+    if (a.L) store<T>(a.L, gb + e, j <= i ? M0[e] : 0.0);
     store<T>(a.Li, gb + e, M1[e]);
   }
-  if (!has_next) return;
+  if (!has_next || !a.F) return;
   __syncthreads();
   for (int e = threadIdx.x; e < nn; e += NT)
     M0[e] = load_rec(a.D, gb + nn + e, a.dtype);
@@ -140,19 +142,105 @@ __device__ __forceinline__ constexpr int tri(int i, int j) {
   return i * (i + 1) / 2 + j;  // packed lower triangle, row-major
 }
 
-// L_g = chol(D_g) and Li_g = L_g^{-1} (in place, row by row), float64.
+// 16-byte vectors of float or double entries (clang vector types, which
+// stay in registers when held in arrays)
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+template <typename S>
+using Vec16 = typename std::conditional<sizeof(S) == 4, f32x4, f64x2>::type;
+
+template <typename D>
+__device__ __forceinline__ void put_chunk(D* dst, const f32x4& v) {
+  dst[0] = (D)v.x;
+  dst[1] = (D)v.y;
+  dst[2] = (D)v.z;
+  dst[3] = (D)v.w;
+}
+template <typename D>
+__device__ __forceinline__ void put_chunk(D* dst, const f64x2& v) {
+  dst[0] = (D)v.x;
+  dst[1] = (D)v.y;
+}
+__device__ __forceinline__ void get_chunk(const float* src, f32x4& v) {
+  v = f32x4{src[0], src[1], src[2], src[3]};
+}
+__device__ __forceinline__ void get_chunk(const double* src, f64x2& v) {
+  v = f64x2{src[0], src[1]};
+}
+
+// Coalesced copies between global memory (blocks of NN entries, contiguous)
+// and LDS (blocks padded to NN + 1 entries, so that lane-per-block reads hit
+// distinct banks). 16-byte global accesses, issued in batches of 16 per lane.
+template <int NN, typename S, typename D>
+__device__ __forceinline__ void stage_in(const S* src, D* lds, int nblk) {
+  constexpr int EPC = 16 / sizeof(S);  // entries per 16-byte chunk
+  constexpr int PER = NN / EPC;        // chunks per lane (64 blocks)
+  constexpr int BAT = 16;
+  static_assert(NN % EPC == 0, "blocks are whole chunks");
+  using V = Vec16<S>;
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int i0 = 0; i0 < PER; i0 += BAT) {
+    V buf[BAT];
+#pragma unroll
+    for (int i = 0; i < BAT; ++i) {
+      const int c = l + 64 * (i0 + i);
+      buf[i] = V{};
+      if (i0 + i < PER && c * EPC < nblk * NN)
+        buf[i] = reinterpret_cast<const V*>(src)[c];
+    }
+#pragma unroll
+    for (int i = 0; i < BAT; ++i) {
+      const int c = l + 64 * (i0 + i);
+      if (i0 + i < PER && c * EPC < nblk * NN) {
+        const int e0 = c * EPC, blk = e0 / NN, off = e0 - blk * NN;
+        put_chunk(lds + blk * (NN + 1) + off, buf[i]);
+      }
+    }
+  }
+}
+
+template <int NN, typename T>
+__device__ __forceinline__ void stage_out(const T* lds, T* dst, int nblk) {
+  constexpr int EPC = 16 / sizeof(T);
+  constexpr int PER = NN / EPC;
+  using V = Vec16<T>;
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int i = 0; i < PER; ++i) {
+    const int c = l + 64 * i;
+    if (c * EPC < nblk * NN) {
+      const int e0 = c * EPC, blk = e0 / NN, off = e0 - blk * NN;
+      V v;
+      get_chunk(lds + blk * (NN + 1) + off, v);
+      reinterpret_cast<V*>(dst)[c] = v;
+    }
+  }
+}
+
+// L_g = chol(D_g) and Li_g = L_g^{-1} (in place, row by row), float64; one
+// lane per block row, a wavefront of 64 consecutive rows per workgroup. The
+// blocks pass through LDS so that global reads and writes are coalesced.
 template <int NB, typename T, typename Rec>
 __global__ void __launch_bounds__(64) k_factor_lane(SetupArgs a) {
-  const int64_t g = (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (g >= a.R) return;
   constexpr int NL = NB * (NB + 1) / 2;
   constexpr int NN = NB * NB;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int64_t g0 = (int64_t)blockIdx.x * 64;
+  const int l = threadIdx.x;
+  const int64_t g = g0 + l;
+  const int nblk = (int)(a.R - g0 < 64 ? a.R - g0 : 64);
+  Rec* din = reinterpret_cast<Rec*>(smem_raw);
+  T* tout = reinterpret_cast<T*>(smem_raw);
+  stage_in<NN>((const Rec*)a.D + (size_t)g0 * NN, din, nblk);
+  __syncthreads();
   double M[NL];
-  const Rec* D = (const Rec*)a.D + (size_t)g * NN;
+  const bool live = g < a.R;
+  const Rec* dl = din + (size_t)(live ? l : 0) * (NN + 1);
 #pragma unroll
   for (int i = 0; i < NB; ++i)
 #pragma unroll
-    for (int j = 0; j <= i; ++j) M[tri<NB>(i, j)] = (double)D[i * NB + j];
+    for (int j = 0; j <= i; ++j) M[tri<NB>(i, j)] = (double)dl[i * NB + j];
   bool ok = true;
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
@@ -174,15 +262,22 @@ __global__ void __launch_bounds__(64) k_factor_lane(SetupArgs a) {
       M[tri<NB>(i, j)] = t * rd;
     }
   }
-  if (!ok) {
+  if (!ok && live) {
     const int inst = find_instance(a.off, a.B, g);
     atomicMin(&a.fail[inst], (int)(g - a.off[inst]));
   }
-  T* L = (T*)a.L + (size_t)g * NN;
+  T* tl = tout + (size_t)l * (NN + 1);
+  __syncthreads();  // every lane has read its D block
+  if (a.L) {
 #pragma unroll
-  for (int i = 0; i < NB; ++i)
+    for (int i = 0; i < NB; ++i)
 #pragma unroll
-    for (int j = 0; j < NB; ++j) L[i * NB + j] = (T)(j <= i ? M[tri<NB>(i, j)] : 0.0);
+      for (int j = 0; j < NB; ++j)
+        tl[i * NB + j] = (T)(j <= i ? M[tri<NB>(i, j)] : 0.0);
+    __syncthreads();
+    stage_out<NN>(tout, (T*)a.L + (size_t)g0 * NN, nblk);
+    __syncthreads();
+  }
   // X = L^{-1}: X[i][j] = -(1/L[i][i]) sum_{k=j}^{i-1} L[i][k] X[k][j];
   // row i overwrites its own L entries in increasing j, each of which is
   // read for the last time by the step that overwrites it.
@@ -198,70 +293,190 @@ __global__ void __launch_bounds__(64) k_factor_lane(SetupArgs a) {
     }
     M[tri<NB>(i, i)] = di;
   }
-  T* Li = (T*)a.Li + (size_t)g * NN;
 #pragma unroll
   for (int i = 0; i < NB; ++i)
 #pragma unroll
-    for (int j = 0; j < NB; ++j) Li[i * NB + j] = (T)(j <= i ? M[tri<NB>(i, j)] : 0.0);
+    for (int j = 0; j < NB; ++j)
+      tl[i * NB + j] = (T)(j <= i ? M[tri<NB>(i, j)] : 0.0);
+  __syncthreads();
+  stage_out<NN>(tout, (T*)a.Li + (size_t)g0 * NN, nblk);
 }
 
-// F_g = Li_g O_g Li_{g+1}^T for rows with a successor; one wavefront per row,
-// operands staged in LDS as float64.
 template <int NB, typename T, typename Rec>
-__global__ void __launch_bounds__(256) k_scaled_offdiag(SetupArgs a) {
-  constexpr int NN = NB * NB;
-  __shared__ double sm[4][4][NN];
+constexpr size_t factor_lds() {
+  return (size_t)64 * (NB * NB + 1) *
+         (sizeof(T) > sizeof(Rec) ? sizeof(T) : sizeof(Rec));
+}
+
+// F_g = Li_g O_g Li_{g+1}^T for the rows g with a successor in their system,
+// zero for the last row of each system. A wavefront covers RPW = 64 / TPR
+// consecutive rows, TPR = NB / 3 lanes per row, lane q forming rows
+// 3q .. 3q+2 of F_g in float64. The wavefront first copies the Li blocks of
+// its rows and the next one (contiguous in memory) and the O blocks of its
+// rows into LDS with coalesced loads; the lanes of a row then read the same
+// LDS words (broadcast).
+template <int NB, typename T>
+struct OffdiagGeo {
+  static constexpr int TPR = NB / 3;
+  static constexpr int RPW = 64 / TPR;
+  static constexpr int NN = NB * NB;
+  static constexpr int WPB = (2 * RPW + 1) * NN * sizeof(T) > 40000 ? 1
+                             : (2 * RPW + 1) * NN * sizeof(T) > 20000 ? 2 : 4;
+  static constexpr size_t LDS = (size_t)WPB * (2 * RPW + 1) * NN * sizeof(T);
+};
+
+template <int NB, typename T, typename Rec>
+__global__ void __launch_bounds__((64 * OffdiagGeo<NB, T>::WPB))
+    k_offdiag_rows(SetupArgs a) {
+  using G = OffdiagGeo<NB, T>;
+  constexpr int NN = G::NN, RPW = G::RPW, TPR = G::TPR;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  __shared__ int64_t obs[G::WPB][RPW];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int64_t g = (int64_t)blockIdx.x * 4 + w;
-  bool valid = g < a.R;
-  int inst = 0;
-  if (valid) {
-    inst = find_instance(a.off, a.B, g);
-    valid = g + 1 < a.off[inst + 1];
+  T* Ls = reinterpret_cast<T*>(smem_raw) + (size_t)w * (2 * RPW + 1) * NN;
+  T* Os = Ls + (size_t)(RPW + 1) * NN;
+  const int64_t g0 = ((int64_t)blockIdx.x * G::WPB + w) * RPW;
+  const int r = l / TPR, q = l % TPR;
+  const int64_t g = g0 + r;
+  bool has_next = false;
+  if (g < a.R) {
+    const int inst = find_instance(a.off, a.B, g);
+    has_next = g + 1 < a.off[inst + 1];
+    if (q == 0) obs[w][r] = has_next ? g - inst : -1;
+  } else if (q == 0) {
+    obs[w][r] = -1;
   }
-  double* Lg = sm[w][0];
-  double* Om = sm[w][1];
-  double* Ln = sm[w][2];
-  double* Tm = sm[w][3];
-  if (valid) {
-    const T* lig = (const T*)a.Li + (size_t)g * NN;
-    const Rec* og = (const Rec*)a.O + (size_t)(g - inst) * NN;
-    for (int e = l; e < NN; e += 64) {
-      Lg[e] = (double)lig[e];
-      Ln[e] = (double)lig[NN + e];
-      Om[e] = (double)og[e];
+  // Li blocks g0 .. g0 + RPW (contiguous), 16-byte loads all issued first
+  {
+    using V = Vec16<T>;
+    constexpr int EPC = 16 / sizeof(T);
+    constexpr int PER = ((RPW + 1) * NN / EPC + 63) / 64;
+    const V* src = reinterpret_cast<const V*>((const T*)a.Li + (size_t)g0 * NN);
+    V buf[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int c = l + 64 * i;
+      buf[i] = V{};
+      if (c < (RPW + 1) * NN / EPC && g0 + (c * EPC) / NN < a.R) buf[i] = src[c];
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int c = l + 64 * i;
+      if (c < (RPW + 1) * NN / EPC) reinterpret_cast<V*>(Ls)[c] = buf[i];
+    }
+  }
+  __syncthreads();  // obs complete
+  {
+    using V = Vec16<Rec>;
+    constexpr int EPC = 16 / sizeof(Rec);
+    constexpr int PER = (RPW * NN / EPC + 63) / 64;
+    const Rec* O = (const Rec*)a.O;
+    V buf[PER];
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int c = l + 64 * i;
+      buf[i] = V{};
+      if (c < RPW * NN / EPC) {
+        const int rr = (c * EPC) / NN, off = c * EPC - rr * NN;
+        const int64_t ob = obs[w][rr];
+        if (ob >= 0)
+          buf[i] = *reinterpret_cast<const V*>(O + (size_t)ob * NN + off);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < PER; ++i) {
+      const int c = l + 64 * i;
+      if (c < RPW * NN / EPC) put_chunk(Os + c * EPC, buf[i]);
     }
   }
   __syncthreads();
-  if (valid) {
-    for (int e = l; e < NN; e += 64) {
-      const int i = e / NB, j = e - (e / NB) * NB;
-      double t = 0.0;
-      for (int p = 0; p <= i; ++p) t += Lg[i * NB + p] * Om[p * NB + j];
-      Tm[e] = t;
+  if (g >= a.R) return;
+  T* F = (T*)a.F + (size_t)g * NN + (size_t)(3 * q) * NB;
+  if (!has_next) {
+#pragma unroll
+    for (int e = 0; e < 3 * NB; ++e) F[e] = (T)0;
+    return;
+  }
+  const T* lk = Ls + (size_t)r * NN;        // Li_g
+  const T* ln = Ls + (size_t)(r + 1) * NN;  // Li_{g+1}
+  const T* ok = Os + (size_t)r * NN;        // O_g
+  double t[3][NB];
+#pragma unroll
+  for (int e = 0; e < 3; ++e)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) t[e][j] = 0.0;
+  // T = (rows 3q..3q+2 of Li_g) O_g; Li_g is zero above the diagonal
+#pragma unroll 2
+  for (int p = 0; p < NB; ++p) {
+    double lp[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) lp[e] = (double)lk[(3 * q + e) * NB + p];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const double o = (double)ok[p * NB + j];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) t[e][j] = fma(lp[e], o, t[e][j]);
     }
   }
-  __syncthreads();
-  if (valid) {
-    T* F = (T*)a.F + (size_t)g * NN;
-    for (int e = l; e < NN; e += 64) {
-      const int i = e / NB, j = e - (e / NB) * NB;
-      double t = 0.0;
-      for (int q = 0; q <= j; ++q) t += Tm[i * NB + q] * Ln[j * NB + q];
-      F[e] = (T)t;
+  // F rows = T Li_{g+1}^T
+#pragma unroll 2
+  for (int j = 0; j < NB; ++j) {
+    double f[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < NB; ++c) {
+      const double lv = (double)ln[j * NB + c];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) f[e] = fma(t[e][c], lv, f[e]);
     }
+#pragma unroll
+    for (int e = 0; e < 3; ++e) F[e * NB + j] = (T)f[e];
   }
+}
+
+template <int NB, typename T, typename Rec>
+hipError_t launch_offdiag(const SetupArgs& a, hipStream_t s) {
+  using G = OffdiagGeo<NB, T>;
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(
+        (const void*)k_offdiag_rows<NB, T, Rec>,
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)G::LDS);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  const int64_t rows_per_block = (int64_t)G::WPB * G::RPW;
+  hipLaunchKernelGGL((k_offdiag_rows<NB, T, Rec>),
+                     dim3((unsigned)((a.R + rows_per_block - 1) / rows_per_block)),
+                     dim3(64 * G::WPB), G::LDS, s, a);
+  return hipGetLastError();
 }
 
 template <int NB, typename T, typename Rec>
 hipError_t launch_lane(const SetupArgs& a, hipStream_t s) {
+  constexpr size_t lds = factor_lds<NB, T, Rec>();
+  static bool attr = false;
+  if (!attr) {
+    hipError_t e = hipFuncSetAttribute(
+        (const void*)k_factor_lane<NB, T, Rec>,
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
   hipLaunchKernelGGL((k_factor_lane<NB, T, Rec>), dim3((a.R + 63) / 64),
-                     dim3(64), 0, s, a);
+                     dim3(64), lds, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_scaled_offdiag<NB, T, Rec>), dim3((a.R + 3) / 4),
-                     dim3(256), 0, s, a);
-  return hipGetLastError();
+  return launch_offdiag<NB, T, Rec>(a, s);
+}
+
+template <int NB>
+hipError_t launch_offdiag_nb(const SetupArgs& a, hipStream_t s) {
+  const bool f64 = a.prec == BT_F64;
+  const bool r64 = a.dtype == BT_DT_F64;
+  if (f64) return r64 ? launch_offdiag<NB, double, double>(a, s)
+                      : launch_offdiag<NB, double, float>(a, s);
+  return r64 ? launch_offdiag<NB, float, double>(a, s)
+             : launch_offdiag<NB, float, float>(a, s);
 }
 
 template <int NB>
@@ -300,10 +515,13 @@ __global__ void __launch_bounds__(256)
 
 }  // namespace btk
 
-hipError_t bt_launch_setup(const SetupArgs& a, hipStream_t s) {
-  if (a.R <= 0) return hipSuccess;
-  if (a.n == 12) return btk::launch_lane_nb<12>(a, s);
-  if (a.n == 6) return btk::launch_lane_nb<6>(a, s);
+hipError_t bt_launch_setup(const SetupArgs& a0, hipStream_t s) {
+  if (a0.R <= 0) return hipSuccess;
+  if (a0.n == 12) return btk::launch_lane_nb<12>(a0, s);
+  if (a0.n == 6) return btk::launch_lane_nb<6>(a0, s);
+  // n = 24: factors by the generic kernel, F by the row-wave kernel
+  SetupArgs a = a0;
+  if (a0.n == 24) a.F = nullptr;
   const size_t sm = 4 * sizeof(double) * (size_t)a.n * a.n;
   const bool f64 = a.prec == BT_F64;
   const bool big = a.n > 16;
@@ -330,7 +548,9 @@ hipError_t bt_launch_setup(const SetupArgs& a, hipStream_t s) {
       hipLaunchKernelGGL((btk::k_setup<64, float>), dim3(a.R), dim3(64), sm, s,
                          a);
   }
-  return hipGetLastError();
+  e = hipGetLastError();
+  if (e != hipSuccess || a0.n != 24) return e;
+  return btk::launch_offdiag_nb<24>(a0, s);
 }
 
 hipError_t bt_launch_setup_init(int B, int32_t* fail, int32_t* ctr,

@@ -202,3 +202,46 @@ def test_autotune_picks_a_converging_config(tmp_path, monkeypatch):
     torch.cuda.synchronize()
     inf = bt.infos_to_numpy(info)
     assert np.all(inf["status"] == bt.OK) and np.all(inf["relres_true"] <= 1e-10)
+
+
+def test_factors_for_other_kernels_formed_on_first_use():
+    """A handle set up for the register-resident kernel forms the Cholesky
+    factors L (which only the other kernels read) when a solve, a
+    preconditioner application or a refactor first needs them; in-place
+    changes of D are picked up."""
+    import torch
+    data = batch(12, 10, (16, 200), seed=31)
+    P = bt.Params.polycoeff(2, prec="f32_ir")
+    Dt = to_dev(data["D"], torch.float32)
+    Ot = to_dev(data["O"], torch.float32)
+    b = to_dev(data["b"].reshape(-1), torch.float64)
+    h = bt.Handle(Dt, Ot, data["offsets"], P)
+    assert h.kernel_config() == fast_indices()[0]
+    generic = [c[0] for c in bt.kernel_configs()
+               if c[3] == bt.F32 and c[2] > 0 and c[1] * c[2] >= 200 * 12][0]
+
+    def solve_check(dat):
+        x, info = h.solve(b, 1e-10)
+        torch.cuda.synchronize()
+        check_against_oracle(dat, x.cpu().numpy().reshape(-1, 12),
+                             bt.infos_to_numpy(info), every=2)
+        return x
+
+    solve_check(data)                      # fast kernel, no L
+    z = h.precondition(b)                  # generic kernel: forms L
+    assert torch.isfinite(z).all()
+    h.set_kernel_config(generic)
+    solve_check(data)
+    # change D in place: refactor (generic config: L and F as well)
+    Dt.mul_(2.0)                           # exact in float32
+    d2 = dict(data, D=data["D"] * 2.0)
+    h.refactor()
+    solve_check(d2)
+    h.set_kernel_config(fast_indices()[0])
+    solve_check(d2)
+    # and back to the generic kernel after a refactor made for the fast one
+    Dt.mul_(2.0)
+    d3 = dict(data, D=data["D"] * 4.0)
+    h.refactor()
+    h.set_kernel_config(generic)
+    solve_check(d3)
