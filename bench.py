@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--inner-tol", type=float, default=None,
                     help="inner tolerance of the refinement (default: the "
                          "autotuned value)")
+    ap.add_argument("--kernel-config", type=int, default=None,
+                    help="solve-kernel configuration (default: autotuned, or "
+                         "the library's choice with --inner-tol / --no-tune)")
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the secondary measurements of the other "
                          "standard workloads")
@@ -71,30 +74,31 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(inner_tol):
+def measured_traffic(inner_tol, kernel_config):
     """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, or None when the kernel's sources (or the inner tolerance, which
-    sets the number of refinement passes) differ from the measured run."""
+    summary, or None when the kernel's sources differ from the measured run
+    or no measurement matches the inner tolerance (which sets the number of
+    refinement passes) and kernel configuration of this run. The summary
+    lists one line per measured pair:
+    ``- hbm_bytes_per_launch[inner_tol=3e-06,kernel_config=13]: 123``."""
+    import re
     path = os.path.join(ROOT, TRAFFIC_FILE)
     if not os.path.exists(path):
         return None
-    vals = {}
+    src, found = None, {}
+    pat = re.compile(r"- hbm_bytes_per_launch\[inner_tol=([^,\]]+),"
+                     r"kernel_config=(\d+)\]:\s*`?([0-9.eE+]+)")
     with open(path) as fh:
         for line in fh:
-            if ":" in line and line.strip().startswith("- "):
-                k, v = line.strip()[2:].split(":", 1)
-                vals[k.strip()] = v.strip().strip("`")
-    if vals.get("kernel_source_sha256") != kernel_source_hash():
+            line = line.strip()
+            if line.startswith("- kernel_source_sha256:"):
+                src = line.split(":", 1)[1].strip().strip("`")
+            m = pat.match(line)
+            if m:
+                found[(float(m.group(1)), int(m.group(2)))] = float(m.group(3))
+    if src != kernel_source_hash():
         return None
-    try:
-        if float(vals.get("inner_tol", "nan")) != float(inner_tol):
-            return None
-    except ValueError:
-        return None
-    try:
-        return float(vals["hbm_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+    return found.get((float(inner_tol), int(kernel_config)))
 
 
 def copy_probe(mib):
@@ -361,7 +365,8 @@ def main():
                                  max_outer=30)
     tol = 1e-10
     tuned = None
-    if not args.no_tune and args.inner_tol is None:
+    if (not args.no_tune and args.inner_tol is None and
+            args.kernel_config is None):
         from paper_2503_15269_amd import autotune
         tuned = autotune.tune(D, O, data["offsets"], b, params, tol, reps=3,
                               use_cache=False)
@@ -369,6 +374,8 @@ def main():
     h = bt.Handle(D, O, data["offsets"], params)
     if tuned is not None:
         h.set_kernel_config(tuned["kernel_config"])
+    elif args.kernel_config is not None:
+        h.set_kernel_config(args.kernel_config)
     x = torch.empty_like(b)
     info = torch.empty(B * bt.INFO_DTYPE.itemsize, dtype=torch.uint8,
                        device=dev)
@@ -492,7 +499,8 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved_tf,
                      "peak": PEAK_FP32_VALU_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tf / PEAK_FP32_VALU_TFLOPS,
-                     "traffic": measured_traffic(params.inner_tol)},
+                     "traffic": measured_traffic(params.inner_tol,
+                                                 h.kernel_config())},
         "cpu_baseline": cpu,
         "extra": {
             "solve_kernel_ms": solve_ms,

@@ -59,7 +59,8 @@ int64_t check_offsets(int B, const int64_t* off, int* maxN) {
 }
 
 struct Layout {
-  size_t off, order, ctr, fail, bins, items, F, L, Li, Fhi, Flo, total;
+  size_t off, order, rowinst, ctr, fail, bins, items, F, L, Li, Fhi, Flo,
+      total;
 };
 
 Layout layout(int B, int64_t R, int n, size_t es, bool split) {
@@ -67,6 +68,7 @@ Layout layout(int B, int64_t R, int n, size_t es, bool split) {
   size_t at = 0;
   l.off = at; at += align_up(sizeof(int64_t) * (B + 1));
   l.order = at; at += align_up(sizeof(int32_t) * B);
+  l.rowinst = at; at += align_up(sizeof(int32_t) * (size_t)R);
   l.ctr = at; at += align_up(sizeof(int32_t) * 64);
   l.fail = at; at += align_up(sizeof(int32_t) * B);
   l.bins = at; at += BT_FAST_VARIANTS * align_up(sizeof(int32_t) * 2 * B);
@@ -168,6 +170,7 @@ int launch_setup(const bt_handle* h, hipStream_t s, bool full) {
   a.prec = h->p.prec;
   a.R = h->R;
   a.off = h->off;
+  a.rowinst = h->rowinst;
   a.D = h->D;
   a.O = h->O;
   a.fail = h->fail;
@@ -302,6 +305,7 @@ int bt_batch_setup(bt_handle** h, int B, const int64_t* offsets_host, int n,
   unsigned char* w = (unsigned char*)workspace;
   hh->off = (int64_t*)(w + l.off);
   hh->order = (int32_t*)(w + l.order);
+  hh->rowinst = (int32_t*)(w + l.rowinst);
   hh->ctr = (int32_t*)(w + l.ctr);
   hh->fail = (int32_t*)(w + l.fail);
   for (int v = 0; v < BT_FAST_VARIANTS; ++v) {
@@ -335,10 +339,16 @@ int bt_batch_setup(bt_handle** h, int B, const int64_t* offsets_host, int n,
     }
   }
   hipStream_t s = (hipStream_t)stream;
+  std::vector<int32_t> rowinst((size_t)R);
+  for (int i = 0; i < B; ++i)
+    for (int64_t g = offsets_host[i]; g < offsets_host[i + 1]; ++g)
+      rowinst[(size_t)g] = i;
   bool ok =
       hipMemcpyAsync(hh->off, hh->off_host.data(), sizeof(int64_t) * (B + 1),
                      hipMemcpyHostToDevice, s) == hipSuccess &&
       hipMemcpyAsync(hh->order, order.data(), sizeof(int32_t) * B,
+                     hipMemcpyHostToDevice, s) == hipSuccess &&
+      hipMemcpyAsync(hh->rowinst, rowinst.data(), sizeof(int32_t) * R,
                      hipMemcpyHostToDevice, s) == hipSuccess;
   for (int v = 0; v < BT_FAST_VARIANTS && ok; ++v)
     if (hh->nbins[v] > 0)
@@ -415,7 +425,8 @@ int bt_solve_adjoint(const bt_handle* h, const double* x, const double* g,
   int rc = bt_solve(h, g, lambda, tol, maxit, info, stream);
   if (rc != BT_OK) return rc;
   if (!dD && !dO) return BT_OK;
-  return hip_status(bt_launch_adjoint_outer(h->B, h->n, h->R, h->off, x,
+  return hip_status(bt_launch_adjoint_outer(h->B, h->n, h->R, h->off,
+                                            h->rowinst, x,
                                             lambda, dD, dO,
                                             (hipStream_t)stream));
 }

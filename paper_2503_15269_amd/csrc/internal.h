@@ -21,6 +21,7 @@ struct bt_handle {
   const void* O = nullptr;
   int64_t* off = nullptr;   // [B+1] row offsets
   int32_t* order = nullptr; // [B] instances, longest first
+  int32_t* rowinst = nullptr;  // [R] instance of each block row
   int32_t* ctr = nullptr;   // [64] queue counters of the persistent kernels
   int32_t* fail = nullptr;  // [B] first failing block row, BT_NO_FAIL if none
   // bins of the register-resident kernel, per variant: [B][2] (start, count)
@@ -72,6 +73,7 @@ struct SetupArgs {
   int B, n, dtype, prec;
   int64_t R;
   const int64_t* off;
+  const int32_t* rowinst;  // [R] instance of each block row
   const void* D;
   const void* O;
   int32_t* fail;
@@ -111,6 +113,7 @@ int bt_mrhs_run(int64_t R, int n, int nrhs, const unsigned short* Fhi,
                 double tol, int maxit, int max_outer, double inner_tol, int m,
                 double alpha1, void* scratch, bt_info* info, hipStream_t s);
 hipError_t bt_launch_adjoint_outer(int B, int n, int64_t R,
-                                   const int64_t* off, const double* x,
+                                   const int64_t* off, const int32_t* rowinst,
+                                   const double* x,
                                    const double* lam, double* dD, double* dO,
                                    hipStream_t s);

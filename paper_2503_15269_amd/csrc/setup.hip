@@ -23,17 +23,6 @@ __device__ __forceinline__ double load_rec(const void* P, size_t i,
                             : (double)((const float*)P)[i];
 }
 
-__device__ __forceinline__ int find_instance(const int64_t* off, int B,
-                                             int64_t g) {
-  int lo = 0, hi = B;  // off[lo] <= g < off[hi]
-  while (hi - lo > 1) {
-    int mid = (lo + hi) >> 1;
-    if (off[mid] <= g) lo = mid;
-    else hi = mid;
-  }
-  return lo;
-}
-
 // In-place Cholesky of the n x n matrix M (row-major, LDS); lower triangle
 // receives L. Returns false (uniformly) if a pivot is not positive.
 template <int NT>
@@ -87,7 +76,7 @@ __global__ void __launch_bounds__(NT) k_setup(SetupArgs a) {
   const int n = a.n;
   const int nn = n * n;
   const int64_t g = blockIdx.x;
-  const int inst = find_instance(a.off, a.B, g);
+  const int inst = a.rowinst[g];
   const int64_t r1 = a.off[inst + 1];
   const bool has_next = g + 1 < r1;
   double* M0 = sm;
@@ -263,7 +252,7 @@ __global__ void __launch_bounds__(64) k_factor_lane(SetupArgs a) {
     }
   }
   if (!ok && live) {
-    const int inst = find_instance(a.off, a.B, g);
+    const int inst = a.rowinst[g];
     atomicMin(&a.fail[inst], (int)(g - a.off[inst]));
   }
   T* tl = tout + (size_t)l * (NN + 1);
@@ -311,10 +300,12 @@ constexpr size_t factor_lds() {
 // F_g = Li_g O_g Li_{g+1}^T for the rows g with a successor in their system,
 // zero for the last row of each system. A wavefront covers RPW = 64 / TPR
 // consecutive rows, TPR = NB / 3 lanes per row, lane q forming rows
-// 3q .. 3q+2 of F_g in float64. The wavefront first copies the Li blocks of
-// its rows and the next one (contiguous in memory) and the O blocks of its
-// rows into LDS with coalesced loads; the lanes of a row then read the same
-// LDS words (broadcast).
+// 3q .. 3q+2 of F_g in float64. The Li blocks of the wavefront's rows and the
+// next one are contiguous in memory, and so are their O blocks (the upper
+// block of row g is number g - i for instance i, and the last row of an
+// instance has none): both ranges go to LDS with coalesced 16-byte loads,
+// the lanes of a row then read the same LDS words (broadcast), and the F
+// blocks return through LDS for coalesced stores.
 template <int NB, typename T>
 struct OffdiagGeo {
   static constexpr int TPR = NB / 3;
@@ -331,105 +322,119 @@ __global__ void __launch_bounds__((64 * OffdiagGeo<NB, T>::WPB))
   using G = OffdiagGeo<NB, T>;
   constexpr int NN = G::NN, RPW = G::RPW, TPR = G::TPR;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  __shared__ int64_t obs[G::WPB][RPW];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   T* Ls = reinterpret_cast<T*>(smem_raw) + (size_t)w * (2 * RPW + 1) * NN;
   T* Os = Ls + (size_t)(RPW + 1) * NN;
   const int64_t g0 = ((int64_t)blockIdx.x * G::WPB + w) * RPW;
   const int r = l / TPR, q = l % TPR;
   const int64_t g = g0 + r;
-  bool has_next = false;
-  if (g < a.R) {
-    const int inst = find_instance(a.off, a.B, g);
-    has_next = g + 1 < a.off[inst + 1];
-    if (q == 0) obs[w][r] = has_next ? g - inst : -1;
-  } else if (q == 0) {
-    obs[w][r] = -1;
+  const int64_t nO = a.R - a.B;  // upper blocks in all
+  const int64_t ob0 = g0 < a.R ? g0 - a.rowinst[g0] : 0;
+  // Li blocks g0 .. g0 + RPW and O blocks ob0 .. ob0 + RPW - 1, all loads of
+  // a lane issued before any LDS store
+  {
+    using V = Vec16<T>;
+    using W = Vec16<Rec>;
+    constexpr int EPC = 16 / sizeof(T), EPR = 16 / sizeof(Rec);
+    constexpr int CL = (RPW + 1) * NN / EPC, CO = RPW * NN / EPR;
+    constexpr int PL = (CL + 63) / 64, PO = (CO + 63) / 64;
+    const V* srcl = reinterpret_cast<const V*>((const T*)a.Li + (size_t)g0 * NN);
+    const W* srco = reinterpret_cast<const W*>((const Rec*)a.O + (size_t)ob0 * NN);
+    V bl[PL];
+    W bo[PO];
+#pragma unroll
+    for (int i = 0; i < PL; ++i) {
+      const int c = l + 64 * i;
+      bl[i] = V{};
+      if (c < CL && g0 + (c * EPC) / NN < a.R) bl[i] = srcl[c];
+    }
+#pragma unroll
+    for (int i = 0; i < PO; ++i) {
+      const int c = l + 64 * i;
+      bo[i] = W{};
+      if (c < CO && ob0 + (c * EPR) / NN < nO) bo[i] = srco[c];
+    }
+#pragma unroll
+    for (int i = 0; i < PL; ++i) {
+      const int c = l + 64 * i;
+      if (c < CL) reinterpret_cast<V*>(Ls)[c] = bl[i];
+    }
+#pragma unroll
+    for (int i = 0; i < PO; ++i) {
+      const int c = l + 64 * i;
+      if (c < CO) put_chunk(Os + c * EPR, bo[i]);
+    }
   }
-  // Li blocks g0 .. g0 + RPW (contiguous), 16-byte loads all issued first
+  bool has_next = false;
+  int lo = 0;  // position of this row's O block in the staged range
+  if (g < a.R) {
+    const int inst = a.rowinst[g];
+    has_next = g + 1 < a.off[inst + 1];
+    lo = has_next ? (int)(g - inst - ob0) : 0;
+  }
+  __syncthreads();
+  T f[3][NB];
+  if (has_next) {
+    const T* lk = Ls + (size_t)r * NN;        // Li_g
+    const T* ln = Ls + (size_t)(r + 1) * NN;  // Li_{g+1}
+    const T* ok = Os + (size_t)lo * NN;       // O_g
+    double t[3][NB];
+#pragma unroll
+    for (int e = 0; e < 3; ++e)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) t[e][j] = 0.0;
+    // T = (rows 3q..3q+2 of Li_g) O_g; Li_g is zero above the diagonal
+#pragma unroll 2
+    for (int p = 0; p < NB; ++p) {
+      double lp[3];
+#pragma unroll
+      for (int e = 0; e < 3; ++e) lp[e] = (double)lk[(3 * q + e) * NB + p];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        const double o = (double)ok[p * NB + j];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) t[e][j] = fma(lp[e], o, t[e][j]);
+      }
+    }
+    // F rows = T Li_{g+1}^T
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      double s3[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        const double lv = (double)ln[j * NB + c];
+#pragma unroll
+        for (int e = 0; e < 3; ++e) s3[e] = fma(t[e][c], lv, s3[e]);
+      }
+#pragma unroll
+      for (int e = 0; e < 3; ++e) f[e][j] = (T)s3[e];
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 3; ++e)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) f[e][j] = (T)0;
+  }
+  __syncthreads();  // every lane is done reading the staged O blocks
+  {
+    T* fo = Os + (size_t)r * NN + (size_t)(3 * q) * NB;
+#pragma unroll
+    for (int e = 0; e < 3; ++e)
+#pragma unroll
+      for (int j = 0; j < NB; ++j) fo[e * NB + j] = f[e][j];
+  }
+  __syncthreads();
   {
     using V = Vec16<T>;
     constexpr int EPC = 16 / sizeof(T);
-    constexpr int PER = ((RPW + 1) * NN / EPC + 63) / 64;
-    const V* src = reinterpret_cast<const V*>((const T*)a.Li + (size_t)g0 * NN);
-    V buf[PER];
+    constexpr int CF = RPW * NN / EPC;
+    V* dst = reinterpret_cast<V*>((T*)a.F + (size_t)g0 * NN);
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
+    for (int i = 0; i < (CF + 63) / 64; ++i) {
       const int c = l + 64 * i;
-      buf[i] = V{};
-      if (c < (RPW + 1) * NN / EPC && g0 + (c * EPC) / NN < a.R) buf[i] = src[c];
+      if (c < CF && g0 + (c * EPC) / NN < a.R)
+        dst[c] = reinterpret_cast<const V*>(Os)[c];
     }
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int c = l + 64 * i;
-      if (c < (RPW + 1) * NN / EPC) reinterpret_cast<V*>(Ls)[c] = buf[i];
-    }
-  }
-  __syncthreads();  // obs complete
-  {
-    using V = Vec16<Rec>;
-    constexpr int EPC = 16 / sizeof(Rec);
-    constexpr int PER = (RPW * NN / EPC + 63) / 64;
-    const Rec* O = (const Rec*)a.O;
-    V buf[PER];
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int c = l + 64 * i;
-      buf[i] = V{};
-      if (c < RPW * NN / EPC) {
-        const int rr = (c * EPC) / NN, off = c * EPC - rr * NN;
-        const int64_t ob = obs[w][rr];
-        if (ob >= 0)
-          buf[i] = *reinterpret_cast<const V*>(O + (size_t)ob * NN + off);
-      }
-    }
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      const int c = l + 64 * i;
-      if (c < RPW * NN / EPC) put_chunk(Os + c * EPC, buf[i]);
-    }
-  }
-  __syncthreads();
-  if (g >= a.R) return;
-  T* F = (T*)a.F + (size_t)g * NN + (size_t)(3 * q) * NB;
-  if (!has_next) {
-#pragma unroll
-    for (int e = 0; e < 3 * NB; ++e) F[e] = (T)0;
-    return;
-  }
-  const T* lk = Ls + (size_t)r * NN;        // Li_g
-  const T* ln = Ls + (size_t)(r + 1) * NN;  // Li_{g+1}
-  const T* ok = Os + (size_t)r * NN;        // O_g
-  double t[3][NB];
-#pragma unroll
-  for (int e = 0; e < 3; ++e)
-#pragma unroll
-    for (int j = 0; j < NB; ++j) t[e][j] = 0.0;
-  // T = (rows 3q..3q+2 of Li_g) O_g; Li_g is zero above the diagonal
-#pragma unroll 2
-  for (int p = 0; p < NB; ++p) {
-    double lp[3];
-#pragma unroll
-    for (int e = 0; e < 3; ++e) lp[e] = (double)lk[(3 * q + e) * NB + p];
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      const double o = (double)ok[p * NB + j];
-#pragma unroll
-      for (int e = 0; e < 3; ++e) t[e][j] = fma(lp[e], o, t[e][j]);
-    }
-  }
-  // F rows = T Li_{g+1}^T
-#pragma unroll 2
-  for (int j = 0; j < NB; ++j) {
-    double f[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-    for (int c = 0; c < NB; ++c) {
-      const double lv = (double)ln[j * NB + c];
-#pragma unroll
-      for (int e = 0; e < 3; ++e) f[e] = fma(t[e][c], lv, f[e]);
-    }
-#pragma unroll
-    for (int e = 0; e < 3; ++e) F[e * NB + j] = (T)f[e];
   }
 }
 
@@ -497,10 +502,11 @@ __global__ void k_setup_init(int B, int32_t* fail, int32_t* ctr) {
 
 // dD_g = -lambda_g x_g^T ; dO_(g-i) = -(lambda_g x_{g+1}^T + x_g lambda_{g+1}^T)
 __global__ void __launch_bounds__(256)
-    k_adjoint_outer(int B, int n, const int64_t* off, const double* x,
-                    const double* lam, double* dD, double* dO) {
+    k_adjoint_outer(int B, int n, const int64_t* off, const int32_t* rowinst,
+                    const double* x, const double* lam, double* dD,
+                    double* dO) {
   const int64_t g = blockIdx.x;
-  const int inst = find_instance(off, B, g);
+  const int inst = rowinst[g];
   const bool has_next = g + 1 < off[inst + 1];
   const int nn = n * n;
   const double* xg = x + g * n;
@@ -562,10 +568,11 @@ hipError_t bt_launch_setup_init(int B, int32_t* fail, int32_t* ctr,
 }
 
 hipError_t bt_launch_adjoint_outer(int B, int n, int64_t R, const int64_t* off,
-                                   const double* x, const double* lam,
-                                   double* dD, double* dO, hipStream_t s) {
+                                   const int32_t* rowinst, const double* x,
+                                   const double* lam, double* dD, double* dO,
+                                   hipStream_t s) {
   if (R <= 0) return hipSuccess;
   hipLaunchKernelGGL(btk::k_adjoint_outer, dim3(R), dim3(256), 0, s, B, n, off,
-                     x, lam, dD, dO);
+                     rowinst, x, lam, dD, dO);
   return hipGetLastError();
 }
