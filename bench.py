@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--kernel-config", type=int, default=None,
                     help="solve-kernel configuration (default: autotuned, or "
                          "the library's choice with --inner-tol / --no-tune)")
+    ap.add_argument("--only", choices=SECONDARY, default=None,
+                    help="run only the measurement of this other standard "
+                         "workload and print its figures (for profiling)")
     ap.add_argument("--no-workloads", action="store_true",
                     help="skip the secondary measurements of the other "
                          "standard workloads")
@@ -183,7 +186,10 @@ def _graph_ms(fn, reps, warmup=3):
     return _events_ms(g.replay, reps, warmup)
 
 
-def workloads_secondary(bt, torch, dev):
+SECONDARY = ("single_n6", "single_n12", "batch_grad_n24", "multirhs_n48")
+
+
+def workloads_secondary(bt, torch, dev, only=SECONDARY):
     """Solve rates and counts on the other standard workloads (a single
     N = 32 and N = 512 system, the n = 24 differentiable batch, the n = 48
     system with 64 right-hand sides). Each figure is setup + solve unless
@@ -206,6 +212,8 @@ def workloads_secondary(bt, torch, dev):
                 ("block_jacobi_m2", bt.Params.block_jacobi(2)),
                 ("none", bt.Params(pc="none"))]
     for name in ("single_n6", "single_n12"):
+        if name not in only:
+            continue
         w, d = one(name)
         D = torch.tensor(d["D"], dtype=torch.float64, device=dev)
         O = torch.tensor(d["O"], dtype=torch.float64, device=dev)
@@ -235,7 +243,15 @@ def workloads_secondary(bt, torch, dev):
                     "relres_true": float(inf["relres_true"])}
         res[name] = rows
 
-    # differentiable batch: forward solve + adjoint (dL/db, dL/dD, dL/dO)
+    if "batch_grad_n24" in only:
+        res["batch_grad_n24"] = _grad_n24(bt, torch, dev, tol)
+    if "multirhs_n48" in only:
+        res["multirhs_n48"] = _multirhs_n48(bt, torch, dev, tol, one)
+    return res
+
+
+def _grad_n24(bt, torch, dev, tol):
+    """Differentiable batch: forward solve + adjoint (dL/db, dL/dD, dL/dO)."""
     w = lqrgen.WORKLOADS["batch_grad_n24"]
     d = lqrgen.lqr_batch(w["B"], w["N"], w["nx"], w["nu"],
                          lqrgen.workload_seed(w["index"]), s=w["s"],
@@ -268,7 +284,7 @@ def workloads_secondary(bt, torch, dev):
     fwd_ms = _events_ms(fwd, 10)
     adj_ms = _events_ms(adj, 10)
     fa_ms = _events_ms(lambda: (fwd(), adj()), 10)
-    res["batch_grad_n24"] = {
+    return {
         "fwd_adj_ms": fa_ms, "fwd_ms": fwd_ms, "adj_ms": adj_ms,
         "inner_tol": tuned["params"].inner_tol,
         "kernel_config": tuned["kernel_config"],
@@ -277,7 +293,10 @@ def workloads_secondary(bt, torch, dev):
         "relres_true_max": float(max(fi["relres_true"].max(),
                                      ai["relres_true"].max()))}
 
-    # one system, 64 right-hand sides, BF16 split blocks on the matrix cores
+
+def _multirhs_n48(bt, torch, dev, tol, one):
+    """One system, 64 right-hand sides, BF16 split blocks on the matrix
+    cores, float64 refinement."""
     w, d = one("multirhs_n48")
     Dd = d["D"].astype(np.float32)
     Od = d["O"].astype(np.float32)
@@ -291,12 +310,11 @@ def workloads_secondary(bt, torch, dev):
     mi = bt.infos_to_numpy(minfo)
     assert np.all(mi["status"] == bt.OK)
     mr_ms = _events_ms(lambda: (h.refactor(), h.solve_mrhs(Bm, tol, X=X)), 5)
-    res["multirhs_n48"] = {
+    return {
         "ms": mr_ms, "rhs_solves_per_s": w["nrhs"] * 1e3 / mr_ms,
         "iters_mean": float(mi["iters"].mean()),
         "outer_mean": float(mi["outer"].mean()),
         "relres_true_max": float(mi["relres_true"].max())}
-    return res
 
 
 def cpu_baseline(data, budget_s, cores):
@@ -339,6 +357,13 @@ def main():
     args = parse()
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.only:
+        import torch
+        import paper_2503_15269_amd as bt
+        res = workloads_secondary(bt, torch, torch.device("cuda:0"),
+                                  only=(args.only,))
+        print(json.dumps({"workload": args.only, **res}), flush=True)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on exactly one GPU; "

@@ -245,3 +245,51 @@ def test_factors_for_other_kernels_formed_on_first_use():
     h.refactor()
     h.set_kernel_config(generic)
     solve_check(d3)
+
+
+@pytest.mark.parametrize("which", ["fast", "generic"])
+def test_graph_replays_match_eager(which):
+    """refactor + solve captured into one HIP graph: every replay (with other
+    GPU work in between) reproduces the eager result bit for bit, and picks
+    up new contents of the input buffers (b scaled by 2 scales x exactly)."""
+    import torch
+    data = batch(12, 24, (16, 200), seed=41)
+    P = bt.Params.polycoeff(2, prec="f32_ir")
+    D = to_dev(data["D"], torch.float32)
+    O = to_dev(data["O"], torch.float32)
+    b = to_dev(data["b"].reshape(-1), torch.float64)
+    h = bt.Handle(D, O, data["offsets"], P)
+    if which == "generic":
+        h.set_kernel_config([c[0] for c in bt.kernel_configs()
+                             if c[3] == bt.F32 and c[2] > 0 and
+                             c[1] * c[2] >= 200 * 12][0])
+    else:
+        assert h.kernel_config() in fast_indices()
+    x = torch.empty_like(b)
+    info = torch.empty((len(data["offsets"]) - 1) * bt.INFO_DTYPE.itemsize,
+                       dtype=torch.uint8, device="cuda")
+    h.refactor()
+    h.solve(b, 1e-10, x=x, info=info)
+    torch.cuda.synchronize()
+    x_ref, info_ref = x.clone(), info.clone()
+    assert np.all(bt.infos_to_numpy(info)["status"] == bt.OK)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        h.refactor()
+        h.solve(b, 1e-10, x=x, info=info)
+    for rep in range(3):
+        x.zero_()
+        info.zero_()
+        junk = torch.randn(1 << 20, device="cuda").sum()   # other work
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.isfinite(junk)
+        assert torch.equal(x, x_ref), rep
+        assert torch.equal(info, info_ref), rep
+    b.mul_(2.0)
+    g.replay()
+    torch.cuda.synchronize()
+    assert torch.equal(x, 2.0 * x_ref)
+    i2, i1 = bt.infos_to_numpy(info), bt.infos_to_numpy(info_ref)
+    assert np.array_equal(i2["iters"], i1["iters"])
