@@ -90,6 +90,9 @@ __global__ void __launch_bounds__(WG) k_mr_app(MrArgs a, const float* V,
   const int kq = 4 * (l >> 4);                 // k-offset of this lane
   const bool has_prev = k > 0, has_next = k < a.R - 1;
   const size_t nn = (size_t)NB * NB;
+  // nothing to do once every column of this workgroup has stopped (the host
+  // only checks every few iterations)
+  if (!__syncthreads_or(a.act[blockIdx.y * CPB + (t & 63)])) return;
   for (int e = t; e < NB * NB; e += WG) {
     if (has_next) {
       sFk[0][e] = a.Fhi[(size_t)k * nn + e];
@@ -318,80 +321,127 @@ __global__ void k_mr_init_cols(MrArgs a) {
   }
 }
 
-__device__ __forceinline__ double rec(const void* P, size_t i, int dtype) {
-  return dtype == BT_DT_F64 ? ((const double*)P)[i]
-                            : (double)((const float*)P)[i];
-}
+// Panel kernels of the refinement, one workgroup per (block row, 64
+// columns): wavefront w takes the rows w, w + 4, ..., lane l the column
+// 64 blockIdx.y + l; the n x n blocks sit in LDS and are read as broadcasts,
+// the panels are read and written with consecutive lanes on consecutive
+// columns.
 
-// r64 = b - A x in float64 (x = 0 on the first pass: r64 = b); its squared
-// column norms go to part; r = L^{-1} r64 (float) is formed by k_mr_tohat.
-// One workgroup per block row, threads over (i, c).
+// r64 = b - A x in float64 (x = 0 on the first pass: r64 = b), with
+//   (A x)_k = D_k x_k + O_k x_{k+1} + O_{k-1}^T x_{k-1},
+// and the squared column norms of r64 per block row into part.
+template <int NB, typename Rec>
 __global__ void __launch_bounds__(256) k_mr_resid(MrArgs a, double* r64,
                                                   int first) {
-  const int k = blockIdx.x, n = a.n, L = a.nrhs;
-  const size_t pn = (size_t)n * L, nn = (size_t)n * n;
+  constexpr int NN = NB * NB, MR = NB / 4;
+  __shared__ Rec sD[NN], sO[NN], sOm[NN];
+  __shared__ double red[4][64];
+  const int k = blockIdx.x, t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int c = blockIdx.y * CPB + lane, L = a.nrhs;
+  const size_t pn = (size_t)NB * L;
   const bool hp = k > 0, hn = k < a.R - 1;
-  const double* xk = a.x + (size_t)k * pn;
-  for (size_t e = threadIdx.x; e < pn; e += 256) {
-    const int i = (int)(e / L), c = (int)(e % L);
-    double acc = 0.0;
-    if (!first && !a.done[c]) {
-      for (int j = 0; j < n; ++j)
-        acc += rec(a.D, (size_t)k * nn + (size_t)i * n + j, a.dtype) *
-               xk[(size_t)j * L + c];
-      if (hn)
-        for (int j = 0; j < n; ++j)
-          acc += rec(a.O, (size_t)k * nn + (size_t)i * n + j, a.dtype) *
-                 xk[pn + (size_t)j * L + c];
-      if (hp)
-        for (int j = 0; j < n; ++j)
-          acc += rec(a.O, (size_t)(k - 1) * nn + (size_t)j * n + i, a.dtype) *
-                 xk[(size_t)j * L + c - pn];
-    }
-    r64[(size_t)k * pn + e] = a.done[c] ? 0.0 : a.b[(size_t)k * pn + e] - acc;
+  const Rec* D = (const Rec*)a.D + (size_t)k * NN;
+  const Rec* O = (const Rec*)a.O;
+  for (int e = t; e < NN; e += 256) {
+    sD[e] = D[e];
+    sO[e] = hn ? O[(size_t)k * NN + e] : (Rec)0;
+    sOm[e] = hp ? O[(size_t)(k - 1) * NN + e] : (Rec)0;
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < L; c += 256) {
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) {
-      const double v = r64[(size_t)k * pn + (size_t)i * L + c];
-      s += v * v;
+  const bool done = a.done[c] != 0;
+  double acc[MR];
+#pragma unroll
+  for (int m = 0; m < MR; ++m) acc[m] = 0.0;
+  if (!first && !done) {
+    const double* xk = a.x + (size_t)k * pn + c;
+    const double* xn = hn ? xk + pn : xk;
+    const double* xm = hp ? xk - pn : xk;
+#pragma unroll 4
+    for (int j = 0; j < NB; ++j) {
+      const double x0 = xk[(size_t)j * L];
+      const double x1 = hn ? xn[(size_t)j * L] : 0.0;
+      const double x2 = hp ? xm[(size_t)j * L] : 0.0;
+#pragma unroll
+      for (int m = 0; m < MR; ++m) {
+        const int i = w + 4 * m;
+        double v = fma((double)sD[i * NB + j], x0, acc[m]);
+        v = fma((double)sO[i * NB + j], x1, v);
+        acc[m] = fma((double)sOm[j * NB + i], x2, v);
+      }
     }
-    a.part[(size_t)k * L + c] = s;
   }
+  double ss = 0.0;
+#pragma unroll
+  for (int m = 0; m < MR; ++m) {
+    const size_t idx = (size_t)k * pn + (size_t)(w + 4 * m) * L + c;
+    const double v = done ? 0.0 : a.b[idx] - acc[m];
+    r64[idx] = v;
+    ss = fma(v, v, ss);
+  }
+  red[w][lane] = ss;
+  __syncthreads();
+  if (w == 0)
+    a.part[(size_t)k * L + c] = (red[0][lane] + red[1][lane]) +
+                                (red[2][lane] + red[3][lane]);
 }
 
-// r = L^{-1} r64 (float), d = 0 for running columns.
+// r = L^{-1} r64 (float), d = 0, p = 0 for the running columns.
+template <int NB>
 __global__ void __launch_bounds__(256) k_mr_tohat(MrArgs a, const double* r64) {
-  const int k = blockIdx.x, n = a.n, L = a.nrhs;
-  const size_t pn = (size_t)n * L, nn = (size_t)n * n;
-  for (size_t e = threadIdx.x; e < pn; e += 256) {
-    const int i = (int)(e / L), c = (int)(e % L);
-    float acc = 0.f;
-    if (a.act[c]) {
-      const float* row = a.Li + (size_t)k * nn + (size_t)i * n;
-      for (int j = 0; j <= i; ++j)
-        acc = __fmaf_rn(row[j], (float)r64[(size_t)k * pn + (size_t)j * L + c], acc);
+  constexpr int NN = NB * NB, MR = NB / 4;
+  __shared__ float sL[NN];
+  const int k = blockIdx.x, t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int c = blockIdx.y * CPB + lane, L = a.nrhs;
+  const size_t pn = (size_t)NB * L;
+  for (int e = t; e < NN; e += 256) sL[e] = a.Li[(size_t)k * NN + e];
+  __syncthreads();
+  float acc[MR];
+#pragma unroll
+  for (int m = 0; m < MR; ++m) acc[m] = 0.f;
+  if (a.act[c]) {
+    const double* rk = r64 + (size_t)k * pn + c;
+#pragma unroll 4
+    for (int j = 0; j < NB; ++j) {
+      const float rv = (float)rk[(size_t)j * L];
+#pragma unroll
+      for (int m = 0; m < MR; ++m)  // L^{-1} is zero above the diagonal
+        acc[m] = __fmaf_rn(sL[(w + 4 * m) * NB + j], rv, acc[m]);
     }
-    a.r[(size_t)k * pn + e] = acc;
-    a.d[(size_t)k * pn + e] = 0.f;
-    a.p[(size_t)k * pn + e] = 0.f;  // beta = 0 at the first step: p = z
+  }
+#pragma unroll
+  for (int m = 0; m < MR; ++m) {
+    const size_t idx = (size_t)k * pn + (size_t)(w + 4 * m) * L + c;
+    a.r[idx] = acc[m];
+    a.d[idx] = 0.f;
+    a.p[idx] = 0.f;  // beta = 0 at the first step: p = z
   }
 }
 
 // x += L^{-T} d for the columns that ran an inner solve.
+template <int NB>
 __global__ void __launch_bounds__(256) k_mr_xupd(MrArgs a) {
-  const int k = blockIdx.x, n = a.n, L = a.nrhs;
-  const size_t pn = (size_t)n * L, nn = (size_t)n * n;
-  for (size_t e = threadIdx.x; e < pn; e += 256) {
-    const int i = (int)(e / L), c = (int)(e % L);
-    if (a.done[c]) continue;
-    float acc = 0.f;
-    for (int j = i; j < n; ++j)
-      acc = __fmaf_rn(a.Li[(size_t)k * nn + (size_t)j * n + i],
-                      a.d[(size_t)k * pn + (size_t)j * L + c], acc);
-    a.x[(size_t)k * pn + e] += (double)acc;
+  constexpr int NN = NB * NB, MR = NB / 4;
+  __shared__ float sL[NN];
+  const int k = blockIdx.x, t = threadIdx.x, w = t >> 6, lane = t & 63;
+  const int c = blockIdx.y * CPB + lane, L = a.nrhs;
+  const size_t pn = (size_t)NB * L;
+  for (int e = t; e < NN; e += 256) sL[e] = a.Li[(size_t)k * NN + e];
+  __syncthreads();
+  if (a.done[c]) return;
+  float acc[MR];
+#pragma unroll
+  for (int m = 0; m < MR; ++m) acc[m] = 0.f;
+  const float* dk = a.d + (size_t)k * pn + c;
+#pragma unroll 4
+  for (int j = 0; j < NB; ++j) {
+    const float dv = dk[(size_t)j * L];
+#pragma unroll
+    for (int m = 0; m < MR; ++m)  // (L^{-1})_{j i} = 0 for j < i
+      acc[m] = __fmaf_rn(sL[j * NB + w + 4 * m], dv, acc[m]);
   }
+#pragma unroll
+  for (int m = 0; m < MR; ++m)
+    a.x[(size_t)k * pn + (size_t)(w + 4 * m) * L + c] += (double)acc[m];
 }
 
 __global__ void k_mr_outer_done(MrArgs a) {
@@ -496,12 +546,17 @@ int solve(const MrArgs& a0, double* r64, int max_outer, bt_info* info,
   hipLaunchKernelGGL(k_mr_bnorm, dim3(a.R), dim3(64), 0, s, a);
   hipLaunchKernelGGL(k_mr_init_cols, dim3(a.nrhs), dim3(256), 0, s, a);
   for (int outer = 0;; ++outer) {
-    hipLaunchKernelGGL(k_mr_resid, dim3(a.R), dim3(256), 0, s, a, r64,
-                       outer == 0 ? 1 : 0);
+    if (a.dtype == BT_DT_F64)
+      hipLaunchKernelGGL((k_mr_resid<NB, double>), dim3(a.R, a.nrhs / CPB),
+                         dim3(256), 0, s, a, r64, outer == 0 ? 1 : 0);
+    else
+      hipLaunchKernelGGL((k_mr_resid<NB, float>), dim3(a.R, a.nrhs / CPB),
+                         dim3(256), 0, s, a, r64, outer == 0 ? 1 : 0);
     hipLaunchKernelGGL((k_mr_colsum<SUM_RES>), dim3(a.nrhs), dim3(256), 0, s, a);
     if (!read_any(&hany)) return BT_EHIP;
     if (hany == 0 || outer >= max_outer) break;
-    hipLaunchKernelGGL(k_mr_tohat, dim3(a.R), dim3(256), 0, s, a, r64);
+    hipLaunchKernelGGL((k_mr_tohat<NB>), dim3(a.R, a.nrhs / CPB), dim3(256),
+                       0, s, a, r64);
     if (precond<NB>(a, s) != hipSuccess) return BT_EHIP;
     hipLaunchKernelGGL((k_mr_colsum<SUM_RHO>), dim3(a.nrhs), dim3(256), 0, s, a);
     for (int it = 0;; ++it) {
@@ -513,7 +568,8 @@ int solve(const MrArgs& a0, double* r64, int max_outer, bt_info* info,
       if (precond<NB>(a, s) != hipSuccess) return BT_EHIP;
       hipLaunchKernelGGL((k_mr_colsum<SUM_RHO>), dim3(a.nrhs), dim3(256), 0, s, a);
     }
-    hipLaunchKernelGGL(k_mr_xupd, dim3(a.R), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((k_mr_xupd<NB>), dim3(a.R, a.nrhs / CPB), dim3(256),
+                       0, s, a);
     hipLaunchKernelGGL(k_mr_outer_done, dim3((a.nrhs + 63) / 64), dim3(64), 0,
                        s, a);
   }

@@ -484,6 +484,157 @@ hipError_t launch_offdiag_nb(const SetupArgs& a, hipStream_t s) {
              : launch_offdiag<NB, float, float>(a, s);
 }
 
+// ---------------------------------------------------------------------------
+// Larger blocks (n = 16 ... 64): one wavefront per block row for the factors,
+// one workgroup per block row for F.
+// ---------------------------------------------------------------------------
+
+// L_g = chol(D_g), Li_g = L_g^{-1}, float64, the block in LDS (rows padded to
+// NB + 1 entries). Cholesky by columns: the diagonal, the scaled column below
+// it, then the trailing update with one row per lane. The inverse by forward
+// substitution, one column per lane, held in registers.
+template <int NB, typename T, typename Rec>
+__global__ void __launch_bounds__(64) k_factor_wave(SetupArgs a) {
+  constexpr int NN = NB * NB, P = NB + 1;
+  __shared__ double M[NB * P];
+  __shared__ double rdiag[NB];
+  const int64_t g = blockIdx.x;
+  const int l = threadIdx.x;
+  const Rec* D = (const Rec*)a.D + (size_t)g * NN;
+  for (int e = l; e < NN; e += 64) M[(e / NB) * P + e % NB] = (double)D[e];
+  __syncthreads();
+  bool ok = true;
+  for (int j = 0; j < NB; ++j) {
+    double djj = M[j * P + j];
+    if (!(djj > 0.0 && djj < INFINITY)) {
+      ok = false;
+      djj = 1.0;
+    }
+    const double dj = sqrt(djj);
+    const double rd = 1.0 / dj;
+    __syncthreads();  // every lane has read M[j][j]
+    if (l == 0) {
+      M[j * P + j] = dj;
+      rdiag[j] = rd;
+    }
+    const int r = j + 1 + l;  // this lane's row below the diagonal
+    double lrj = 0.0;
+    if (r < NB) {
+      lrj = M[r * P + j] * rd;
+      M[r * P + j] = lrj;
+    }
+    __syncthreads();
+    if (r < NB)
+      for (int c = j + 1; c <= r; ++c) M[r * P + c] -= lrj * M[c * P + j];
+    __syncthreads();
+  }
+  if (!ok && l == 0) {
+    const int inst = a.rowinst[g];
+    atomicMin(&a.fail[inst], (int)(g - a.off[inst]));
+  }
+  if (a.L) {
+    T* L = (T*)a.L + (size_t)g * NN;
+    for (int e = l; e < NN; e += 64) {
+      const int i = e / NB, j = e % NB;
+      L[e] = (T)(j <= i ? M[i * P + j] : 0.0);
+    }
+  }
+  __syncthreads();  // L written out before its diagonal is overwritten
+  // Column c = l of X = L^{-1}: X[i][c] = (delta_ic - sum_{k=c}^{i-1}
+  // L[i][k] X[k][c]) / L[i][i] for i >= c, kept transposed in the upper
+  // triangle of M (X[i][c] at M[c][i]); the substitution reads only the
+  // strict lower triangle of L and the reciprocal diagonal.
+  if (l < NB) {
+    const int c = l;
+    for (int i = c; i < NB; ++i) {
+      double t = (i == c) ? 1.0 : 0.0;
+      for (int k = c; k < i; ++k) t = fma(-M[i * P + k], M[c * P + k], t);
+      M[c * P + i] = t * rdiag[i];
+    }
+  }
+  __syncthreads();
+  T* Li = (T*)a.Li + (size_t)g * NN;
+  for (int e = l; e < NN; e += 64) {
+    const int i = e / NB, c = e % NB;
+    Li[e] = (T)(i >= c ? M[c * P + i] : 0.0);
+  }
+}
+
+// F_g = Li_g O_g Li_{g+1}^T (zero for the last row of each instance), one
+// 256-thread workgroup per block row, operands in LDS as float64.
+template <int NB, typename T, typename Rec>
+__global__ void __launch_bounds__(256) k_offdiag_block(SetupArgs a) {
+  constexpr int NN = NB * NB;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* Lg = reinterpret_cast<double*>(smem_raw);
+  double* Ln = Lg + NN;
+  double* Og = Ln + NN;
+  double* Tm = Og + NN;
+  const int64_t g = blockIdx.x;
+  const int t = threadIdx.x;
+  const int inst = a.rowinst[g];
+  const bool has_next = g + 1 < a.off[inst + 1];
+  T* F = (T*)a.F + (size_t)g * NN;
+  if (!has_next) {
+    for (int e = t; e < NN; e += 256) F[e] = (T)0;
+    return;
+  }
+  const T* lig = (const T*)a.Li + (size_t)g * NN;
+  const Rec* og = (const Rec*)a.O + (size_t)(g - inst) * NN;
+  for (int e = t; e < NN; e += 256) {
+    Lg[e] = (double)lig[e];
+    Ln[e] = (double)lig[NN + e];
+    Og[e] = (double)og[e];
+  }
+  __syncthreads();
+  for (int e = t; e < NN; e += 256) {
+    const int i = e / NB, j = e % NB;
+    double s0 = 0.0;
+#pragma unroll 8
+    for (int p = 0; p < NB; ++p) s0 = fma(Lg[i * NB + p], Og[p * NB + j], s0);
+    Tm[e] = s0;
+  }
+  __syncthreads();
+  for (int e = t; e < NN; e += 256) {
+    const int i = e / NB, j = e % NB;
+    double s0 = 0.0;
+#pragma unroll 8
+    for (int q = 0; q < NB; ++q) s0 = fma(Tm[i * NB + q], Ln[j * NB + q], s0);
+    F[e] = (T)s0;
+  }
+}
+
+template <int NB, typename T, typename Rec>
+hipError_t launch_wave(const SetupArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_factor_wave<NB, T, Rec>), dim3((unsigned)a.R),
+                     dim3(64), 0, s, a);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || !a.F) return e;
+  if (NB == 24) return launch_offdiag<24, T, Rec>(a, s);
+  constexpr size_t lds = 4 * sizeof(double) * (size_t)NB * NB;
+  static bool attr = false;
+  if (!attr) {
+    e = hipFuncSetAttribute((const void*)k_offdiag_block<NB, T, Rec>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_offdiag_block<NB, T, Rec>), dim3((unsigned)a.R),
+                     dim3(256), lds, s, a);
+  return hipGetLastError();
+}
+
+template <int NB>
+hipError_t launch_wave_nb(const SetupArgs& a, hipStream_t s) {
+  const bool f64 = a.prec == BT_F64;
+  const bool r64 = a.dtype == BT_DT_F64;
+  if (f64) return r64 ? launch_wave<NB, double, double>(a, s)
+                      : launch_wave<NB, double, float>(a, s);
+  return r64 ? launch_wave<NB, float, double>(a, s)
+             : launch_wave<NB, float, float>(a, s);
+}
+
 template <int NB>
 hipError_t launch_lane_nb(const SetupArgs& a, hipStream_t s) {
   const bool f64 = a.prec == BT_F64;
@@ -525,9 +676,15 @@ hipError_t bt_launch_setup(const SetupArgs& a0, hipStream_t s) {
   if (a0.R <= 0) return hipSuccess;
   if (a0.n == 12) return btk::launch_lane_nb<12>(a0, s);
   if (a0.n == 6) return btk::launch_lane_nb<6>(a0, s);
-  // n = 24: factors by the generic kernel, F by the row-wave kernel
-  SetupArgs a = a0;
-  if (a0.n == 24) a.F = nullptr;
+  switch (a0.n) {
+    case 16: return btk::launch_wave_nb<16>(a0, s);
+    case 24: return btk::launch_wave_nb<24>(a0, s);
+    case 32: return btk::launch_wave_nb<32>(a0, s);
+    case 48: return btk::launch_wave_nb<48>(a0, s);
+    case 64: return btk::launch_wave_nb<64>(a0, s);
+    default: break;
+  }
+  const SetupArgs& a = a0;
   const size_t sm = 4 * sizeof(double) * (size_t)a.n * a.n;
   const bool f64 = a.prec == BT_F64;
   const bool big = a.n > 16;
@@ -554,9 +711,7 @@ hipError_t bt_launch_setup(const SetupArgs& a0, hipStream_t s) {
       hipLaunchKernelGGL((btk::k_setup<64, float>), dim3(a.R), dim3(64), sm, s,
                          a);
   }
-  e = hipGetLastError();
-  if (e != hipSuccess || a0.n != 24) return e;
-  return btk::launch_offdiag_nb<24>(a0, s);
+  return hipGetLastError();
 }
 
 hipError_t bt_launch_setup_init(int B, int32_t* fail, int32_t* ctr,

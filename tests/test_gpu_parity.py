@@ -94,7 +94,9 @@ def test_single_n12_f32_plain():
 
 
 @pytest.mark.parametrize("N,n", [(1, 1), (1, 5), (2, 1), (2, 3), (3, 2),
-                                 (7, 1), (17, 4), (64, 12), (70, 16)])
+                                 (7, 1), (17, 4), (64, 12), (70, 16),
+                                 (40, 24), (24, 32), (12, 48), (6, 64),
+                                 (1, 48)])
 def test_shapes_and_ragged_tails(N, n):
     """Sizes spanning several elements per thread and ragged tails."""
     d = lqrgen.lqr_instance(N, n, max(1, n // 3), 4242, N * 100 + n)
@@ -104,6 +106,22 @@ def test_shapes_and_ragged_tails(N, n):
 def test_batch_f64_per_instance_parity():
     B = 24
     data = lqrgen.lqr_batch(B, (1, 40), 5, 2, seed=77)
+    P = bt.Params.polycoeff(2)
+    x, info, _ = gpu_solve(data["D"], data["O"], data["b"], data["offsets"], P)
+    for i, rows, oblk in orc.batch_slices(data["offsets"]):
+        xr, ri = orc.pcg(data["D"][rows], data["O"][oblk], data["b"][rows],
+                         m=2, alpha=orc.polycoeff(2))
+        assert info[i]["status"] == bt.OK
+        assert iteration_match(int(info[i]["iters"]), ri), (i, info[i], ri)
+        if info[i]["iters"] == ri["iters"]:
+            assert rel(x[rows], xr) <= 1e-10
+
+
+@pytest.mark.parametrize("n", [16, 24, 48])
+def test_batch_f64_larger_blocks(n):
+    """Setup kernels of the larger block sizes (wavefront-per-row factors,
+    row-wavefront or block F) across instance boundaries, lengths 1..20."""
+    data = lqrgen.lqr_batch(12, (1, 20), n, n // 3, seed=500 + n)
     P = bt.Params.polycoeff(2)
     x, info, _ = gpu_solve(data["D"], data["O"], data["b"], data["offsets"], P)
     for i, rows, oblk in orc.batch_slices(data["offsets"]):
