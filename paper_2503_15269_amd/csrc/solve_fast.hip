@@ -452,10 +452,13 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
                   acc += (double)((const Rec*)a.O)[o + jj] * xk[NB + jj];
               }
               if (c.k > 0) {
-                const size_t o = (size_t)(ob - 1) * nn + i;
+                // column i of O_{k-1}: all loads issued before the sums
+                const Rec* oc = (const Rec*)a.O + (size_t)(ob - 1) * nn + i;
+                Rec col[NB];
 #pragma unroll
-                for (int jj = 0; jj < NB; ++jj)
-                  acc += (double)((const Rec*)a.O)[o + (size_t)jj * NB] * xk[jj - NB];
+                for (int jj = 0; jj < NB; ++jj) col[jj] = oc[(size_t)jj * NB];
+#pragma unroll
+                for (int jj = 0; jj < NB; ++jj) acc += (double)col[jj] * xk[jj - NB];
               }
             }
             r64 = a.b[g * NB + i] - acc;
