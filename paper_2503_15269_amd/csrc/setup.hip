@@ -489,75 +489,95 @@ hipError_t launch_offdiag_nb(const SetupArgs& a, hipStream_t s) {
 // one workgroup per block row for F.
 // ---------------------------------------------------------------------------
 
-// L_g = chol(D_g), Li_g = L_g^{-1}, float64, the block in LDS (rows padded to
-// NB + 1 entries). Cholesky by columns: the diagonal, the scaled column below
-// it, then the trailing update with one row per lane. The inverse by forward
-// substitution, one column per lane, held in registers.
+// L_g = chol(D_g), Li_g = L_g^{-1}, float64, one wavefront per block row.
+// Cholesky by columns with lane r holding row r in registers: after the
+// pivot step of column j each lane publishes its entry of column j in LDS
+// and updates the rest of its row from that column (broadcast reads). The
+// inverse by forward substitution with lane c forming column c in
+// registers from the rows of L in LDS.
 template <int NB, typename T, typename Rec>
 __global__ void __launch_bounds__(64) k_factor_wave(SetupArgs a) {
   constexpr int NN = NB * NB, P = NB + 1;
-  __shared__ double M[NB * P];
-  __shared__ double rdiag[NB];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* Ls = reinterpret_cast<double*>(smem_raw);  // [NB][P]: L, then X^T
+  double* rdiag = Ls + NB * P;                        // [NB]
   const int64_t g = blockIdx.x;
-  const int l = threadIdx.x;
-  const Rec* D = (const Rec*)a.D + (size_t)g * NN;
-  for (int e = l; e < NN; e += 64) M[(e / NB) * P + e % NB] = (double)D[e];
-  __syncthreads();
+  const int r = threadIdx.x;
+  const int rr = r < NB ? r : NB - 1;  // lanes past the block mirror the last row
+  double m[NB];
+  {
+    const Rec* D = (const Rec*)a.D + (size_t)g * NN + (size_t)rr * NB;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) m[j] = (double)D[j];
+  }
   bool ok = true;
+#pragma unroll
   for (int j = 0; j < NB; ++j) {
-    double djj = M[j * P + j];
+    double djj = __shfl(m[j], j);  // pivot from lane j
     if (!(djj > 0.0 && djj < INFINITY)) {
       ok = false;
       djj = 1.0;
     }
-    const double dj = sqrt(djj);
-    const double rd = 1.0 / dj;
-    __syncthreads();  // every lane has read M[j][j]
-    if (l == 0) {
-      M[j * P + j] = dj;
-      rdiag[j] = rd;
-    }
-    const int r = j + 1 + l;  // this lane's row below the diagonal
-    double lrj = 0.0;
-    if (r < NB) {
-      lrj = M[r * P + j] * rd;
-      M[r * P + j] = lrj;
-    }
+    const double dj = sqrt(djj), rd = 1.0 / dj;
+    if (rr > j) m[j] *= rd;
+    if (rr == j) m[j] = dj;
+    if (r < NB) Ls[r * P + j] = m[j];
+    if (r == 0) rdiag[j] = rd;
     __syncthreads();
-    if (r < NB)
-      for (int c = j + 1; c <= r; ++c) M[r * P + c] -= lrj * M[c * P + j];
-    __syncthreads();
+#pragma unroll
+    for (int c = j + 1; c < NB; ++c) {
+      const double lcj = Ls[c * P + j];
+      if (rr >= c) m[c] = fma(-m[j], lcj, m[c]);
+    }
   }
-  if (!ok && l == 0) {
+  if (!ok && r == 0) {
     const int inst = a.rowinst[g];
     atomicMin(&a.fail[inst], (int)(g - a.off[inst]));
   }
+  __syncthreads();
   if (a.L) {
     T* L = (T*)a.L + (size_t)g * NN;
-    for (int e = l; e < NN; e += 64) {
+    for (int e = r; e < NN; e += 64) {
       const int i = e / NB, j = e % NB;
-      L[e] = (T)(j <= i ? M[i * P + j] : 0.0);
+      L[e] = (T)(j <= i ? Ls[i * P + j] : 0.0);
     }
   }
-  __syncthreads();  // L written out before its diagonal is overwritten
-  // Column c = l of X = L^{-1}: X[i][c] = (delta_ic - sum_{k=c}^{i-1}
-  // L[i][k] X[k][c]) / L[i][i] for i >= c, kept transposed in the upper
-  // triangle of M (X[i][c] at M[c][i]); the substitution reads only the
-  // strict lower triangle of L and the reciprocal diagonal.
-  if (l < NB) {
-    const int c = l;
-    for (int i = c; i < NB; ++i) {
-      double t = (i == c) ? 1.0 : 0.0;
-      for (int k = c; k < i; ++k) t = fma(-M[i * P + k], M[c * P + k], t);
-      M[c * P + i] = t * rdiag[i];
+  // X = L^{-1} by the same scheme, lane r holding row r of X: at step k
+  // row k is final (scaled by 1 / L[k][k]) and published; every row i > k
+  // subtracts L[i][k] times it (L[i][k] is lane i's own m[k]).
+  double x[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) x[c] = (c == rr) ? 1.0 : 0.0;
+  double* Xs = Ls;  // L is no longer read from LDS
+#pragma unroll
+  for (int k = 0; k < NB; ++k) {
+    if (rr == k) {
+      const double rk = rdiag[k];
+#pragma unroll
+      for (int c = 0; c <= k; ++c) x[c] *= rk;
+    }
+    __syncthreads();  // previous readers of row k-1 are done
+    if (r == k) {
+#pragma unroll
+      for (int c = 0; c <= k; ++c) Xs[k * P + c] = x[c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c <= k; ++c) {
+      const double xk = Xs[k * P + c];
+      if (rr > k) x[c] = fma(-m[k], xk, x[c]);
     }
   }
-  __syncthreads();
-  T* Li = (T*)a.Li + (size_t)g * NN;
-  for (int e = l; e < NN; e += 64) {
-    const int i = e / NB, c = e % NB;
-    Li[e] = (T)(i >= c ? M[c * P + i] : 0.0);
+  if (r < NB) {
+    T* Li = (T*)a.Li + (size_t)g * NN + (size_t)r * NB;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) Li[c] = (T)x[c];
   }
+}
+
+template <int NB>
+constexpr size_t factor_wave_lds() {
+  return sizeof(double) * ((size_t)NB * (NB + 1) + NB);
 }
 
 // F_g = Li_g O_g Li_{g+1}^T (zero for the last row of each instance), one
@@ -606,8 +626,17 @@ __global__ void __launch_bounds__(256) k_offdiag_block(SetupArgs a) {
 
 template <int NB, typename T, typename Rec>
 hipError_t launch_wave(const SetupArgs& a, hipStream_t s) {
+  constexpr size_t flds = factor_wave_lds<NB>();
+  static bool fattr = false;
+  if (!fattr) {
+    hipError_t e0 = hipFuncSetAttribute(
+        (const void*)k_factor_wave<NB, T, Rec>,
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)flds);
+    if (e0 != hipSuccess) return e0;
+    fattr = true;
+  }
   hipLaunchKernelGGL((k_factor_wave<NB, T, Rec>), dim3((unsigned)a.R),
-                     dim3(64), 0, s, a);
+                     dim3(64), flds, s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !a.F) return e;
   if (NB == 24) return launch_offdiag<24, T, Rec>(a, s);
