@@ -14,19 +14,26 @@
 //
 // One inner iteration (m = 2 shown; the polynomial follows eq. Mminv-poly-
 // nomial-coefficients at a = 1: y_0 = r + C r, y_i = C(C y_{i-1}))
-//   p = z + beta p                          k_mr_axpy_p
-//   q = p - C p,  sigma = p'q partials      k_mr_app<EPI_Q>
+//   p = z + beta p, q = p - C p,
+//     sigma = p'q partials                  k_mr_app<EPI_QU>
 //   alpha = rho / sigma                     k_mr_colsum<SIGMA>
-//   d += alpha p, r -= alpha q              k_mr_axpy_dr
-//   y0 = r + C r                            k_mr_app<EPI_Y0>
+//   r = r - alpha q, d += alpha p,
+//     y0 = r + C r                          k_mr_app<EPI_Y0U>
 //   w = C y0                                k_mr_app<EPI_W>
 //   z = y0 + alpha_1 C w, rho = r'z parts   k_mr_app<EPI_Z>
 //   beta, stopping test                     k_mr_colsum<RHO>
-// Converged right-hand sides keep being carried through the products but no
-// longer update. The host checks every few iterations whether any is left.
+// The vector updates are fused into the products: a workgroup forms the
+// updated p (or r) of its own row and of both neighbour rows from the old
+// values, so p and r alternate between two panels (the neighbours' old
+// values must survive until every workgroup has read them). Workgroups are
+// mapped to rows so that each XCD gets a contiguous range of block rows and
+// the neighbour rows' data is shared in its L2. Converged right-hand sides
+// no longer update; a workgroup whose columns have all stopped returns at
+// once. The host checks every few iterations whether any is left.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <utility>
 #include <vector>
 
 #include "internal.h"
@@ -50,7 +57,7 @@ __device__ __forceinline__ float bf2f(unsigned short h) {
   return __uint_as_float((unsigned)h << 16);
 }
 
-enum { EPI_Q = 0, EPI_Y0 = 1, EPI_W = 2, EPI_Z = 3 };
+enum { EPI_QU = 0, EPI_Y0 = 1, EPI_W = 2, EPI_Z = 3, EPI_Y0U = 4 };
 
 struct MrArgs {
   int R, n, nrhs;
@@ -63,6 +70,7 @@ struct MrArgs {
   const double* b;            // [R][n][nrhs]
   double* x;
   float *p, *q, *r, *d, *y0, *w, *z;  // panels [R][n][nrhs]
+  float *p2, *r2;             // second panels of p and r (alternating)
   double* part;               // [R][nrhs] per-row partial sums
   // per right-hand-side state
   double *rho, *rho0, *alpha, *beta, *nb2, *nr2;
@@ -74,37 +82,70 @@ struct MrArgs {
 };
 
 // ---------------------------------------------------------------------------
-// Y = C V on the matrix cores, with an epilogue. Grid (R, nrhs / 64).
+// Y = C V on the matrix cores, with an epilogue. Grid (8 ceil(R / 8),
+// nrhs / 64); block b works on row (b mod 8) ceil(R / 8) + b / 8, so that the
+// workgroups of one XCD (dispatched round-robin) cover consecutive rows.
+// For EPI_QU and EPI_Y0U the operand is an update formed on the fly:
+//   QU:  V = p_new = z + beta p   (V1 = z, V2 = p old, out2 = p new)
+//   Y0U: V = r_new = r - alpha q  (V1 = r old, V2 = q, out2 = r new)
+// (for a column that has stopped the operand is the old value, unchanged).
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int xcd_row(int b, int R) {
+  const int chunk = (R + 7) / 8;
+  return (b & 7) * chunk + (b >> 3);
+}
+
+template <int EPI>
+__device__ __forceinline__ float operand(const MrArgs& a, const float* V1,
+                                         const float* V2, size_t idx, int col,
+                                         bool act) {
+  if constexpr (EPI == EPI_QU) {
+    return act ? __fmaf_rn((float)a.beta[col], V2[idx], V1[idx]) : V2[idx];
+  } else if constexpr (EPI == EPI_Y0U) {
+    return act ? __fmaf_rn(-(float)a.alpha[col], V2[idx], V1[idx]) : V1[idx];
+  } else {
+    return V1[idx];
+  }
+}
+
 template <int NB, int EPI>
 __global__ void __launch_bounds__(WG) k_mr_app(MrArgs a, const float* V,
-                                              const float* aux, float* out) {
+                                              const float* V2, const float* aux,
+                                              float* out, float* out2) {
   constexpr int MT = NB / 16;
-  __shared__ unsigned short sFk[2][NB * NB];   // hi, lo of F_k
-  __shared__ unsigned short sFm[2][NB * NB];   // hi, lo of F_{k-1}
-  const int k = blockIdx.x;
+  constexpr int NN = NB * NB;
+  __shared__ __align__(16) unsigned short sFk[2][NN];   // hi, lo of F_k
+  __shared__ __align__(16) unsigned short sFm[2][NN];   // hi, lo of F_{k-1}
+  const int k = xcd_row(blockIdx.x, a.R);
+  if (k >= a.R) return;
   const int t = threadIdx.x;
   const int wv = t >> 6, l = t & 63;
   const int c0 = blockIdx.y * CPB + wv * CPW;
   const int col = c0 + (l & 15);
   const int kq = 4 * (l >> 4);                 // k-offset of this lane
   const bool has_prev = k > 0, has_next = k < a.R - 1;
-  const size_t nn = (size_t)NB * NB;
   // nothing to do once every column of this workgroup has stopped (the host
   // only checks every few iterations)
   if (!__syncthreads_or(a.act[blockIdx.y * CPB + (t & 63)])) return;
-  for (int e = t; e < NB * NB; e += WG) {
-    if (has_next) {
-      sFk[0][e] = a.Fhi[(size_t)k * nn + e];
-      sFk[1][e] = a.Flo[(size_t)k * nn + e];
-    }
-    if (has_prev) {
-      sFm[0][e] = a.Fhi[(size_t)(k - 1) * nn + e];
-      sFm[1][e] = a.Flo[(size_t)(k - 1) * nn + e];
+  {
+    // 16-byte loads of the bfloat16 halves (NN is a multiple of 8)
+    const uint4* fh = reinterpret_cast<const uint4*>(a.Fhi);
+    const uint4* fl = reinterpret_cast<const uint4*>(a.Flo);
+    constexpr int NC = NN / 8;
+    for (int e = t; e < NC; e += WG) {
+      if (has_next) {
+        reinterpret_cast<uint4*>(sFk[0])[e] = fh[(size_t)k * NC + e];
+        reinterpret_cast<uint4*>(sFk[1])[e] = fl[(size_t)k * NC + e];
+      }
+      if (has_prev) {
+        reinterpret_cast<uint4*>(sFm[0])[e] = fh[(size_t)(k - 1) * NC + e];
+        reinterpret_cast<uint4*>(sFm[1])[e] = fl[(size_t)(k - 1) * NC + e];
+      }
     }
   }
   __syncthreads();
   const int ld = a.nrhs;
+  const bool act = a.act[col] != 0;
   f32x4 acc[MT];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -113,10 +154,10 @@ __global__ void __launch_bounds__(WG) k_mr_app(MrArgs a, const float* V,
     const int kr = 16 * ks + kq;  // first of the 4 K rows of this lane
     if (has_next) {
       bf16x4 bh, bl;
-      const float* vp = V + ((size_t)(k + 1) * NB + kr) * ld + col;
+      const size_t base = ((size_t)(k + 1) * NB + kr) * ld + col;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const float v = vp[(size_t)i * ld];
+        const float v = operand<EPI>(a, V, V2, base + (size_t)i * ld, col, act);
         const unsigned short h = f2bf(v);
         bh[i] = (short)h;
         bl[i] = (short)f2bf(v - bf2f(h));
@@ -137,10 +178,10 @@ __global__ void __launch_bounds__(WG) k_mr_app(MrArgs a, const float* V,
     }
     if (has_prev) {
       bf16x4 bh, bl;
-      const float* vm = V + ((size_t)(k - 1) * NB + kr) * ld + col;
+      const size_t base = ((size_t)(k - 1) * NB + kr) * ld + col;
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const float v = vm[(size_t)i * ld];
+        const float v = operand<EPI>(a, V, V2, base + (size_t)i * ld, col, act);
         const unsigned short h = f2bf(v);
         bh[i] = (short)h;
         bl[i] = (short)f2bf(v - bf2f(h));
@@ -162,6 +203,7 @@ __global__ void __launch_bounds__(WG) k_mr_app(MrArgs a, const float* V,
   }
   // epilogue: lane holds rows 16 mt + kq + i of column ``col``; C V = -acc
   double dp = 0.0;
+  const float alc = (float)a.alpha[col];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
 #pragma unroll
@@ -170,10 +212,16 @@ __global__ void __launch_bounds__(WG) k_mr_app(MrArgs a, const float* V,
       const size_t idx = ((size_t)k * NB + row) * ld + col;
       const float cv = -acc[mt][i];
       float o;
-      if constexpr (EPI == EPI_Q) {
-        const float pv = V[idx];
+      if constexpr (EPI == EPI_QU) {
+        const float pv = operand<EPI>(a, V, V2, idx, col, act);
+        out2[idx] = pv;                  // p new
         o = pv - cv;                     // q = p - C p
         dp += (double)pv * (double)o;    // sigma = p'q
+      } else if constexpr (EPI == EPI_Y0U) {
+        const float rv = operand<EPI>(a, V, V2, idx, col, act);
+        out2[idx] = rv;                  // r new
+        if (act) a.d[idx] = __fmaf_rn(alc, aux[idx], a.d[idx]);  // d += alpha p
+        o = rv + cv;                     // y0 = r + C r
       } else if constexpr (EPI == EPI_Y0) {
         o = aux[idx] + cv;               // y0 = r + C r
       } else if constexpr (EPI == EPI_W) {
@@ -185,34 +233,10 @@ __global__ void __launch_bounds__(WG) k_mr_app(MrArgs a, const float* V,
       out[idx] = o;
     }
   }
-  if constexpr (EPI == EPI_Q || EPI == EPI_Z) {
+  if constexpr (EPI == EPI_QU || EPI == EPI_Z) {
     dp += __shfl_xor(dp, 16);
     dp += __shfl_xor(dp, 32);
     if (l < 16) a.part[(size_t)k * ld + col] = dp;
-  }
-}
-
-// p = z + beta p for the right-hand sides still iterating.
-__global__ void k_mr_axpy_p(MrArgs a) {
-  const size_t N = (size_t)a.R * a.n * a.nrhs;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
-       i += (size_t)gridDim.x * blockDim.x) {
-    const int c = (int)(i % a.nrhs);
-    if (a.act[c]) a.p[i] = __fmaf_rn((float)a.beta[c], a.p[i], a.z[i]);
-  }
-}
-
-// d += alpha p, r -= alpha q.
-__global__ void k_mr_axpy_dr(MrArgs a) {
-  const size_t N = (size_t)a.R * a.n * a.nrhs;
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
-       i += (size_t)gridDim.x * blockDim.x) {
-    const int c = (int)(i % a.nrhs);
-    if (a.act[c]) {
-      const float al = (float)a.alpha[c];
-      a.d[i] = __fmaf_rn(al, a.p[i], a.d[i]);
-      a.r[i] = __fmaf_rn(-al, a.q[i], a.r[i]);
-    }
   }
 }
 
@@ -487,40 +511,43 @@ __global__ void k_mr_split(const float* F, unsigned short* hi,
 }
 
 template <int NB, int EPI>
-hipError_t app(const MrArgs& a, const float* V, const float* aux, float* out,
-               hipStream_t s) {
-  hipLaunchKernelGGL((k_mr_app<NB, EPI>), dim3(a.R, a.nrhs / CPB), dim3(WG), 0,
-                     s, a, V, aux, out);
+hipError_t app(const MrArgs& a, const float* V, const float* V2,
+               const float* aux, float* out, float* out2, hipStream_t s) {
+  const int rows = 8 * ((a.R + 7) / 8);
+  hipLaunchKernelGGL((k_mr_app<NB, EPI>), dim3(rows, a.nrhs / CPB), dim3(WG),
+                     0, s, a, V, V2, aux, out, out2);
   return hipGetLastError();
 }
 
+// z = M^{-1} r at a = 1 for the current r: y0 = r + C r, then per extra term
+// y = C(C y), z = y0 + alpha_1 y (m <= 2 on this path; m = 1 reuses the Z
+// epilogue with alpha_1 = 0). ``y0_done``: y0 already formed (by EPI_Y0U).
 template <int NB>
-hipError_t inner_iteration(const MrArgs& a, hipStream_t s, int grid_ew) {
-  hipLaunchKernelGGL(k_mr_axpy_p, dim3(grid_ew), dim3(256), 0, s, a);
-  hipError_t e = app<NB, EPI_Q>(a, a.p, nullptr, a.q, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_mr_colsum<SUM_SIGMA>), dim3(a.nrhs), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(k_mr_axpy_dr, dim3(grid_ew), dim3(256), 0, s, a);
-  return hipGetLastError();
-}
-
-// z = M^{-1} r at a = 1: y0 = r + C r, then per extra term y = C(C y),
-// z = y0 + alpha_1 y (m <= 2 on this path).
-template <int NB>
-hipError_t precond(const MrArgs& a, hipStream_t s) {
-  hipError_t e = app<NB, EPI_Y0>(a, a.r, a.r, a.y0, s);
-  if (e != hipSuccess) return e;
-  if (a.m == 1) {
-    // z = y0 and rho = r'y0: reuse the Z epilogue with alpha_1 = 0
-    MrArgs b = a;
-    b.alpha1 = 0.0;
-    e = app<NB, EPI_W>(b, a.y0, nullptr, a.w, s);
+hipError_t precond(const MrArgs& a, hipStream_t s, bool y0_done) {
+  hipError_t e = hipSuccess;
+  if (!y0_done) {
+    e = app<NB, EPI_Y0>(a, a.r, nullptr, a.r, a.y0, nullptr, s);
     if (e != hipSuccess) return e;
-    return app<NB, EPI_Z>(b, a.w, a.y0, a.z, s);
   }
-  e = app<NB, EPI_W>(a, a.y0, nullptr, a.w, s);
+  MrArgs b = a;
+  if (a.m == 1) b.alpha1 = 0.0;
+  e = app<NB, EPI_W>(b, a.y0, nullptr, nullptr, a.w, nullptr, s);
   if (e != hipSuccess) return e;
-  return app<NB, EPI_Z>(a, a.w, a.y0, a.z, s);
+  return app<NB, EPI_Z>(b, a.w, nullptr, a.y0, a.z, nullptr, s);
+}
+
+// One inner iteration up to and including y0 = r + C r of the new residual;
+// swaps the p and r panels of ``a``.
+template <int NB>
+hipError_t inner_iteration(MrArgs& a, hipStream_t s) {
+  hipError_t e = app<NB, EPI_QU>(a, a.z, a.p, nullptr, a.q, a.p2, s);
+  if (e != hipSuccess) return e;
+  std::swap(a.p, a.p2);
+  hipLaunchKernelGGL((k_mr_colsum<SUM_SIGMA>), dim3(a.nrhs), dim3(256), 0, s, a);
+  e = app<NB, EPI_Y0U>(a, a.r, a.q, a.p, a.y0, a.r2, s);
+  if (e != hipSuccess) return e;
+  std::swap(a.r, a.r2);
+  return hipSuccess;
 }
 
 template <int NB>
@@ -557,15 +584,15 @@ int solve(const MrArgs& a0, double* r64, int max_outer, bt_info* info,
     if (hany == 0 || outer >= max_outer) break;
     hipLaunchKernelGGL((k_mr_tohat<NB>), dim3(a.R, a.nrhs / CPB), dim3(256),
                        0, s, a, r64);
-    if (precond<NB>(a, s) != hipSuccess) return BT_EHIP;
+    if (precond<NB>(a, s, false) != hipSuccess) return BT_EHIP;
     hipLaunchKernelGGL((k_mr_colsum<SUM_RHO>), dim3(a.nrhs), dim3(256), 0, s, a);
     for (int it = 0;; ++it) {
       if ((it & 7) == 7) {
         if (!read_any(&hany)) return BT_EHIP;
         if (hany == 0) break;
       }
-      if (inner_iteration<NB>(a, s, grid_ew) != hipSuccess) return BT_EHIP;
-      if (precond<NB>(a, s) != hipSuccess) return BT_EHIP;
+      if (inner_iteration<NB>(a, s) != hipSuccess) return BT_EHIP;
+      if (precond<NB>(a, s, true) != hipSuccess) return BT_EHIP;
       hipLaunchKernelGGL((k_mr_colsum<SUM_RHO>), dim3(a.nrhs), dim3(256), 0, s, a);
     }
     hipLaunchKernelGGL((k_mr_xupd<NB>), dim3(a.R, a.nrhs / CPB), dim3(256),
@@ -580,11 +607,11 @@ int solve(const MrArgs& a0, double* r64, int max_outer, bt_info* info,
 
 }  // namespace btm
 
-// Bytes of scratch for a multi-RHS solve: seven float32 panels, the float64
+// Bytes of scratch for a multi-RHS solve: nine float32 panels, the float64
 // residual panel, per-row partial sums and per-column state.
 size_t bt_mrhs_scratch_bytes(int64_t R, int n, int nrhs) {
   const size_t pn = (size_t)R * n * nrhs;
-  return 7 * pn * sizeof(float) + pn * sizeof(double) +
+  return 9 * pn * sizeof(float) + pn * sizeof(double) +
          (size_t)R * nrhs * sizeof(double) + 6 * (size_t)nrhs * sizeof(double) +
          8 * (size_t)nrhs * sizeof(int) + 256;
 }
@@ -628,7 +655,9 @@ int bt_mrhs_run(int64_t R, int n, int nrhs, const unsigned short* Fhi,
   a.y0 = f + 4 * pn;
   a.w = f + 5 * pn;
   a.z = f + 6 * pn;
-  double* r64 = (double*)(f + 7 * pn);
+  a.p2 = f + 7 * pn;
+  a.r2 = f + 8 * pn;
+  double* r64 = (double*)(f + 9 * pn);
   a.part = r64 + pn;
   double* cs = a.part + (size_t)R * nrhs;
   a.rho = cs;
