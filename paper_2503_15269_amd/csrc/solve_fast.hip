@@ -218,11 +218,14 @@ struct Ctx {
     for (int e = 0; e < EPT; ++e) y[e] = -acc[e];
   }
 
+  // ``on``: this wavefront's system still iterates (wavefront-uniform); the
+  // barrier is always taken, the arithmetic only when needed.
   template <int BUF>
-  __device__ __forceinline__ void C(const float (&v)[EPT], float (&y)[EPT]) {
-    prep<BUF>(v);
+  __device__ __forceinline__ void C(const float (&v)[EPT], float (&y)[EPT],
+                                    bool on = true) {
+    if (on) prep<BUF>(v);
     __syncthreads();
-    finish<BUF>(y);
+    if (on) finish<BUF>(y);
   }
 
   // ---- reductions --------------------------------------------------------
@@ -242,15 +245,22 @@ struct Ctx {
     sf = (sf + 1) % SL;
     return uni(v.lane(0).value());
   }
+  __device__ __forceinline__ double take_if(bool on) {  // after the barrier
+    if (on) return take();
+    sf = (sf + 1) % SL;  // keep the slot rotation in step with the others
+    return 0.0;
+  }
   __device__ __forceinline__ double dot(const float (&x)[EPT],
-                                        const float (&y)[EPT]) {
-    AccF acc;
-    acc.zero();
+                                        const float (&y)[EPT], bool on = true) {
+    if (on) {
+      AccF acc;
+      acc.zero();
 #pragma unroll
-    for (int e = 0; e < EPT; ++e) acc.add_prod(x[e], y[e]);
-    put_wave(acc);
+      for (int e = 0; e < EPT; ++e) acc.add_prod(x[e], y[e]);
+      put_wave(acc);
+    }
     __syncthreads();
-    return take();
+    return take_if(on);
   }
   __device__ __forceinline__ double sumd(double v) {
     AccD a;
@@ -294,7 +304,8 @@ struct Ctx {
   __device__ __forceinline__ void precond_rest(const SolveArgs& a,
                                                const float (&r)[EPT],
                                                const float (&cr)[EPT],
-                                               float (&z)[EPT]) {
+                                               float (&z)[EPT],
+                                               bool on = true) {
     float y[EPT], w[EPT];
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
@@ -303,8 +314,8 @@ struct Ctx {
     }
 #pragma unroll
     for (int m = 1; m < M; ++m) {
-      C<0>(y, w);
-      C<1>(w, y);
+      C<0>(y, w, on);
+      C<1>(w, y, on);
       const float al = (float)a.alpha[m];
 #pragma unroll
       for (int e = 0; e < EPT; ++e) z[e] = __fmaf_rn(al, y[e], z[e]);
@@ -506,8 +517,8 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
       // z = M^{-1} r for the inner right-hand side
       {
         float cr[EPT];
-        c.template C<1>(r, cr);
-        c.template precond_rest<M>(a, r, cr, z);
+        c.template C<1>(r, cr, !done);
+        c.template precond_rest<M>(a, r, cr, z, !done);
       }
       // Inner PCG, arranged so that each iteration has two reductions and
       // five barriers: rho = r'z shares its barrier with the staging of z,
@@ -524,15 +535,19 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
         qv[e] = 0.f;
       }
       for (;;) {
-        AccF acc;
-        acc.zero();
+        // a system that has stopped keeps taking the barriers (with its
+        // bin) but no longer does arithmetic
+        if (act) {
+          AccF acc;
+          acc.zero();
 #pragma unroll
-        for (int e = 0; e < EPT; ++e) acc.add_prod(r[e], z[e]);
-        c.template prep<0>(z);
-        c.put_wave(acc);
+          for (int e = 0; e < EPT; ++e) acc.add_prod(r[e], z[e]);
+          c.template prep<0>(z);
+          c.put_wave(acc);
+        }
         c.put_flag(act);
         __syncthreads();
-        const double rho1 = c.take();
+        const double rho1 = c.take_if(act);
         if (!c.any_after_barrier()) break;
         if (act) {
           if (!(rho1 > 0.0)) act = false;
@@ -541,7 +556,7 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
           if (total >= a.maxit) act = false;
         }
         float u[EPT];
-        c.template finish<0>(u);
+        if (act) c.template finish<0>(u);
 #pragma unroll
         for (int e = 0; e < EPT; ++e) u[e] = z[e] - u[e];
         if (act) {
@@ -554,7 +569,7 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
           rho = rho1;
         }
         first = false;
-        const double sigma = c.dot(p, qv);
+        const double sigma = c.dot(p, qv, act);
         if (act && !(sigma > 0.0)) act = false;
         if (act) {
           const float al = (float)(rho / sigma);
@@ -567,8 +582,8 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
           ++total;
         }
         float cr[EPT];
-        c.template C<1>(r, cr);
-        c.template precond_rest<M>(a, r, cr, z);
+        c.template C<1>(r, cr, act);
+        c.template precond_rest<M>(a, r, cr, z, act);
       }
       // x64 += L^{-T} d
       {
