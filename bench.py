@@ -498,6 +498,14 @@ def main():
     torch.cuda.synchronize()
     batched_f64 = 3 * B / (time.perf_counter() - t1)
     it64 = bt.infos_to_numpy(i64)
+    # the direct method of Section IV-C on the same batch and GPU: batched
+    # block Cholesky (float64, no setup beyond its own factorisation)
+    xd, idd = h.solve_direct(b)
+    torch.cuda.synchronize()
+    direct_ms = _events_ms(lambda: h.solve_direct(b, x=xd, info=idd), 5)
+    dinf = bt.infos_to_numpy(idd)
+    direct_ok = bool(np.all(dinf["status"] == bt.OK))
+    direct_diff = float(((xd - x).norm() / x.norm()).item())
 
     secondary = (None if args.no_workloads
                  else workloads_secondary(bt, torch, dev))
@@ -546,6 +554,10 @@ def main():
             "f64_iters_mean": float(it64["iters"].mean()),
             "speedup_vs_plain_f64": value / plain_f64,
             "speedup_vs_batched_f64": value / batched_f64,
+            "direct_block_cholesky_solves_per_s": (B * 1e3 / direct_ms
+                                                   if direct_ok else None),
+            "direct_block_cholesky_ms": direct_ms,
+            "direct_vs_pcg_rel_diff": direct_diff,
             "workloads": secondary,
         },
     }

@@ -191,6 +191,22 @@ int bt_solve_mrhs(const bt_handle* h, int nrhs, const double* b, double* x,
                   double tol, int maxit, bt_info* info, void* scratch,
                   size_t scratch_bytes, void* stream);
 
+/* Direct solve by block Cholesky (block Thomas, Section IV-C: the
+ * O(N n^3) sequential-in-N method the paper weighs PCG against), for every
+ * instance of the handle, in float64 from the system of record:
+ * S_0 = D_0, S_k = D_k - M_k M_k^T, L_k = chol(S_k), M_k = O_{k-1}^T
+ * L_{k-1}^{-T}; forward and backward substitution. Independent of the
+ * preconditioner parameters; n <= 16. b, x: device [R][n] float64. info:
+ * device, B entries (status BT_OK or BT_ENOTSPD with fail_index = the block
+ * row whose Schur complement is not positive definite; iters = 0; relres
+ * fields NaN, not computed). scratch: device, >= bt_direct_workspace_bytes
+ * (the factors L_k and M_k, 2 R n^2 float64). Asynchronous on the stream.
+ * Errors: BT_EINVAL (n > 16, NULL pointers), BT_ENOSPACE, BT_EHIP. */
+size_t bt_direct_workspace_bytes(const bt_handle* h);
+int bt_solve_direct(const bt_handle* h, const double* b, double* x,
+                    bt_info* info, void* scratch, size_t scratch_bytes,
+                    void* stream);
+
 /* Kernel configurations for the solve (workgroup size x vector elements per
  * thread), for the autotuner. bt_kernel_config_count() entries; entry i has
  * threads nt[i], elements per thread s[i] and iteration precision prec[i].

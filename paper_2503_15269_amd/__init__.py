@@ -72,6 +72,8 @@ def load_library(path: str = LIB_PATH):
         "bt_solve_batched": (I, [P, P, P, Dd, I, P, P]),
         "bt_solve_adjoint": (I, [P, P, P, P, P, P, Dd, I, P, P]),
         "bt_mrhs_workspace_bytes": (Sz, [P, I]),
+        "bt_direct_workspace_bytes": (Sz, [P]),
+        "bt_solve_direct": (I, [P, P, P, P, P, Sz, P]),
         "bt_solve_mrhs": (I, [P, I, P, P, Dd, I, P, P, Sz, P]),
         "bt_kernel_config_count": (I, []),
         "bt_kernel_config": (I, [I, ctypes.POINTER(I), ctypes.POINTER(I),
@@ -94,6 +96,7 @@ def exported_symbols():
             "bt_batch_setup", "bt_setup", "bt_refactor", "bt_precondition",
             "bt_solve", "bt_solve_batched", "bt_solve_adjoint",
             "bt_mrhs_workspace_bytes", "bt_solve_mrhs",
+            "bt_direct_workspace_bytes", "bt_solve_direct",
             "bt_kernel_config_count", "bt_kernel_config",
             "bt_set_kernel_config", "bt_get_kernel_config", "bt_destroy"]
 
@@ -322,6 +325,27 @@ class Handle:
                                _stream(torch, stream))
         _check(rc, "bt_solve_mrhs")
         return X, info
+
+    def solve_direct(self, b, x=None, info=None, scratch=None, stream=None):
+        """x = A^{-1} b for every system by block Cholesky (float64, no
+        preconditioner, no iteration); n <= 16. Returns (x, info)."""
+        torch = _torch()
+        b = self._vec(b, "b")
+        lib = load_library()
+        nbytes = lib.bt_direct_workspace_bytes(self._h)
+        if nbytes == 0:
+            raise BtError(EINVAL, "bt_direct_workspace_bytes")
+        if scratch is None:
+            scratch = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if x is None:
+            x = torch.empty_like(b)
+        if info is None:
+            info = torch.empty(self.B * INFO_DTYPE.itemsize, dtype=torch.uint8,
+                               device=self.device)
+        _check(lib.bt_solve_direct(self._h, _ptr(b), _ptr(x), _ptr(info),
+                                   _ptr(scratch), scratch.numel(),
+                                   _stream(torch, stream)), "bt_solve_direct")
+        return x, info
 
     def precondition(self, r, z=None, stream=None):
         torch = _torch()

@@ -454,6 +454,22 @@ int bt_solve_mrhs(const bt_handle* h, int nrhs, const double* b, double* x,
                      scratch, info, (hipStream_t)stream);
 }
 
+size_t bt_direct_workspace_bytes(const bt_handle* h) {
+  if (!h || !bt_direct_supported(h->n)) return 0;
+  return bt_direct_scratch_bytes(h->R, h->n);
+}
+
+int bt_solve_direct(const bt_handle* h, const double* b, double* x,
+                    bt_info* info, void* scratch, size_t scratch_bytes,
+                    void* stream) {
+  if (!h || !b || !x || !info || !scratch) return BT_EINVAL;
+  if (!bt_direct_supported(h->n)) return BT_EINVAL;
+  if (scratch_bytes < bt_direct_scratch_bytes(h->R, h->n)) return BT_ENOSPACE;
+  return hip_status(bt_launch_direct(h->B, h->n, h->dtype, h->off, h->order,
+                                     h->D, h->O, b, x, info, h->R, scratch,
+                                     (hipStream_t)stream));
+}
+
 int bt_kernel_config_count(void) { return num_configs(); }
 
 int bt_kernel_config(int i, int* nt, int* s, int* prec) {

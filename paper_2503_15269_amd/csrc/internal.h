@@ -112,6 +112,12 @@ int bt_mrhs_run(int64_t R, int n, int nrhs, const unsigned short* Fhi,
                 const void* O, int dtype, const double* b, double* x,
                 double tol, int maxit, int max_outer, double inner_tol, int m,
                 double alpha1, void* scratch, bt_info* info, hipStream_t s);
+size_t bt_direct_scratch_bytes(int64_t R, int n);
+bool bt_direct_supported(int n);
+hipError_t bt_launch_direct(int B, int n, int dtype, const int64_t* off,
+                            const int32_t* order, const void* D, const void* O,
+                            const double* b, double* x, bt_info* info,
+                            int64_t R, void* scratch, hipStream_t s);
 hipError_t bt_launch_adjoint_outer(int B, int n, int64_t R,
                                    const int64_t* off, const int32_t* rowinst,
                                    const double* x,

@@ -1,0 +1,85 @@
+"""Batched block-Cholesky direct solve (bt_solve_direct) against the oracle's
+block Cholesky, on ragged batches, float32 and float64 records, several
+block sizes, and a system whose Schur complement is not positive definite."""
+import numpy as np
+import pytest
+
+import lqrgen
+import oracle as orc
+import paper_2503_15269_amd as bt
+from gpu_util import rel, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu(oracle_lib):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    bt.load_library()
+
+
+def run(data, record="f32"):
+    import torch
+    dt = torch.float32 if record == "f32" else torch.float64
+    h = bt.Handle(to_dev(data["D"], dt), to_dev(data["O"], dt),
+                  data["offsets"], bt.Params.polycoeff(2, prec="f32_ir"
+                                                       if record == "f32"
+                                                       else "f64"))
+    x, info = h.solve_direct(to_dev(data["b"].reshape(-1), torch.float64))
+    torch.cuda.synchronize()
+    n = data["D"].shape[1]
+    return x.cpu().numpy().reshape(-1, n), bt.infos_to_numpy(info)
+
+
+@pytest.mark.parametrize("n,record", [(12, "f32"), (12, "f64"), (6, "f64"),
+                                      (16, "f32"), (5, "f64")])
+def test_direct_matches_oracle(n, record):
+    data = lqrgen.lqr_batch(37, (1, 90), n, max(1, n // 3), seed=600 + n,
+                            record=record)
+    x, info = run(data, record)
+    assert np.all(info["status"] == bt.OK)
+    for i, rows, oblk in orc.batch_slices(data["offsets"]):
+        xd = orc.btchol_solve(data["D"][rows], data["O"][oblk], data["b"][rows])
+        assert rel(x[rows], xd) <= 1e-11, (i, rel(x[rows], xd))
+
+
+def test_direct_full_ragged_batch_sampled():
+    d = lqrgen.WORKLOADS["batch_ragged_n12"]
+    data = lqrgen.lqr_batch(d["B"], d["N"], d["nx"], d["nu"],
+                            lqrgen.workload_seed(d["index"]), s=d["s"],
+                            record=d["record"])
+    x, info = run(data, "f32")
+    assert np.all(info["status"] == bt.OK)
+    rng = np.random.default_rng(1)
+    for i in rng.choice(d["B"], 16, replace=False):
+        r0, r1 = int(data["offsets"][i]), int(data["offsets"][i + 1])
+        xd = orc.btchol_solve(data["D"][r0:r1], data["O"][r0 - i:r1 - i - 1],
+                              data["b"][r0:r1])
+        assert rel(x[r0:r1], xd) <= 1e-11
+
+
+def test_direct_reports_indefinite_schur_block():
+    data = lqrgen.lqr_batch(5, (10, 20), 6, 2, seed=61)
+    D = data["D"].copy()
+    r0 = int(data["offsets"][3])
+    D[r0 + 4] -= 1e3 * np.eye(6)        # system 3, row 4 (first failing block)
+    d2 = dict(data, D=D)
+    x, info = run(d2, "f64")
+    assert info[3]["status"] == bt.ENOTSPD and info[3]["fail_index"] == 4
+    with pytest.raises(np.linalg.LinAlgError, match="block 4"):
+        rows = slice(r0, int(data["offsets"][4]))
+        orc.btchol_solve(D[rows], data["O"][r0 - 3:int(data["offsets"][4]) - 4],
+                         data["b"][rows])
+    for i in (0, 1, 2, 4):
+        assert info[i]["status"] == bt.OK
+
+
+def test_direct_argument_checks():
+    import torch
+    d = lqrgen.lqr_instance(4, 20, 5, 1, 0)
+    h = bt.Handle(to_dev(d["D"], torch.float64), to_dev(d["O"], torch.float64),
+                  None, bt.Params.polycoeff(2))
+    with pytest.raises(bt.BtError):      # n = 20 > 16
+        h.solve_direct(to_dev(d["b"].reshape(-1), torch.float64))
