@@ -20,6 +20,7 @@ relative, so the tolerance is 1e-6 / sqrt(N n), the expected norm of a
 standard normal right-hand side (their norms spread by a few per cent).
 
 Run: python -m paper_2503_15269_amd.fig2 [--matrices 100] [--rhs 100]
+     python -m paper_2503_15269_amd.fig2 --alpha-search 2   (alpha grid)
 """
 from __future__ import annotations
 
@@ -147,6 +148,50 @@ def run(matrices=100, rhs=100, N=30, n=20, nu=7, ms=(1, 2, 3, 4),
                 eig_matrices=eig_matrices, tol_rel=tol, rows=rows)
 
 
+def alpha_search(alphas=(1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 12, 15), m=2,
+                 matrices=20, rhs=20, N=30, n=20, nu=7, seed=20250502):
+    """Grid search of the last polynomial coefficient alpha_{m-1} at the
+    optimal weights (the search behind the Section V footnote): mean PCG
+    iterations and gemvs on the same random systems for each value (the
+    other coefficients 1). Returns [(alpha, iters_mean, gemv_mean)]."""
+    import torch
+
+    import lqrgen
+    import paper_2503_15269_amd as bt
+    from . import Handle, infos_to_numpy, OK
+
+    dev = torch.device("cuda:0")
+    insts = [lqrgen.lqr_instance(N, n, nu, seed, i, nrhs=rhs)
+             for i in range(matrices)]
+    offs = np.arange(matrices * rhs + 1, dtype=np.int64) * N
+    D_t = torch.tensor(np.stack([d["D"] for d in insts]), dtype=torch.float64,
+                       device=dev).repeat_interleave(rhs, dim=0)
+    O_t = torch.tensor(np.stack([d["O"] for d in insts]), dtype=torch.float64,
+                       device=dev).repeat_interleave(rhs, dim=0)
+    D_t = D_t.reshape(-1, n, n).contiguous()
+    O_t = O_t.reshape(-1, n, n).contiguous()
+    bb = np.stack([np.transpose(d["b"], (2, 0, 1)) for d in insts])
+    b_t = torch.tensor(bb.reshape(-1), dtype=torch.float64, device=dev)
+    tol = 1e-6 / np.sqrt(N * n)
+    out = []
+    for al in alphas:
+        alpha = [1.0] * m
+        if m > 1:
+            alpha[m - 1] = float(al)
+        P = bt.Params(a=1.0, b=-1.0, m=m, alpha=alpha, prec="f64")
+        h = Handle(D_t, O_t, offs, P)
+        x, info = h.solve(b_t, tol)
+        torch.cuda.synchronize()
+        inf = infos_to_numpy(info)
+        its = inf["iters"].astype(np.float64)
+        ok = bool(np.all(inf["status"] == OK))
+        out.append((float(al), float(its.mean()) if ok else float("nan"),
+                    float(its.mean()) * gemv_per_iteration(1.0, m)
+                    if ok else float("nan")))
+        del h, x
+    return out
+
+
 def markdown(res):
     out = [f"N = {res['N']}, n = {res['n']}, nu = {res['nu']}; "
            f"{res['matrices']} matrices x {res['rhs']} right-hand sides per "
@@ -169,7 +214,17 @@ def main():
     ap.add_argument("--rhs", type=int, default=100)
     ap.add_argument("--eig-matrices", type=int, default=5)
     ap.add_argument("--json", action="store_true")
+    ap.add_argument("--alpha-search", type=int, default=0, metavar="M",
+                    help="instead: grid search of alpha_{M-1} at order M")
     args = ap.parse_args()
+    if args.alpha_search:
+        m = args.alpha_search
+        rows = alpha_search(m=m)
+        print(f"| alpha_{m - 1} | PCG iterations (mean) | block gemvs |")
+        print("|---|---|---|")
+        for al, it, gv in rows:
+            print(f"| {al:g} | {it:.2f} | {gv:.1f} |")
+        return
     res = run(matrices=args.matrices, rhs=args.rhs,
               eig_matrices=args.eig_matrices, verbose=args.json)
     print(markdown(res))
