@@ -77,7 +77,8 @@ Layout layout(int B, int64_t R, int n, size_t es, bool split) {
   l.F = at; at += blk;
   l.L = at; at += blk;
   l.Li = at; at += blk;
-  const size_t hblk = split ? align_up(2 * (size_t)R * n * n) : 0;
+  // bfloat16 splits of F and of the transposed blocks
+  const size_t hblk = split ? align_up(2 * 2 * (size_t)R * n * n) : 0;
   l.Fhi = at; at += hblk;
   l.Flo = at; at += hblk;
   l.total = at;
@@ -182,8 +183,8 @@ int launch_setup(const bt_handle* h, hipStream_t s, bool full) {
   if (bt_launch_setup(a, s) != hipSuccess) return BT_EHIP;
   h->full_valid = full;
   if (h->Fhi)
-    return hip_status(bt_mrhs_split((const float*)h->F, h->Fhi, h->Flo,
-                                    (size_t)h->R * h->n * h->n, s));
+    return hip_status(
+        bt_mrhs_split((const float*)h->F, h->Fhi, h->Flo, h->R, h->n, s));
   return BT_OK;
 }
 

@@ -32,8 +32,8 @@ struct bt_handle {
   void* F = nullptr;        // [R][n][n] scaled off-diagonal blocks
   void* L = nullptr;        // [R][n][n] Cholesky factors of D_k
   void* Li = nullptr;       // [R][n][n] their inverses
-  unsigned short* Fhi = nullptr;  // BT_BF16X2_IR: F split into bfloat16 pairs
-  unsigned short* Flo = nullptr;
+  unsigned short* Fhi = nullptr;  // BT_BF16X2_IR: [2][R][n][n], F then F^T
+  unsigned short* Flo = nullptr;  // blockwise, split into bfloat16 hi + lo
   int cfg = -1;             // solve-kernel configuration, -1 = automatic
   // L is current (the register-resident kernel does not read it; for the
   // other kernels it is computed on first use)
@@ -106,7 +106,7 @@ hipError_t bt_launch_setup_init(int B, int32_t* fail, int32_t* ctr,
                                 hipStream_t s);
 size_t bt_mrhs_scratch_bytes(int64_t R, int n, int nrhs);
 hipError_t bt_mrhs_split(const float* F, unsigned short* hi, unsigned short* lo,
-                         size_t N, hipStream_t s);
+                         int64_t R, int n, hipStream_t s);
 int bt_mrhs_run(int64_t R, int n, int nrhs, const unsigned short* Fhi,
                 const unsigned short* Flo, const float* Li, const void* D,
                 const void* O, int dtype, const double* b, double* x,

@@ -15,21 +15,22 @@
 // One inner iteration (m = 2 shown; the polynomial follows eq. Mminv-poly-
 // nomial-coefficients at a = 1: y_0 = r + C r, y_i = C(C y_{i-1}))
 //   p = z + beta p, q = p - C p,
-//     sigma = p'q partials                  k_mr_app<EPI_QU>
+//     sigma = p'q partials                  k_mr_qu
 //   alpha = rho / sigma                     k_mr_colsum<SIGMA>
 //   r = r - alpha q, d += alpha p,
-//     y0 = r + C r                          k_mr_app<EPI_Y0U>
-//   w = C y0                                k_mr_app<EPI_W>
-//   z = y0 + alpha_1 C w, rho = r'z parts   k_mr_app<EPI_Z>
+//     y0 = r + C r, w = C y0,
+//     z = y0 + alpha_1 C w, rho = r'z parts k_mr_post
 //   beta, stopping test                     k_mr_colsum<RHO>
 // The vector updates are fused into the products: a workgroup forms the
-// updated p (or r) of its own row and of both neighbour rows from the old
+// updated p (or r) of its own row and of the neighbour rows from the old
 // values, so p and r alternate between two panels (the neighbours' old
-// values must survive until every workgroup has read them). Workgroups are
-// mapped to rows so that each XCD gets a contiguous range of block rows and
-// the neighbour rows' data is shared in its L2. Converged right-hand sides
-// no longer update; a workgroup whose columns have all stopped returns at
-// once. The host checks every few iterations whether any is left.
+// values must survive until every workgroup has read them), and k_mr_post
+// recomputes the y0 and w rows its z row depends on instead of storing them.
+// Workgroups are mapped to rows so that each XCD gets a contiguous range of
+// block rows and the neighbour rows' data is shared in its L2. Converged
+// right-hand sides no longer update; a workgroup whose columns have all
+// stopped returns at once. The host checks every few iterations whether any
+// is left.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -44,6 +45,14 @@ typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int WG = 256;       // 4 wavefronts, 16 right-hand sides each
+// A block in LDS: rows of NB + 4 entries (the padding spreads the 16 rows a
+// wavefront reads at once over distinct banks), hi half then lo half.
+template <int NB>
+struct Lds {
+  static constexpr int LDR = NB + 4;    // row stride (bfloat16 entries)
+  static constexpr int HS = NB * LDR;   // one half
+  static constexpr int BLK = 2 * HS;    // one block
+};
 constexpr int CPW = 16;       // columns per wavefront
 constexpr int CPB = 64;       // columns per workgroup
 
@@ -57,19 +66,19 @@ __device__ __forceinline__ float bf2f(unsigned short h) {
   return __uint_as_float((unsigned)h << 16);
 }
 
-enum { EPI_QU = 0, EPI_Y0 = 1, EPI_W = 2, EPI_Z = 3, EPI_Y0U = 4 };
-
 struct MrArgs {
   int R, n, nrhs;
-  const unsigned short* Fhi;  // [R][n][n]
+  const unsigned short* Fhi;  // [R][n][n] bfloat16 split of F_k
   const unsigned short* Flo;
+  const unsigned short* Ghi;  // [R][n][n] the same for G_k = F_k^T
+  const unsigned short* Glo;
   const float* Li;            // [R][n][n]
   const void* D;              // record
   const void* O;
   int dtype;
   const double* b;            // [R][n][nrhs]
   double* x;
-  float *p, *q, *r, *d, *y0, *w, *z;  // panels [R][n][nrhs]
+  float *p, *q, *r, *d, *z;   // panels [R][n][nrhs]
   float *p2, *r2;             // second panels of p and r (alternating)
   double* part;               // [R][nrhs] per-row partial sums
   // per right-hand-side state
@@ -82,162 +91,393 @@ struct MrArgs {
 };
 
 // ---------------------------------------------------------------------------
-// Y = C V on the matrix cores, with an epilogue. Grid (8 ceil(R / 8),
-// nrhs / 64); block b works on row (b mod 8) ceil(R / 8) + b / 8, so that the
-// workgroups of one XCD (dispatched round-robin) cover consecutive rows.
-// For EPI_QU and EPI_Y0U the operand is an update formed on the fly:
-//   QU:  V = p_new = z + beta p   (V1 = z, V2 = p old, out2 = p new)
-//   Y0U: V = r_new = r - alpha q  (V1 = r old, V2 = q, out2 = r new)
-// (for a column that has stopped the operand is the old value, unchanged).
+// Matrix-core building blocks. A 16 x 16 tile of a product is accumulated by
+// v_mfma_f32_16x16x16_bf16: lane l holds rows 4 (l / 16) + i (i = 0..3) of
+// column l mod 16 of the accumulator, and the B operand of a K step wants
+// exactly those rows of the same column, so the result of one product feeds
+// the next one without data movement. Pan<NB> is one block row of a panel
+// in that layout (16 columns per wavefront); Spl<NB> the same entries split
+// x = hi + lo into bfloat16, so a product is hi*hi + hi*lo + lo*hi. The A
+// operand (a block) is read from LDS as 4 consecutive entries of a row, so
+// products with F_k^T use the stored transposed blocks G_k.
 // ---------------------------------------------------------------------------
+template <int NB>
+struct Pan {
+  f32x4 v[NB / 16];  // rows 16 t + 4 (l / 16) + i of column l mod 16
+};
+
+template <int NB>
+struct Spl {
+  bf16x4 h[NB / 16], lo[NB / 16];
+};
+
+template <int NB>
+__device__ __forceinline__ Spl<NB> split(const Pan<NB>& p) {
+  Spl<NB> s;
+#pragma unroll
+  for (int t = 0; t < NB / 16; ++t)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const __bf16 h = (__bf16)p.v[t][i];  // round to nearest even
+      const __bf16 lo = (__bf16)(p.v[t][i] - (float)h);
+      s.h[t][i] = __builtin_bit_cast(short, h);
+      s.lo[t][i] = __builtin_bit_cast(short, lo);
+    }
+  return s;
+}
+
+// hi*hi + hi*lo + lo*hi into acc for one K step of 16 (A: 4 entries of the
+// block row in LDS at ``e``, hi and lo halves HS apart)
+template <int HS>
+__device__ __forceinline__ f32x4 mma16(const unsigned short* A, int e,
+                                       bf16x4 bh, bf16x4 bl, f32x4 acc) {
+  const bf16x4 ah = *reinterpret_cast<const bf16x4*>(A + e);
+  const bf16x4 al = *reinterpret_cast<const bf16x4*>(A + HS + e);
+  acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
+}
+
+template <int NB, bool HM, bool HP>
+__device__ __forceinline__ void cprod_t(const unsigned short* Am,
+                                        const Spl<NB>& Vm,
+                                        const unsigned short* Ap,
+                                        const Spl<NB>& Vp, int l,
+                                        f32x4 (&acc)[NB / 16]) {
+  constexpr int MT = NB / 16, LDR = Lds<NB>::LDR, HS = Lds<NB>::HS;
+  const int kq = 4 * (l >> 4);  // first K row of this lane in a K step
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ks = 0; ks < MT; ++ks) {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int e = (16 * mt + (l & 15)) * LDR + 16 * ks + kq;  // 8-byte aligned
+      if constexpr (HP) acc[mt] = mma16<HS>(Ap, e, Vp.h[ks], Vp.lo[ks], acc[mt]);
+      if constexpr (HM) acc[mt] = mma16<HS>(Am, e, Vm.h[ks], Vm.lo[ks], acc[mt]);
+    }
+  }
+}
+
+// acc = [Am V_m] + [Ap V_p], each term only if its (wavefront-uniform) flag
+// is set; Am and Ap point at row-major blocks in LDS (Lds<NB> layout). With Am = G_{j-1} = F_{j-1}^T, Ap = F_j and V_m, V_p
+// the rows j -+ 1 this is -(C V)_j.
+template <int NB>
+__device__ __forceinline__ void cprod(bool hm, const unsigned short* Am,
+                                      const Spl<NB>& Vm, bool hp,
+                                      const unsigned short* Ap,
+                                      const Spl<NB>& Vp, int l,
+                                      f32x4 (&acc)[NB / 16]) {
+  if (hm && hp) cprod_t<NB, true, true>(Am, Vm, Ap, Vp, l, acc);
+  else if (hp) cprod_t<NB, false, true>(Am, Vm, Ap, Vp, l, acc);
+  else if (hm) cprod_t<NB, true, false>(Am, Vm, Ap, Vp, l, acc);
+  else cprod_t<NB, false, false>(Am, Vm, Ap, Vp, l, acc);
+}
+
+// Grid (8 ceil(R / 8), nrhs / 64); block b works on row (b mod 8) ceil(R / 8)
+// + b / 8, so that the workgroups of one XCD (dispatched round-robin) cover
+// consecutive rows.
 __device__ __forceinline__ int xcd_row(int b, int R) {
   const int chunk = (R + 7) / 8;
   return (b & 7) * chunk + (b >> 3);
 }
 
-template <int EPI>
-__device__ __forceinline__ float operand(const MrArgs& a, const float* V1,
-                                         const float* V2, size_t idx, int col,
-                                         bool act) {
-  if constexpr (EPI == EPI_QU) {
-    return act ? __fmaf_rn((float)a.beta[col], V2[idx], V1[idx]) : V2[idx];
-  } else if constexpr (EPI == EPI_Y0U) {
-    return act ? __fmaf_rn(-(float)a.alpha[col], V2[idx], V1[idx]) : V1[idx];
-  } else {
-    return V1[idx];
+// NS blocks of split arrays on their way to LDS: all global loads are issued
+// first (into registers), then written into the Lds<NB> layout, so a
+// workgroup waits for memory once. 16-byte pieces of 8 entries (NB is a
+// multiple of 8). A block index outside [0, R - 2] is clamped: that slot is
+// then never read.
+template <int NB, int NS>
+struct Blocks {
+  static constexpr int NN = NB * NB, NC = NN / 8, PER = (NC + WG - 1) / WG;
+  uint4 vh[NS * PER], vl[NS * PER];
+
+  __device__ __forceinline__ void load(const MrArgs& a, int s,
+                                       const unsigned short* hi,
+                                       const unsigned short* lo, int b) {
+    b = min(max(b, 0), max(a.R - 2, 0));
+    const uint4* sh = reinterpret_cast<const uint4*>(hi) + (size_t)b * NC;
+    const uint4* sl = reinterpret_cast<const uint4*>(lo) + (size_t)b * NC;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = min((int)threadIdx.x + q * WG, NC - 1);  // stored if < NC
+      vh[s * PER + q] = sh[e];
+      vl[s * PER + q] = sl[e];
+    }
   }
+  __device__ __forceinline__ void store(int s, unsigned short* dst) const {
+    constexpr int PR = NB / 8;  // pieces per row
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * WG;
+      if (NC % WG == 0 || e < NC) {
+        const int o = (e / PR) * Lds<NB>::LDR + 8 * (e % PR);  // 8-byte aligned
+        const uint4 h = vh[s * PER + q], w = vl[s * PER + q];
+        *reinterpret_cast<uint2*>(dst + o) = make_uint2(h.x, h.y);
+        *reinterpret_cast<uint2*>(dst + o + 4) = make_uint2(h.z, h.w);
+        *reinterpret_cast<uint2*>(dst + Lds<NB>::HS + o) = make_uint2(w.x, w.y);
+        *reinterpret_cast<uint2*>(dst + Lds<NB>::HS + o + 4) = make_uint2(w.z, w.w);
+      }
+    }
+  }
+};
+
+// Panel access through buffer instructions: a resource over block row j
+// ([n][nrhs] floats), the lane's column offset in a register and the row
+// offset inside the block as a scalar, so no per-access address arithmetic.
+struct PRow {
+  __amdgpu_buffer_rsrc_t rs;
+};
+
+template <int NB>
+__device__ __forceinline__ PRow prow(const float* X, int j, int ld) {
+  const float* base = X + (size_t)j * NB * ld;
+  return {__builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), 0,
+                                            NB * ld * 4, 0x00020000)};
 }
 
-template <int NB, int EPI>
-__global__ void __launch_bounds__(WG) k_mr_app(MrArgs a, const float* V,
-                                              const float* V2, const float* aux,
-                                              float* out, float* out2) {
-  constexpr int MT = NB / 16;
-  constexpr int NN = NB * NB;
-  __shared__ __align__(16) unsigned short sFk[2][NN];   // hi, lo of F_k
-  __shared__ __align__(16) unsigned short sFm[2][NN];   // hi, lo of F_{k-1}
+// entry (16 tt + 4 (l / 16) + i, column) of the row; ``voff`` = byte offset
+// of the lane's first entry
+__device__ __forceinline__ float pld(PRow r, int voff, int ld, int tt, int i) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+      r.rs, voff, (16 * tt + i) * ld * 4, 0));
+}
+
+__device__ __forceinline__ void pst(PRow r, int voff, int ld, int tt, int i,
+                                    float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r.rs, voff,
+                                        (16 * tt + i) * ld * 4, 0);
+}
+
+// ---------------------------------------------------------------------------
+// p = z + beta p (new p of the row and both neighbours, formed on the fly),
+// q = p - C p = Ahat p, sigma = p'q partials. For a column that has stopped
+// p keeps its old value.
+// ---------------------------------------------------------------------------
+template <int NB>
+__global__ void __launch_bounds__(WG) k_mr_qu(MrArgs a, const float* pold,
+                                             float* pnew) {
+  constexpr int MT = NB / 16, BLK = Lds<NB>::BLK;
+  __shared__ __align__(16) unsigned short sF[2 * BLK];  // G_{k-1}, F_k
   const int k = xcd_row(blockIdx.x, a.R);
   if (k >= a.R) return;
-  const int t = threadIdx.x;
-  const int wv = t >> 6, l = t & 63;
-  const int c0 = blockIdx.y * CPB + wv * CPW;
-  const int col = c0 + (l & 15);
-  const int kq = 4 * (l >> 4);                 // k-offset of this lane
-  const bool has_prev = k > 0, has_next = k < a.R - 1;
+  const int t = threadIdx.x, l = t & 63;
+  const int col = blockIdx.y * CPB + (t >> 6) * CPW + (l & 15);
+  const int kq = 4 * (l >> 4);
   // nothing to do once every column of this workgroup has stopped (the host
   // only checks every few iterations)
   if (!__syncthreads_or(a.act[blockIdx.y * CPB + (t & 63)])) return;
+  const int ld = a.nrhs;
+  const int voff = 4 * (kq * ld + col);
+  const bool act = a.act[col] != 0;
+  const float be = (float)a.beta[col];
+  auto load = [&](int j) {
+    const PRow po = prow<NB>(pold, j, ld), zr = prow<NB>(a.z, j, ld);
+    Pan<NB> p;
+#pragma unroll
+    for (int tt = 0; tt < MT; ++tt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float pv = pld(po, voff, ld, tt, i);
+        const float pn = __fmaf_rn(be, pv, pld(zr, voff, ld, tt, i));
+        p.v[tt][i] = act ? pn : pv;
+      }
+    return p;
+  };
+  const bool hm = k > 0, hp = k < a.R - 1;
+  // panel rows first, then the blocks: one wait for memory
+  const Pan<NB> zero{};
+  const Pan<NB> pm = hm ? load(k - 1) : zero;
+  const Pan<NB> pp = hp ? load(k + 1) : zero;
+  const Pan<NB> p0 = load(k);
   {
-    // 16-byte loads of the bfloat16 halves (NN is a multiple of 8)
-    const uint4* fh = reinterpret_cast<const uint4*>(a.Fhi);
-    const uint4* fl = reinterpret_cast<const uint4*>(a.Flo);
-    constexpr int NC = NN / 8;
-    for (int e = t; e < NC; e += WG) {
-      if (has_next) {
-        reinterpret_cast<uint4*>(sFk[0])[e] = fh[(size_t)k * NC + e];
-        reinterpret_cast<uint4*>(sFk[1])[e] = fl[(size_t)k * NC + e];
-      }
-      if (has_prev) {
-        reinterpret_cast<uint4*>(sFm[0])[e] = fh[(size_t)(k - 1) * NC + e];
-        reinterpret_cast<uint4*>(sFm[1])[e] = fl[(size_t)(k - 1) * NC + e];
-      }
-    }
+    Blocks<NB, 2> blk;
+    blk.load(a, 0, a.Ghi, a.Glo, k - 1);
+    blk.load(a, 1, a.Fhi, a.Flo, k);
+    blk.store(0, sF);
+    blk.store(1, sF + BLK);
   }
   __syncthreads();
-  const int ld = a.nrhs;
-  const bool act = a.act[col] != 0;
+  const Spl<NB> sm = split(pm), sp = split(pp);
   f32x4 acc[MT];
-#pragma unroll
-  for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-  for (int ks = 0; ks < MT; ++ks) {
-    const int kr = 16 * ks + kq;  // first of the 4 K rows of this lane
-    if (has_next) {
-      bf16x4 bh, bl;
-      const size_t base = ((size_t)(k + 1) * NB + kr) * ld + col;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float v = operand<EPI>(a, V, V2, base + (size_t)i * ld, col, act);
-        const unsigned short h = f2bf(v);
-        bh[i] = (short)h;
-        bl[i] = (short)f2bf(v - bf2f(h));
-      }
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const int row = 16 * mt + (l & 15);
-        bf16x4 ah, al;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          ah[i] = (short)sFk[0][row * NB + kr + i];
-          al[i] = (short)sFk[1][row * NB + kr + i];
-        }
-        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[mt], 0, 0, 0);
-        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[mt], 0, 0, 0);
-        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[mt], 0, 0, 0);
-      }
-    }
-    if (has_prev) {
-      bf16x4 bh, bl;
-      const size_t base = ((size_t)(k - 1) * NB + kr) * ld + col;
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const float v = operand<EPI>(a, V, V2, base + (size_t)i * ld, col, act);
-        const unsigned short h = f2bf(v);
-        bh[i] = (short)h;
-        bl[i] = (short)f2bf(v - bf2f(h));
-      }
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt) {
-        const int mcol = 16 * mt + (l & 15);   // row of F^T = column of F
-        bf16x4 ah, al;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          ah[i] = (short)sFm[0][(kr + i) * NB + mcol];
-          al[i] = (short)sFm[1][(kr + i) * NB + mcol];
-        }
-        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[mt], 0, 0, 0);
-        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[mt], 0, 0, 0);
-        acc[mt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[mt], 0, 0, 0);
-      }
-    }
-  }
-  // epilogue: lane holds rows 16 mt + kq + i of column ``col``; C V = -acc
+  cprod<NB>(hm, sF, sm, hp, sF + BLK, sp, l, acc);
+  const PRow pw = prow<NB>(pnew, k, ld), qw = prow<NB>(a.q, k, ld);
   double dp = 0.0;
-  const float alc = (float)a.alpha[col];
 #pragma unroll
-  for (int mt = 0; mt < MT; ++mt) {
+  for (int tt = 0; tt < MT; ++tt)
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int row = 16 * mt + kq + i;
-      const size_t idx = ((size_t)k * NB + row) * ld + col;
-      const float cv = -acc[mt][i];
-      float o;
-      if constexpr (EPI == EPI_QU) {
-        const float pv = operand<EPI>(a, V, V2, idx, col, act);
-        out2[idx] = pv;                  // p new
-        o = pv - cv;                     // q = p - C p
-        dp += (double)pv * (double)o;    // sigma = p'q
-      } else if constexpr (EPI == EPI_Y0U) {
-        const float rv = operand<EPI>(a, V, V2, idx, col, act);
-        out2[idx] = rv;                  // r new
-        if (act) a.d[idx] = __fmaf_rn(alc, aux[idx], a.d[idx]);  // d += alpha p
-        o = rv + cv;                     // y0 = r + C r
-      } else if constexpr (EPI == EPI_Y0) {
-        o = aux[idx] + cv;               // y0 = r + C r
-      } else if constexpr (EPI == EPI_W) {
-        o = cv;                          // w = C y0
-      } else {
-        o = aux[idx] + (float)a.alpha1 * cv;  // z = y0 + alpha_1 C w
-        dp += (double)a.r[idx] * (double)o;   // rho = r'z
-      }
-      out[idx] = o;
+      const float pv = p0.v[tt][i];
+      const float o = pv + acc[tt][i];  // q = p - C p, C p = -acc
+      pst(pw, voff, ld, tt, i, pv);
+      pst(qw, voff, ld, tt, i, o);
+      dp += (double)pv * (double)o;
     }
+  dp += __shfl_xor(dp, 16);
+  dp += __shfl_xor(dp, 32);
+  if (l < 16) a.part[(size_t)k * ld + col] = dp;
+}
+
+// ---------------------------------------------------------------------------
+// Everything of an inner iteration after alpha, for one block row k:
+//   r' = r - alpha q and d += alpha p (UPD; r' = r otherwise),
+//   y0 = r' + C r',  w = C y0,  z = y0 + alpha_1 C w,  rho = r''z partials,
+// writing r' (UPD) and z of row k. z_k needs w at rows k +- 1, which need y0
+// at rows k - 2, k, k + 2, which need r' at rows k - 3 .. k + 3: the
+// workgroup recomputes these neighbour values itself (twice the matrix-core
+// work of separate passes for y0, w and z) so that y0 and w never leave the
+// registers and each panel is read once from memory. LDS holds six blocks:
+// G_{k-3}, F_{k-2}, G_{k-1}, F_k, G_{k+1}, F_{k+2} for the y0 rows, then
+// G_{k-2}, F_{k-1}, G_k, F_{k+1} replace the first, second, fifth and sixth
+// for the w rows; z uses G_{k-1}, F_k (for M = 1, z = y0 and only those two
+// are staged). Dynamic LDS: (M = 1 ? 2 : 6) blocks in the Lds<NB> layout.
+// ---------------------------------------------------------------------------
+template <int NB, int M, bool UPD>
+__global__ void __launch_bounds__(WG) k_mr_post(MrArgs a) {
+  constexpr int MT = NB / 16;
+  extern __shared__ __align__(16) unsigned short sF[];
+  auto S = [&](int slot) { return sF + slot * Lds<NB>::BLK; };
+  const int k = xcd_row(blockIdx.x, a.R);
+  if (k >= a.R) return;
+  const int t = threadIdx.x, l = t & 63;
+  const int col = blockIdx.y * CPB + (t >> 6) * CPW + (l & 15);
+  const int kq = 4 * (l >> 4);
+  if (!__syncthreads_or(a.act[blockIdx.y * CPB + (t & 63)])) return;
+  // slots for M = 2: 0 G_{k-3}, 1 F_{k-2}, 2 G_{k-1}, 3 F_k, 4 G_{k+1},
+  // 5 F_{k+2}; for M = 1 only G_{k-1}, F_k, in slots 0 and 1
+  constexpr int SG = M >= 2 ? 2 : 0;  // slot of G_{k-1}; F_k follows
+  const int ld = a.nrhs;
+  const int voff = 4 * (kq * ld + col);
+  const bool act = a.act[col] != 0;
+  const float al = UPD && act ? (float)a.alpha[col] : 0.f;
+  auto load = [&](int j) {  // r' of row j
+    const PRow rr = prow<NB>(a.r, j, ld);
+    Pan<NB> p;
+    if constexpr (UPD) {
+      const PRow qr = prow<NB>(a.q, j, ld);
+#pragma unroll
+      for (int tt = 0; tt < MT; ++tt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const float rv = pld(rr, voff, ld, tt, i);
+          const float rn = __fmaf_rn(-al, pld(qr, voff, ld, tt, i), rv);
+          p.v[tt][i] = act ? rn : rv;
+        }
+    } else {
+#pragma unroll
+      for (int tt = 0; tt < MT; ++tt)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) p.v[tt][i] = pld(rr, voff, ld, tt, i);
+    }
+    return p;
+  };
+  // y0 of row j from r' of row j and the split r' of rows j - 1, j + 1,
+  // with G_{j-1}, F_j in slots sg, sg + 1 (absent rows: flags off)
+  auto y0_of = [&](int j, int sg, const Spl<NB>& rm, const Pan<NB>& r0,
+                   const Spl<NB>& rp) {
+    f32x4 acc[MT];
+    cprod<NB>(j >= 1, S(sg), rm, j <= a.R - 2, S(sg + 1), rp, l, acc);
+    Pan<NB> y;
+#pragma unroll
+    for (int tt = 0; tt < MT; ++tt) y.v[tt] = r0.v[tt] - acc[tt];
+    return y;
+  };
+  const bool hm1 = k >= 1, hp1 = k <= a.R - 2;
+  const bool hm2 = M >= 2 && k >= 2, hp2 = M >= 2 && k + 2 <= a.R - 1;
+  const Pan<NB> zero{};
+  const Spl<NB> szero{};
+  // panel rows first, then the blocks: one wait for memory
+  const Pan<NB> r0 = load(k);
+  const Pan<NB> rm1 = hm1 ? load(k - 1) : zero;
+  const Pan<NB> rp1 = hp1 ? load(k + 1) : zero;
+  const Pan<NB> rm2 = hm2 ? load(k - 2) : zero;
+  const Pan<NB> rm3 = hm2 && k >= 3 ? load(k - 3) : zero;
+  const Pan<NB> rp2 = hp2 ? load(k + 2) : zero;
+  const Pan<NB> rp3 = hp2 && k + 3 <= a.R - 1 ? load(k + 3) : zero;
+  if constexpr (UPD) {  // r' and d += alpha p of the own row
+    const PRow rw = prow<NB>(a.r2, k, ld), dr = prow<NB>(a.d, k, ld),
+               pr = prow<NB>(a.p, k, ld);
+#pragma unroll
+    for (int tt = 0; tt < MT; ++tt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        pst(rw, voff, ld, tt, i, r0.v[tt][i]);
+        const float dv = pld(dr, voff, ld, tt, i);
+        const float dn = __fmaf_rn(al, pld(pr, voff, ld, tt, i), dv);
+        pst(dr, voff, ld, tt, i, act ? dn : dv);
+      }
   }
-  if constexpr (EPI == EPI_QU || EPI == EPI_Z) {
-    dp += __shfl_xor(dp, 16);
-    dp += __shfl_xor(dp, 32);
-    if (l < 16) a.part[(size_t)k * ld + col] = dp;
+  {
+    Blocks<NB, M >= 2 ? 6 : 2> blk;
+    blk.load(a, SG, a.Ghi, a.Glo, k - 1);
+    blk.load(a, SG + 1, a.Fhi, a.Flo, k);
+    if constexpr (M >= 2) {
+      blk.load(a, 0, a.Ghi, a.Glo, k - 3);
+      blk.load(a, 1, a.Fhi, a.Flo, k - 2);
+      blk.load(a, 4, a.Ghi, a.Glo, k + 1);
+      blk.load(a, 5, a.Fhi, a.Flo, k + 2);
+    }
+#pragma unroll
+    for (int q = 0; q < (M >= 2 ? 6 : 2); ++q) blk.store(q, S(q));
   }
+  __syncthreads();
+  const Spl<NB> sm1 = split(rm1), sp1 = split(rp1);
+  const Pan<NB> y0 = y0_of(k, SG, sm1, r0, sp1);
+  Pan<NB> z = y0;
+  if constexpr (M >= 2) {
+    Pan<NB> y0m = zero, y0p = zero;
+    if (hm2) y0m = y0_of(k - 2, 0, split(rm3), rm2, sm1);
+    if (hp2) y0p = y0_of(k + 2, 4, sp1, rp2, split(rp3));
+    // the w rows need G_{k-2}, F_{k-1}, G_k, F_{k+1}
+    __syncthreads();  // every wavefront is done with the y0 blocks
+    {
+      Blocks<NB, 4> late;
+      late.load(a, 0, a.Ghi, a.Glo, k - 2);
+      late.load(a, 1, a.Fhi, a.Flo, k - 1);
+      late.load(a, 2, a.Ghi, a.Glo, k);
+      late.load(a, 3, a.Fhi, a.Flo, k + 1);
+      late.store(0, S(0));
+      late.store(1, S(1));
+      late.store(2, S(4));
+      late.store(3, S(5));
+    }
+    __syncthreads();
+    const Spl<NB> s0 = split(y0);
+    f32x4 acc[MT];
+    Spl<NB> swm{}, swp{};
+    if (hm1) {  // w_{k-1} = -(F_{k-2}^T y0_{k-2} + F_{k-1} y0_k)
+      cprod<NB>(hm2, S(0), hm2 ? split(y0m) : szero, true, S(1), s0, l, acc);
+      Pan<NB> w;
+#pragma unroll
+      for (int tt = 0; tt < MT; ++tt) w.v[tt] = -acc[tt];
+      swm = split(w);
+    }
+    if (hp1) {  // w_{k+1} = -(F_k^T y0_k + F_{k+1} y0_{k+2})
+      cprod<NB>(true, S(4), s0, hp2, S(5), hp2 ? split(y0p) : szero, l, acc);
+      Pan<NB> w;
+#pragma unroll
+      for (int tt = 0; tt < MT; ++tt) w.v[tt] = -acc[tt];
+      swp = split(w);
+    }
+    cprod<NB>(hm1, S(2), swm, hp1, S(3), swp, l, acc);
+    const float a1 = (float)a.alpha1;
+#pragma unroll
+    for (int tt = 0; tt < MT; ++tt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) z.v[tt][i] = y0.v[tt][i] + a1 * -acc[tt][i];
+  }
+  const PRow zw = prow<NB>(a.z, k, ld);
+  double dp = 0.0;
+#pragma unroll
+  for (int tt = 0; tt < MT; ++tt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      pst(zw, voff, ld, tt, i, z.v[tt][i]);
+      dp += (double)r0.v[tt][i] * (double)z.v[tt][i];
+    }
+  dp += __shfl_xor(dp, 16);
+  dp += __shfl_xor(dp, 32);
+  if (l < 16) a.part[(size_t)k * ld + col] = dp;
 }
 
 // Per right-hand side: sum of the per-row partials in a fixed order, then
@@ -498,53 +738,68 @@ __global__ void k_mr_info(MrArgs a, bt_info* info) {
   info[c].relres_true = rr;
 }
 
-// F (float32) -> Fhi + Flo (bfloat16 pair).
+// F (float32) -> hi + lo (bfloat16 pair): entries [0, R NN) the split of the
+// blocks F_k, entries [R NN, 2 R NN) the split of G_k = F_k^T.
 __global__ void k_mr_split(const float* F, unsigned short* hi,
-                           unsigned short* lo, size_t N) {
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+                           unsigned short* lo, size_t RNN, int n) {
+  const size_t nn = (size_t)n * n;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < 2 * RNN;
        i += (size_t)gridDim.x * blockDim.x) {
-    const float v = F[i];
+    float v;
+    if (i < RNN) {
+      v = F[i];
+    } else {  // G_k[r][c] = F_k[c][r]
+      const size_t g = i - RNN, k = g / nn, e = g - k * nn;
+      const size_t r = e / n, c = e - r * n;
+      v = F[k * nn + c * n + r];
+    }
     const unsigned short h = f2bf(v);
     hi[i] = h;
     lo[i] = f2bf(v - bf2f(h));
   }
 }
 
-template <int NB, int EPI>
-hipError_t app(const MrArgs& a, const float* V, const float* V2,
-               const float* aux, float* out, float* out2, hipStream_t s) {
+template <int NB>
+hipError_t qu(const MrArgs& a, hipStream_t s) {
   const int rows = 8 * ((a.R + 7) / 8);
-  hipLaunchKernelGGL((k_mr_app<NB, EPI>), dim3(rows, a.nrhs / CPB), dim3(WG),
-                     0, s, a, V, V2, aux, out, out2);
+  hipLaunchKernelGGL((k_mr_qu<NB>), dim3(rows, a.nrhs / CPB), dim3(WG), 0, s,
+                     a, a.p, a.p2);
   return hipGetLastError();
 }
 
-// z = M^{-1} r at a = 1 for the current r: y0 = r + C r, then per extra term
-// y = C(C y), z = y0 + alpha_1 y (m <= 2 on this path; m = 1 reuses the Z
-// epilogue with alpha_1 = 0). ``y0_done``: y0 already formed (by EPI_Y0U).
-template <int NB>
-hipError_t precond(const MrArgs& a, hipStream_t s, bool y0_done) {
-  hipError_t e = hipSuccess;
-  if (!y0_done) {
-    e = app<NB, EPI_Y0>(a, a.r, nullptr, a.r, a.y0, nullptr, s);
+template <int NB, int M, bool UPD>
+hipError_t post_m(const MrArgs& a, hipStream_t s) {
+  constexpr size_t lds = (M >= 2 ? 6 : 2) * Lds<NB>::BLK * sizeof(unsigned short);
+  static bool attr = false;  // above 64 KiB of LDS the limit must be raised
+  if (!attr) {
+    const hipError_t e = hipFuncSetAttribute(
+        (const void*)k_mr_post<NB, M, UPD>,
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
+    attr = true;
   }
-  MrArgs b = a;
-  if (a.m == 1) b.alpha1 = 0.0;
-  e = app<NB, EPI_W>(b, a.y0, nullptr, nullptr, a.w, nullptr, s);
-  if (e != hipSuccess) return e;
-  return app<NB, EPI_Z>(b, a.w, nullptr, a.y0, a.z, nullptr, s);
+  const int rows = 8 * ((a.R + 7) / 8);
+  hipLaunchKernelGGL((k_mr_post<NB, M, UPD>), dim3(rows, a.nrhs / CPB),
+                     dim3(WG), lds, s, a);
+  return hipGetLastError();
 }
 
-// One inner iteration up to and including y0 = r + C r of the new residual;
-// swaps the p and r panels of ``a``.
+// z = M^{-1} r' at a = 1 (m <= 2 on this path) and the rho partials, with
+// r' = r - alpha q and d += alpha p first if ``upd``.
+template <int NB, bool UPD>
+hipError_t post(const MrArgs& a, hipStream_t s) {
+  return a.m >= 2 ? post_m<NB, 2, UPD>(a, s) : post_m<NB, 1, UPD>(a, s);
+}
+
+// One inner iteration up to the rho partials of the new residual; swaps the
+// p and r panels of ``a``.
 template <int NB>
 hipError_t inner_iteration(MrArgs& a, hipStream_t s) {
-  hipError_t e = app<NB, EPI_QU>(a, a.z, a.p, nullptr, a.q, a.p2, s);
+  hipError_t e = qu<NB>(a, s);
   if (e != hipSuccess) return e;
   std::swap(a.p, a.p2);
   hipLaunchKernelGGL((k_mr_colsum<SUM_SIGMA>), dim3(a.nrhs), dim3(256), 0, s, a);
-  e = app<NB, EPI_Y0U>(a, a.r, a.q, a.p, a.y0, a.r2, s);
+  e = post<NB, true>(a, s);
   if (e != hipSuccess) return e;
   std::swap(a.r, a.r2);
   return hipSuccess;
@@ -584,7 +839,7 @@ int solve(const MrArgs& a0, double* r64, int max_outer, bt_info* info,
     if (hany == 0 || outer >= max_outer) break;
     hipLaunchKernelGGL((k_mr_tohat<NB>), dim3(a.R, a.nrhs / CPB), dim3(256),
                        0, s, a, r64);
-    if (precond<NB>(a, s, false) != hipSuccess) return BT_EHIP;
+    if (post<NB, false>(a, s) != hipSuccess) return BT_EHIP;
     hipLaunchKernelGGL((k_mr_colsum<SUM_RHO>), dim3(a.nrhs), dim3(256), 0, s, a);
     for (int it = 0;; ++it) {
       if ((it & 7) == 7) {
@@ -592,7 +847,6 @@ int solve(const MrArgs& a0, double* r64, int max_outer, bt_info* info,
         if (hany == 0) break;
       }
       if (inner_iteration<NB>(a, s) != hipSuccess) return BT_EHIP;
-      if (precond<NB>(a, s, true) != hipSuccess) return BT_EHIP;
       hipLaunchKernelGGL((k_mr_colsum<SUM_RHO>), dim3(a.nrhs), dim3(256), 0, s, a);
     }
     hipLaunchKernelGGL((k_mr_xupd<NB>), dim3(a.R, a.nrhs / CPB), dim3(256),
@@ -607,19 +861,21 @@ int solve(const MrArgs& a0, double* r64, int max_outer, bt_info* info,
 
 }  // namespace btm
 
-// Bytes of scratch for a multi-RHS solve: nine float32 panels, the float64
+// Bytes of scratch for a multi-RHS solve: seven float32 panels, the float64
 // residual panel, per-row partial sums and per-column state.
 size_t bt_mrhs_scratch_bytes(int64_t R, int n, int nrhs) {
   const size_t pn = (size_t)R * n * nrhs;
-  return 9 * pn * sizeof(float) + pn * sizeof(double) +
+  return 7 * pn * sizeof(float) + pn * sizeof(double) +
          (size_t)R * nrhs * sizeof(double) + 6 * (size_t)nrhs * sizeof(double) +
          8 * (size_t)nrhs * sizeof(int) + 256;
 }
 
 hipError_t bt_mrhs_split(const float* F, unsigned short* hi, unsigned short* lo,
-                         size_t N, hipStream_t s) {
-  const int grid = (int)std::min<size_t>((N + 255) / 256, 4096);
-  hipLaunchKernelGGL(btm::k_mr_split, dim3(grid), dim3(256), 0, s, F, hi, lo, N);
+                         int64_t R, int n, hipStream_t s) {
+  const size_t RNN = (size_t)R * n * n;
+  const int grid = (int)std::min<size_t>((2 * RNN + 255) / 256, 4096);
+  hipLaunchKernelGGL(btm::k_mr_split, dim3(grid), dim3(256), 0, s, F, hi, lo,
+                     RNN, n);
   return hipGetLastError();
 }
 
@@ -634,6 +890,8 @@ int bt_mrhs_run(int64_t R, int n, int nrhs, const unsigned short* Fhi,
   a.nrhs = nrhs;
   a.Fhi = Fhi;
   a.Flo = Flo;
+  a.Ghi = Fhi + (size_t)R * n * n;
+  a.Glo = Flo + (size_t)R * n * n;
   a.Li = Li;
   a.D = D;
   a.O = O;
@@ -652,12 +910,10 @@ int bt_mrhs_run(int64_t R, int n, int nrhs, const unsigned short* Fhi,
   a.q = f + pn;
   a.r = f + 2 * pn;
   a.d = f + 3 * pn;
-  a.y0 = f + 4 * pn;
-  a.w = f + 5 * pn;
-  a.z = f + 6 * pn;
-  a.p2 = f + 7 * pn;
-  a.r2 = f + 8 * pn;
-  double* r64 = (double*)(f + 9 * pn);
+  a.z = f + 4 * pn;
+  a.p2 = f + 5 * pn;
+  a.r2 = f + 6 * pn;
+  double* r64 = (double*)(f + 7 * pn);
   a.part = r64 + pn;
   double* cs = a.part + (size_t)R * nrhs;
   a.rho = cs;
