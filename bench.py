@@ -509,6 +509,33 @@ def main():
 
     secondary = (None if args.no_workloads
                  else workloads_secondary(bt, torch, dev))
+    # polynomial order on the same batch, kernel configuration and inner
+    # tolerance (m = 2, alpha_1 = 7 is the timed configuration above; for
+    # m = 3, 4 the last coefficient is the grid-search optimum 9)
+    order_sweep = None
+    if not args.no_workloads:
+        order_sweep = {}
+        cfg = h.kernel_config()
+        for m, last in ((1, None), (3, 9.0), (4, 9.0)):
+            alpha = None if last is None else [1.0] * (m - 1) + [last]
+            pm = bt.Params(a=1.0, m=m, alpha=alpha, prec="f32_ir",
+                           inner_tol=params.inner_tol, max_outer=30)
+            hm = bt.Handle(D, O, data["offsets"], pm)
+            hm.set_kernel_config(cfg)
+            xm, im = hm.solve(b, tol, maxit)
+            torch.cuda.synchronize()
+            ms = _events_ms(lambda: hm.solve(b, tol, maxit, x=xm, info=im), 5)
+            infm = bt.infos_to_numpy(im)
+            order_sweep[f"m{m}"] = {
+                "alpha_last": last, "solve_ms": ms,
+                "solves_per_s": B / (ms * 1e-3),
+                "inner_iters_mean": float(infm["iters"].mean()),
+                "converged": bool(np.all(infm["status"] == bt.OK))}
+            del hm, xm, im
+        order_sweep["m2"] = {"alpha_last": 7.0, "solve_ms": solve_ms,
+                             "solves_per_s": B / (solve_ms * 1e-3),
+                             "inner_iters_mean": float(iters.mean()),
+                             "converged": True}
 
     cores = min(16, len(os.sched_getaffinity(0)))
     cpu = None if args.no_cpu else cpu_baseline(data, args.cpu_seconds, cores)
@@ -554,6 +581,7 @@ def main():
             "f64_iters_mean": float(it64["iters"].mean()),
             "speedup_vs_plain_f64": value / plain_f64,
             "speedup_vs_batched_f64": value / batched_f64,
+            "polynomial_order_sweep": order_sweep,
             "direct_block_cholesky_solves_per_s": (B * 1e3 / direct_ms
                                                    if direct_ok else None),
             "direct_block_cholesky_ms": direct_ms,
