@@ -207,6 +207,26 @@ int bt_solve_direct(const bt_handle* h, const double* b, double* x,
                     bt_info* info, void* scratch, size_t scratch_bytes,
                     void* stream);
 
+/* One system spread over the whole GPU (Algorithm PCG of Section II with the
+ * preconditioner of eq. Mminv-polynomial-coefficients, Section IV-B): every
+ * step of the iteration is a kernel over all block rows, so a single long
+ * horizon is not confined to one workgroup, and systems above the
+ * single-workgroup capacity of bt_solve (N n > 8192) can be solved. Same
+ * parameters, stopping tests and results as bt_solve for a handle of one
+ * system (B = 1): BT_F64 / BT_F32 iterate in that precision, BT_F32_IR (and
+ * BT_BF16X2_IR) run float32 PCG inside float64 refinement on the record.
+ * b, x: device [N][n] float64; info: device, 1 entry. scratch: device,
+ * >= bt_grid_workspace_bytes(h) (seven vectors of the iteration precision,
+ * one float64 vector and per-workgroup partial sums). Host-driven: the call
+ * synchronises with the stream every few iterations and returns when the
+ * solve is complete (not capturable in a graph). Errors: BT_EINVAL (B != 1,
+ * NULL pointers, tol < 0, maxit < 0), BT_ENOSPACE, BT_EHIP; a D_k that is
+ * not positive definite gives info.status BT_ENOTSPD with fail_index. */
+size_t bt_grid_workspace_bytes(const bt_handle* h);
+int bt_solve_grid(const bt_handle* h, const double* b, double* x, double tol,
+                  int maxit, bt_info* info, void* scratch,
+                  size_t scratch_bytes, void* stream);
+
 /* Kernel configurations for the solve (workgroup size x vector elements per
  * thread), for the autotuner. bt_kernel_config_count() entries; entry i has
  * threads nt[i], elements per thread s[i] and iteration precision prec[i].

@@ -75,6 +75,8 @@ def load_library(path: str = LIB_PATH):
         "bt_direct_workspace_bytes": (Sz, [P]),
         "bt_solve_direct": (I, [P, P, P, P, P, Sz, P]),
         "bt_solve_mrhs": (I, [P, I, P, P, Dd, I, P, P, Sz, P]),
+        "bt_grid_workspace_bytes": (Sz, [P]),
+        "bt_solve_grid": (I, [P, P, P, Dd, I, P, P, Sz, P]),
         "bt_kernel_config_count": (I, []),
         "bt_kernel_config": (I, [I, ctypes.POINTER(I), ctypes.POINTER(I),
                                  ctypes.POINTER(I)]),
@@ -97,6 +99,7 @@ def exported_symbols():
             "bt_solve", "bt_solve_batched", "bt_solve_adjoint",
             "bt_mrhs_workspace_bytes", "bt_solve_mrhs",
             "bt_direct_workspace_bytes", "bt_solve_direct",
+            "bt_grid_workspace_bytes", "bt_solve_grid",
             "bt_kernel_config_count", "bt_kernel_config",
             "bt_set_kernel_config", "bt_get_kernel_config", "bt_destroy"]
 
@@ -345,6 +348,31 @@ class Handle:
         _check(lib.bt_solve_direct(self._h, _ptr(b), _ptr(x), _ptr(info),
                                    _ptr(scratch), scratch.numel(),
                                    _stream(torch, stream)), "bt_solve_direct")
+        return x, info
+
+    def solve_grid(self, b, tol=1e-10, maxit=None, x=None, info=None,
+                   scratch=None, stream=None):
+        """Solve the handle's single system with every PCG step a kernel over
+        all block rows (bt_solve_grid). Returns (x, info)."""
+        torch = _torch()
+        b = self._vec(b, "b")
+        lib = load_library()
+        nbytes = lib.bt_grid_workspace_bytes(self._h)
+        if nbytes == 0:
+            raise BtError(EINVAL, "bt_grid_workspace_bytes")
+        if scratch is None:
+            scratch = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        if x is None:
+            x = torch.empty_like(b)
+        if info is None:
+            info = torch.empty(INFO_DTYPE.itemsize, dtype=torch.uint8,
+                               device=self.device)
+        if maxit is None:
+            maxit = self.default_maxit()
+        _check(lib.bt_solve_grid(self._h, _ptr(b), _ptr(x), float(tol),
+                                 int(maxit), _ptr(info), _ptr(scratch),
+                                 scratch.numel(), _stream(torch, stream)),
+               "bt_solve_grid")
         return x, info
 
     def precondition(self, r, z=None, stream=None):

@@ -18,7 +18,7 @@ LIB = os.path.join(PKG, "libbtpcg.so")
 ARCH = os.environ.get("BTPCG_ARCH", "gfx950")
 
 SOURCES = ["api.cpp", "setup.hip", "solve.hip", "solve_fast.hip", "mrhs.hip",
-           "direct.hip"]
+           "direct.hip", "grid.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

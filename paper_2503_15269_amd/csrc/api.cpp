@@ -9,6 +9,7 @@
 #include <numeric>
 #include <vector>
 
+#include "grid.h"
 #include "internal.h"
 
 namespace {
@@ -285,9 +286,10 @@ int bt_batch_setup(bt_handle** h, int B, const int64_t* offsets_host, int n,
   const int64_t R = check_offsets(B, offsets_host, &maxN);
   if (R < 0) return BT_EINVAL;
   if (R > B && !O) return BT_EINVAL;
-  // The single-workgroup solve kernels must hold the largest instance; the
-  // many-right-hand-side solve of a bf16x2 handle spans the grid instead.
-  if (p->prec != BT_BF16X2_IR &&
+  // The single-workgroup solve kernels must hold the largest instance; a
+  // single system may be larger (bt_solve_grid and the many-right-hand-side
+  // solve span the grid instead).
+  if (B > 1 && p->prec != BT_BF16X2_IR &&
       auto_config(kernel_prec(p), (int64_t)maxN * n) < 0)
     return BT_EINVAL;
   const Layout l = layout(B, R, n, elem_bytes(p), p->prec == BT_BF16X2_IR);
@@ -469,6 +471,43 @@ int bt_solve_direct(const bt_handle* h, const double* b, double* x,
   return hip_status(bt_launch_direct(h->B, h->n, h->dtype, h->off, h->order,
                                      h->D, h->O, b, x, info, h->R, scratch,
                                      (hipStream_t)stream));
+}
+
+size_t bt_grid_workspace_bytes(const bt_handle* h) {
+  return bt_grid_scratch_bytes(h);
+}
+
+int bt_solve_grid(const bt_handle* h, const double* b, double* x, double tol,
+                  int maxit, bt_info* info, void* scratch,
+                  size_t scratch_bytes, void* stream) {
+  if (!h || !b || !x || !info || !scratch || h->B != 1 || !(tol >= 0.0) ||
+      maxit < 0)
+    return BT_EINVAL;
+  if (scratch_bytes < bt_grid_scratch_bytes(h)) return BT_ENOSPACE;
+  hipStream_t s = (hipStream_t)stream;
+  if (!h->full_valid) {  // the stopping test and BT_PC_NONE read L
+    const int rc = launch_setup(h, s, true);
+    if (rc != BT_OK) return rc;
+  }
+  int fail = BT_NO_FAIL;
+  if (hipMemcpyAsync(&fail, h->fail, sizeof(int), hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return BT_EHIP;
+  if (fail != BT_NO_FAIL) {  // a D_k is not positive definite
+    bt_info hi{};
+    hi.status = BT_ENOTSPD;
+    hi.fail_index = fail;
+    hi.relres = NAN;
+    hi.relres_true = NAN;
+    if (hipMemsetAsync(x, 0, sizeof(double) * h->R * h->n, s) != hipSuccess ||
+        hipMemcpyAsync(info, &hi, sizeof(hi), hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return BT_EHIP;
+    return BT_OK;
+  }
+  return bt_grid_solve(h, b, x, tol, maxit, info, scratch, s);
 }
 
 int bt_kernel_config_count(void) { return num_configs(); }

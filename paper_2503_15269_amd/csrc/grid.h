@@ -1,0 +1,17 @@
+// Internal declarations of the grid-wide single-system solve (grid.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "btpcg.h"
+
+struct bt_handle;
+
+// Scratch bytes of bt_grid_solve for a handle of one system.
+size_t bt_grid_scratch_bytes(const bt_handle* h);
+
+// PCG for the single system of ``h`` with every step a kernel over all block
+// rows; host-driven (synchronises with the stream every few iterations).
+int bt_grid_solve(const bt_handle* h, const double* b, double* x, double tol,
+                  int maxit, bt_info* info, void* scratch, hipStream_t s);

@@ -1,0 +1,684 @@
+// Grid-wide PCG for one large system.
+//
+// The register-resident and persistent kernels give each system one
+// workgroup, which leaves a single long horizon (hundreds of block rows) on
+// one CU with the whole iteration latency-bound there. Here every step of
+// the iteration is a kernel over all block rows instead, and the kernel
+// boundaries are the grid-wide barriers the PCG recurrences need:
+//   k_g_init   r = L^{-1} s (s = b, or the float64 residual under
+//              refinement), z = M^{-1} r, rho and ||s||^2 partials
+//   k_g_q      p = z + beta p, q = Ahat p = p - C p, sigma partials
+//   k_g_u      x += alpha p, r -= alpha q, ||L r||^2 partials,
+//              z = M^{-1} r, rho partials
+//   k_g_x      x = L^{-T} xhat (or x += L^{-T} d under refinement)
+//   k_g_res    float64 residual b - A x of the record, ||.||^2 partials
+// Same scaled coordinates as the other solve kernels: Ahat = I - C,
+// (C v)_k = -(F_{k-1}^T v_{k-1} + F_k v_{k+1}), and the preconditioner of
+// eq. Mminv-polynomial-coefficients evaluated as y_0 = (I + aC) r,
+// y_i = ((1-a)C + aC^2) y_{i-1}, z = sum alpha_i y_i (Section IV-B).
+//
+// A workgroup owns rb consecutive block rows. M^{-1} needs neighbours to a
+// depth D (1 + 2(m-1) at a = 1): the workgroup loads r (or forms r - alpha q)
+// on its rows plus D on each side into LDS and applies C there on windows
+// that shrink by one row per application, so M^{-1} r of its own rows needs
+// no further grid-wide exchange. Scalars never leave the device: each
+// workgroup writes one partial per reduction, and every workgroup of the
+// next kernel sums all partials in the same fixed order, so all of them
+// take the same decisions (alpha, beta, stopping) without a broadcast.
+// Workgroup 0 records the outcome in a small control block that the host
+// reads every few iterations; kernels that find it settled return at once.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "grid.h"
+#include "internal.h"
+#include "reduce.h"
+
+namespace btg {
+
+using btk::AccOf;
+
+constexpr int NT = 256;    // threads per workgroup
+constexpr int CHUNK = 8;   // iterations enqueued between host checks
+// partial-sum slots, nwg doubles each
+enum { P_RHO0 = 0, P_RHO1 = 1, P_SIG = 2, P_NR2 = 3, P_NB2 = 4, P_RES = 5,
+       P_RHOF = 6, P_SLOTS = 7 };
+
+struct Ctl {
+  int status;  // BT_NOT_CONVERGED while the (inner) iteration runs
+  int it;      // PCG steps of this (inner) solve
+};
+
+template <typename T>
+struct GArgs {
+  int R, n, rb, depth, nwg, pc, m, ir, dtype;
+  double a, tol, itol;
+  double alpha[BT_MAX_M];
+  const T* F;
+  const T* L;
+  const T* Li;
+  const void* D;  // record
+  const void* O;
+  const double* src;  // k_g_init: b or the float64 residual
+  const double* b;
+  double* x;          // float64 iterate / solution
+  double* r64;        // float64 residual (refinement)
+  T* pb[2];
+  T* rbuf[2];
+  T* q;
+  T* z;
+  T* xh;              // scaled iterate (direct) or correction d (refinement)
+  double* part;       // [P_SLOTS][nwg]
+  Ctl* ctl;
+};
+
+__device__ __forceinline__ double rec(const void* P, size_t i, int dtype) {
+  return dtype == BT_DT_F64 ? ((const double*)P)[i]
+                            : (double)((const float*)P)[i];
+}
+
+// Sum over the workgroup, every thread gets it (fixed order).
+__device__ __forceinline__ double wg_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+#pragma unroll
+  for (int h = NT / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Sum of one partial slot over all workgroups, fixed order.
+__device__ __forceinline__ double slot_sum(const double* part, int slot,
+                                           int nwg, double* red) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nwg; i += NT) s += part[slot * nwg + i];
+  return wg_sum(s, red);
+}
+
+// Settle the solve (workgroup 0 writes; the others took the same decision).
+__device__ __forceinline__ void settle(Ctl* ctl, int status) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->status = status;
+}
+
+// Window geometry: own rows [k0, k1), window [w0, w1) with depth d.
+struct Win {
+  int k0, k1, w0, w1;
+};
+__device__ __forceinline__ Win window(int R, int rb, int d) {
+  Win w;
+  w.k0 = blockIdx.x * rb;
+  w.k1 = min(R, w.k0 + rb);
+  w.w0 = max(0, w.k0 - d);
+  w.w1 = min(R, w.k1 + d);
+  return w;
+}
+
+// out = C v on rows [lo, hi); v valid on the rows it needs; both in the
+// window layout (row k at (k - w0) n). Same arithmetic order as the other
+// solve kernels: the F_{k-1}^T term, then the F_k term, in order j.
+template <typename T>
+__device__ void applyC(const GArgs<T>& a, const T* v, T* out, int w0, int lo,
+                       int hi) {
+  const int n = a.n;
+  const size_t nn = (size_t)n * n;
+  const int cnt = (hi - lo) * n;
+  for (int e = threadIdx.x; e < cnt; e += NT) {
+    const int k = lo + e / n, i = e % n;
+    T acc = T(0);
+    if (k > 0) {
+      const T* Fm = a.F + (size_t)(k - 1) * nn + i;
+      const T* vm = v + (k - 1 - w0) * n;
+#pragma unroll 4
+      for (int j = 0; j < n; ++j) acc += Fm[(size_t)j * n] * vm[j];
+    }
+    if (k < a.R - 1) {
+      const T* Fk = a.F + (size_t)k * nn + (size_t)i * n;
+      const T* vp = v + (k + 1 - w0) * n;
+#pragma unroll 4
+      for (int j = 0; j < n; ++j) acc += Fk[j] * vp[j];
+    }
+    out[(k - w0) * n + i] = -acc;
+  }
+}
+
+// rows on which C v is known when v is known on [lo, hi)
+__device__ __forceinline__ void shrink(int R, int& lo, int& hi) {
+  if (lo > 0) ++lo;
+  if (hi < R) --hi;
+}
+
+// z = M^{-1} r on the own rows; r known on the whole window (LDS), y, w1,
+// w2, z window buffers. Returns with z valid on [k0, k1).
+template <typename T>
+__device__ void precond(const GArgs<T>& a, const Win& W, const T* r, T* y,
+                        T* w1, T* w2, T* z) {
+  const int n = a.n, w0 = W.w0;
+  const T av = (T)a.a, om = (T)(1.0 - a.a);
+  int lo = W.w0, hi = W.w1;
+  // y_0 = r + a C r
+  if (a.a != 0.0) {
+    shrink(a.R, lo, hi);
+    applyC(a, r, w1, w0, lo, hi);
+    __syncthreads();
+    for (int e = threadIdx.x; e < (hi - lo) * n; e += NT) {
+      const int o = (lo - w0) * n + e;
+      y[o] = r[o] + av * w1[o];
+      z[o] = y[o];
+    }
+  } else {
+    for (int e = threadIdx.x; e < (hi - lo) * n; e += NT) {
+      const int o = (lo - w0) * n + e;
+      y[o] = r[o];
+      z[o] = r[o];
+    }
+  }
+  __syncthreads();
+  for (int m = 1; m < a.m; ++m) {
+    shrink(a.R, lo, hi);
+    applyC(a, y, w1, w0, lo, hi);
+    __syncthreads();
+    if (a.a != 0.0) {
+      shrink(a.R, lo, hi);
+      applyC(a, w1, w2, w0, lo, hi);
+      __syncthreads();
+    }
+    const T al = (T)a.alpha[m];
+    for (int e = threadIdx.x; e < (hi - lo) * n; e += NT) {
+      const int o = (lo - w0) * n + e;
+      y[o] = a.a != 0.0 ? om * w1[o] + av * w2[o] : w1[o];
+      z[o] += al * y[o];
+    }
+    __syncthreads();
+  }
+}
+
+// (M v)_k[i] for the lower-triangular block M_k (row i, columns 0..i)
+template <typename T>
+__device__ __forceinline__ T lower(const T* M, const T* v, int n, int k,
+                                   int i) {
+  const T* row = M + ((size_t)k * n + i) * n;
+  T acc = T(0);
+  for (int j = 0; j <= i; ++j) acc += row[j] * v[j];
+  return acc;
+}
+
+// (M^T v)_k[i] for the lower-triangular block M_k (column i, rows i..n-1)
+template <typename T>
+__device__ __forceinline__ T lowerT(const T* M, const T* v, int n, int k,
+                                    int i) {
+  const T* blk = M + (size_t)k * n * n;
+  T acc = T(0);
+  for (int j = i; j < n; ++j) acc += blk[(size_t)j * n + i] * v[j];
+  return acc;
+}
+
+// Partial of one reduction over the own rows into its slot.
+template <typename T>
+__device__ __forceinline__ void put_partial(const GArgs<T>& a, int slot,
+                                            double v, double* red) {
+  const double s = wg_sum(v, red);
+  if (threadIdx.x == 0) a.part[slot * a.nwg + blockIdx.x] = s;
+}
+
+// The preconditioner on the own rows from r known on the window; for
+// BT_PC_NONE (M = I on the original system) z = L^T L r, a row-local map.
+// Returns the rho partial r'z (the accumulator of the precision).
+template <typename T>
+__device__ double precond_own(const GArgs<T>& a, const Win& W, T* r, T* y,
+                              T* w1, T* w2, T* z) {
+  const int n = a.n, w0 = W.w0;
+  if (a.pc == BT_PC_NONE) {
+    for (int e = threadIdx.x; e < (W.k1 - W.k0) * n; e += NT) {
+      const int k = W.k0 + e / n, i = e % n;
+      y[(k - w0) * n + i] = lower(a.L, r + (k - w0) * n, n, k, i);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < (W.k1 - W.k0) * n; e += NT) {
+      const int k = W.k0 + e / n, i = e % n;
+      z[(k - w0) * n + i] = lowerT(a.L, y + (k - w0) * n, n, k, i);
+    }
+    __syncthreads();
+  } else {
+    precond(a, W, r, y, w1, w2, z);
+  }
+  typename AccOf<T>::type acc;
+  acc.zero();
+  for (int e = threadIdx.x; e < (W.k1 - W.k0) * n; e += NT) {
+    const int o = (W.k0 - w0) * n + e;
+    acc.add_prod(r[o], z[o]);
+    a.z[(size_t)W.k0 * n + e] = z[o];
+  }
+  return acc.value();
+}
+
+template <typename T>
+__device__ __forceinline__ T* lds_vec(double* red, int slot, int len) {
+  return reinterpret_cast<T*>(red + NT) + (size_t)slot * len;
+}
+
+// r = L^{-1} s on the window (s = a.src, float64, cast to T first),
+// z = M^{-1} r, partials rho (both rho slots of step 0), ||s||^2.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_g_init(GArgs<T> a) {
+  extern __shared__ double red[];
+  const Win W = window(a.R, a.rb, a.depth);
+  const int n = a.n, len = (W.w1 - W.w0) * n;
+  const int lmax = (a.rb + 2 * a.depth) * n;
+  T* r = lds_vec<T>(red, 0, lmax);
+  T* y = lds_vec<T>(red, 1, lmax);
+  T* w1 = lds_vec<T>(red, 2, lmax);
+  T* w2 = lds_vec<T>(red, 3, lmax);
+  T* z = lds_vec<T>(red, 4, lmax);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.ctl->status = BT_NOT_CONVERGED;
+    a.ctl->it = 0;
+  }
+  for (int e = threadIdx.x; e < len; e += NT)
+    y[e] = (T)a.src[(size_t)W.w0 * n + e];
+  __syncthreads();
+  double nb = 0.0;
+  for (int e = threadIdx.x; e < len; e += NT) {
+    const int k = W.w0 + e / n, i = e % n;
+    r[e] = lower(a.Li, y + (k - W.w0) * n, n, k, i);
+    if (k >= W.k0 && k < W.k1) {
+      const double s = a.src[(size_t)W.w0 * n + e];
+      nb += s * s;
+      a.rbuf[0][(size_t)k * n + i] = r[e];
+      a.xh[(size_t)k * n + i] = T(0);
+    }
+  }
+  __syncthreads();
+  put_partial(a, P_NB2, nb, red);
+  const double rho = precond_own(a, W, r, y, w1, w2, z);
+  const double s = wg_sum(rho, red);
+  if (threadIdx.x == 0) {
+    a.part[P_RHO0 * a.nwg + blockIdx.x] = s;
+    a.part[P_RHOF * a.nwg + blockIdx.x] = s;
+  }
+}
+
+// Step i: the stopping test on the state after step i - 1, beta,
+// p = z + beta p (own rows and both neighbour rows), q = p - C p, sigma.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_g_q(GArgs<T> a, int i) {
+  extern __shared__ double red[];
+  if (a.ctl->status != BT_NOT_CONVERGED) return;
+  const Win W = window(a.R, a.rb, 1);
+  const int n = a.n, len = (W.w1 - W.w0) * n;
+  const int lmax = (a.rb + 2 * a.depth) * n;
+  T* p = lds_vec<T>(red, 0, lmax);
+  T* cp = lds_vec<T>(red, 1, lmax);
+  const double rho = slot_sum(a.part, i & 1, a.nwg, red);
+  if (!a.ir) {
+    const double nb2 = slot_sum(a.part, P_NB2, a.nwg, red);
+    if (i == 0) {
+      if (!(nb2 < INFINITY)) { settle(a.ctl, BT_ENONFINITE); return; }
+      if (nb2 == 0.0) { settle(a.ctl, BT_OK); return; }
+    } else {
+      const double nr2 = slot_sum(a.part, P_NR2, a.nwg, red);
+      if (nr2 <= a.tol * a.tol * nb2) { settle(a.ctl, BT_OK); return; }
+      if (!(nr2 < INFINITY)) { settle(a.ctl, BT_ENONFINITE); return; }
+    }
+    if (!(rho > 0.0)) {
+      settle(a.ctl, rho == rho ? BT_EBREAKDOWN : BT_ENONFINITE);
+      return;
+    }
+  } else {  // inner solve of a refinement step: stop when r'z fell enough
+    if (!(rho > 0.0)) { settle(a.ctl, BT_OK); return; }
+    if (i > 0) {
+      const double rho0 = slot_sum(a.part, P_RHOF, a.nwg, red);
+      if (rho <= a.itol * a.itol * rho0) { settle(a.ctl, BT_OK); return; }
+    }
+  }
+  const T* pin = a.pb[(i + 1) & 1];
+  T* pout = a.pb[i & 1];
+  if (i == 0) {
+    for (int e = threadIdx.x; e < len; e += NT)
+      p[e] = a.z[(size_t)W.w0 * n + e];
+  } else {
+    const double rprev = slot_sum(a.part, (i + 1) & 1, a.nwg, red);
+    const T be = (T)(rho / rprev);
+    for (int e = threadIdx.x; e < len; e += NT) {
+      const size_t g = (size_t)W.w0 * n + e;
+      p[e] = a.z[g] + be * pin[g];
+    }
+  }
+  __syncthreads();
+  applyC(a, p, cp, W.w0, W.k0, W.k1);
+  __syncthreads();
+  typename AccOf<T>::type acc;
+  acc.zero();
+  for (int e = threadIdx.x; e < (W.k1 - W.k0) * n; e += NT) {
+    const int o = (W.k0 - W.w0) * n + e;
+    const size_t g = (size_t)W.k0 * n + e;
+    const T qv = p[o] - cp[o];
+    pout[g] = p[o];
+    a.q[g] = qv;
+    acc.add_prod(p[o], qv);
+  }
+  put_partial(a, P_SIG, acc.value(), red);
+}
+
+// Step i: alpha = rho / sigma, x += alpha p, r -= alpha q (own rows and the
+// preconditioner's halo), ||L r||^2, z = M^{-1} r, rho.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_g_u(GArgs<T> a, int i) {
+  extern __shared__ double red[];
+  if (a.ctl->status != BT_NOT_CONVERGED) return;
+  const Win W = window(a.R, a.rb, a.depth);
+  const int n = a.n, len = (W.w1 - W.w0) * n;
+  const int lmax = (a.rb + 2 * a.depth) * n;
+  T* r = lds_vec<T>(red, 0, lmax);
+  T* y = lds_vec<T>(red, 1, lmax);
+  T* w1 = lds_vec<T>(red, 2, lmax);
+  T* w2 = lds_vec<T>(red, 3, lmax);
+  T* z = lds_vec<T>(red, 4, lmax);
+  const double sigma = slot_sum(a.part, P_SIG, a.nwg, red);
+  const double rho = slot_sum(a.part, i & 1, a.nwg, red);
+  if (!(sigma > 0.0)) {
+    settle(a.ctl, a.ir ? BT_OK : (sigma == sigma ? BT_EBREAKDOWN
+                                                 : BT_ENONFINITE));
+    return;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->it = i + 1;
+  const T al = (T)(rho / sigma);
+  const T* rin = a.rbuf[i & 1];
+  T* rout = a.rbuf[(i + 1) & 1];
+  const T* p = a.pb[i & 1];
+  for (int e = threadIdx.x; e < len; e += NT) {
+    const int k = W.w0 + e / n;
+    const size_t g = (size_t)W.w0 * n + e;
+    r[e] = rin[g] - al * a.q[g];
+    if (k >= W.k0 && k < W.k1) {
+      a.xh[g] += al * p[g];
+      rout[g] = r[e];
+    }
+  }
+  __syncthreads();
+  if (!a.ir) {  // ||r|| = ||L rhat|| of the original system
+    double t2 = 0.0;
+    typename AccOf<T>::type acc;
+    acc.zero();
+    for (int e = threadIdx.x; e < (W.k1 - W.k0) * n; e += NT) {
+      const int k = W.k0 + e / n, ii = e % n;
+      const T t = lower(a.L, r + (k - W.w0) * n, n, k, ii);
+      acc.add_prod(t, t);
+    }
+    t2 = acc.value();
+    put_partial(a, P_NR2, t2, red);
+  }
+  const double rz = precond_own(a, W, r, y, w1, w2, z);
+  put_partial(a, (i + 1) & 1, rz, red);
+}
+
+// x = L^{-T} xhat (add = 0) or x += L^{-T} d (add = 1), own rows.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_g_x(GArgs<T> a, int add) {
+  extern __shared__ double red[];
+  const Win W = window(a.R, a.rb, 0);
+  const int n = a.n;
+  T* v = lds_vec<T>(red, 0, (a.rb + 2 * a.depth) * n);
+  for (int e = threadIdx.x; e < (W.k1 - W.k0) * n; e += NT)
+    v[e] = a.xh[(size_t)W.k0 * n + e];
+  __syncthreads();
+  for (int e = threadIdx.x; e < (W.k1 - W.k0) * n; e += NT) {
+    const int k = W.k0 + e / n, i = e % n;
+    const double u = (double)lowerT(a.Li, v + (k - W.k0) * n, n, k, i);
+    const size_t g = (size_t)W.k0 * n + e;
+    a.x[g] = add ? a.x[g] + u : u;
+  }
+}
+
+// r64 = b - A x in float64 from the record, own rows, and ||r64||^2.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_g_res(GArgs<T> a) {
+  extern __shared__ double red[];
+  const Win W = window(a.R, a.rb, 0);
+  const int n = a.n;
+  const size_t nn = (size_t)n * n;
+  double s2 = 0.0;
+  for (int e = threadIdx.x; e < (W.k1 - W.k0) * n; e += NT) {
+    const int k = W.k0 + e / n, i = e % n;
+    const double* xk = a.x + (size_t)k * n;
+    double acc = 0.0;
+    const size_t db = (size_t)k * nn + (size_t)i * n;
+    for (int j = 0; j < n; ++j) acc += rec(a.D, db + j, a.dtype) * xk[j];
+    if (k > 0) {
+      const size_t ob = (size_t)(k - 1) * nn + i;
+      for (int j = 0; j < n; ++j)
+        acc += rec(a.O, ob + (size_t)j * n, a.dtype) * xk[j - n];
+    }
+    if (k < a.R - 1) {
+      const size_t ob = (size_t)k * nn + (size_t)i * n;
+      for (int j = 0; j < n; ++j)
+        acc += rec(a.O, ob + j, a.dtype) * xk[n + j];
+    }
+    const size_t g = (size_t)k * n + i;
+    const double rv = a.b[g] - acc;
+    if (a.r64) a.r64[g] = rv;
+    s2 += rv * rv;
+  }
+  put_partial(a, P_RES, s2, red);
+}
+
+template <typename T>
+struct Plan {
+  GArgs<T> a;
+  size_t lds;
+  int grid;
+};
+
+inline int depth_of(const bt_params& p) {
+  if (p.pc == BT_PC_NONE) return 0;
+  const int d1 = p.a != 0.0 ? 1 : 0, dh = p.a != 0.0 ? 2 : 1;
+  return d1 + (p.m - 1) * dh;
+}
+
+inline int rows_per_wg(int64_t R) {
+  return (int)std::max<int64_t>(4, std::min<int64_t>(16, R / 64));
+}
+
+// Scratch layout: seven T vectors (p twice, r twice, q, z, xhat), the
+// float64 residual, the partial sums, the control block.
+template <typename T>
+struct Scratch {
+  size_t r64, part, ctl, total;
+  Scratch(int64_t R, int n) {
+    const int nwg = (int)((R + rows_per_wg(R) - 1) / rows_per_wg(R));
+    const size_t v = (size_t)R * n;
+    r64 = (7 * v * sizeof(T) + 255) / 256 * 256;
+    part = r64 + v * sizeof(double);
+    ctl = part + (size_t)P_SLOTS * nwg * sizeof(double);
+    total = ctl + sizeof(Ctl);
+  }
+};
+
+template <typename T, typename K, typename... Args>
+hipError_t launch(K kernel, const Plan<T>& pl, hipStream_t s, Args... args) {
+  hipLaunchKernelGGL(kernel, dim3(pl.grid), dim3(NT), pl.lds, s, pl.a,
+                     args...);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t set_lds(size_t lds) {
+  static size_t done = 0;  // largest size the attributes were raised to
+  if (lds <= 65536 || lds <= done) return hipSuccess;
+  const void* fns[] = {(const void*)k_g_init<T>, (const void*)k_g_q<T>,
+                       (const void*)k_g_u<T>, (const void*)k_g_x<T>,
+                       (const void*)k_g_res<T>};
+  for (const void* f : fns) {
+    const hipError_t e = hipFuncSetAttribute(
+        f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  done = lds;
+  return hipSuccess;
+}
+
+template <typename T>
+int run(const bt_handle* h, const double* b, double* x, double tol, int maxit,
+        bt_info* info, void* scratch, hipStream_t s) {
+  const int64_t R = h->R;
+  const int n = h->n;
+  Plan<T> pl{};
+  GArgs<T>& a = pl.a;
+  a.R = (int)R;
+  a.n = n;
+  a.rb = rows_per_wg(R);
+  a.nwg = (int)((R + a.rb - 1) / a.rb);
+  a.depth = depth_of(h->p);
+  a.pc = h->p.pc;
+  a.m = h->p.m;
+  a.a = h->p.a;
+  for (int i = 0; i < BT_MAX_M; ++i) a.alpha[i] = i == 0 ? 1.0 : h->p.alpha[i];
+  a.ir = 0;
+  a.dtype = h->dtype;
+  a.tol = tol;
+  a.itol = h->p.inner_tol;
+  a.F = (const T*)h->F;
+  a.L = (const T*)h->L;
+  a.Li = (const T*)h->Li;
+  a.D = h->D;
+  a.O = h->O;
+  a.b = b;
+  a.x = x;
+  const size_t v = (size_t)R * n;
+  T* f = (T*)scratch;
+  a.pb[0] = f;
+  a.pb[1] = f + v;
+  a.rbuf[0] = f + 2 * v;
+  a.rbuf[1] = f + 3 * v;
+  a.q = f + 4 * v;
+  a.z = f + 5 * v;
+  a.xh = f + 6 * v;
+  const Scratch<T> sl(R, n);
+  a.r64 = (double*)((unsigned char*)scratch + sl.r64);
+  a.part = (double*)((unsigned char*)scratch + sl.part);
+  a.ctl = (Ctl*)((unsigned char*)scratch + sl.ctl);
+  pl.grid = a.nwg;
+  pl.lds = NT * sizeof(double) +
+           5 * (size_t)(a.rb + 2 * a.depth) * n * sizeof(T);
+  if (set_lds<T>(pl.lds) != hipSuccess) return BT_EHIP;
+
+  std::vector<double> hp((size_t)P_SLOTS * a.nwg);
+  Ctl ctl{};
+  auto sync_state = [&](bool parts) -> bool {
+    if (hipMemcpyAsync(&ctl, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s) !=
+        hipSuccess)
+      return false;
+    if (parts && hipMemcpyAsync(hp.data(), a.part, hp.size() * sizeof(double),
+                                hipMemcpyDeviceToHost, s) != hipSuccess)
+      return false;
+    return hipStreamSynchronize(s) == hipSuccess;
+  };
+  auto host_slot = [&](int slot) {
+    double t = 0.0;
+    for (int i = 0; i < a.nwg; ++i) t += hp[(size_t)slot * a.nwg + i];
+    return t;
+  };
+  // inner loop: steps until the control block is settled or ``cap`` steps
+  auto iterate = [&](int cap, int* steps) -> bool {
+    int i = 0;
+    for (;;) {
+      const int stop = std::min(cap, i + CHUNK);
+      for (; i < stop; ++i) {
+        if (launch(k_g_q<T>, pl, s, i) != hipSuccess ||
+            launch(k_g_u<T>, pl, s, i) != hipSuccess)
+          return false;
+      }
+      if (!sync_state(false)) return false;
+      if (ctl.status != BT_NOT_CONVERGED || i >= cap) break;
+    }
+    *steps = ctl.it;
+    return true;
+  };
+
+  int status = BT_NOT_CONVERGED, total = 0, outer = 0;
+  double nb2 = 0.0, nr2 = 0.0, nrt2 = 0.0;
+  const bool refine = h->p.prec == BT_F32_IR || h->p.prec == BT_BF16X2_IR;
+  if (!refine) {
+    // plain PCG in the precision of the factors
+    a.src = b;
+    if (launch(k_g_init<T>, pl, s) != hipSuccess) return BT_EHIP;
+    int steps = 0;
+    if (!iterate(maxit, &steps)) return BT_EHIP;
+    status = ctl.status;
+    total = steps;
+    outer = 1;
+    a.r64 = nullptr;
+    if (launch(k_g_x<T>, pl, s, 0) != hipSuccess ||
+        launch(k_g_res<T>, pl, s) != hipSuccess || !sync_state(true))
+      return BT_EHIP;
+    nb2 = host_slot(P_NB2);
+    nr2 = total > 0 ? host_slot(P_NR2) : nb2;
+    nrt2 = host_slot(P_RES);
+    // the test after the last permitted step (the kernels run it at the
+    // start of the next step, which is not launched)
+    if (status == BT_NOT_CONVERGED && total > 0 && nr2 <= tol * tol * nb2)
+      status = BT_OK;
+  } else {
+    // float inner PCG inside float64 refinement on the record
+    a.ir = 1;
+    if (hipMemsetAsync(x, 0, v * sizeof(double), s) != hipSuccess)
+      return BT_EHIP;
+    for (;;) {
+      if (launch(k_g_res<T>, pl, s) != hipSuccess || !sync_state(true))
+        return BT_EHIP;
+      nr2 = host_slot(P_RES);
+      if (outer == 0) nb2 = nr2;
+      nrt2 = nr2;
+      if (nr2 <= tol * tol * nb2) { status = BT_OK; break; }
+      if (!(nr2 < INFINITY)) { status = BT_ENONFINITE; break; }
+      if (outer >= h->p.max_outer || total >= maxit) break;
+      a.src = a.r64;
+      if (launch(k_g_init<T>, pl, s) != hipSuccess) return BT_EHIP;
+      int steps = 0;
+      if (!iterate(maxit - total, &steps)) return BT_EHIP;
+      total += steps;
+      if (launch(k_g_x<T>, pl, s, 1) != hipSuccess) return BT_EHIP;
+      ++outer;
+      if (steps == 0) {
+        status = BT_EBREAKDOWN;
+        if (launch(k_g_res<T>, pl, s) != hipSuccess || !sync_state(true))
+          return BT_EHIP;
+        nrt2 = nr2 = host_slot(P_RES);
+        break;
+      }
+    }
+  }
+  bt_info hi{};
+  hi.status = status;
+  hi.iters = total;
+  hi.outer = outer;
+  hi.fail_index = -1;
+  hi.relres = nb2 > 0.0 ? std::sqrt(nr2 / nb2) : 0.0;
+  hi.relres_true = nb2 > 0.0 ? std::sqrt(nrt2 / nb2) : 0.0;
+  if (hipMemcpyAsync(info, &hi, sizeof(hi), hipMemcpyHostToDevice, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return BT_EHIP;
+  return BT_OK;
+}
+
+}  // namespace btg
+
+size_t bt_grid_scratch_bytes(const bt_handle* h) {
+  if (!h || h->B != 1) return 0;
+  return h->p.prec == BT_F64 ? btg::Scratch<double>(h->R, h->n).total
+                             : btg::Scratch<float>(h->R, h->n).total;
+}
+
+int bt_grid_solve(const bt_handle* h, const double* b, double* x, double tol,
+                  int maxit, bt_info* info, void* scratch, hipStream_t s) {
+  if (h->p.prec == BT_F64)
+    return btg::run<double>(h, b, x, tol, maxit, info, scratch, s);
+  return btg::run<float>(h, b, x, tol, maxit, info, scratch, s);
+}

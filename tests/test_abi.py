@@ -99,9 +99,10 @@ def test_setup_rejects_before_touching_memory(lib):
     rc = lib.bt_setup(ctypes.byref(h), 0, 4, bt.DT_F64, bogus, bogus,
                       ctypes.byref(good), bogus, 1 << 30, None)
     assert rc == bt.EINVAL
-    # a system too large for one workgroup of the solve kernel
-    big = np.array([0, 1 << 20], dtype=np.int64)
-    rc = lib.bt_batch_setup(ctypes.byref(h), 1,
+    # a batch with a system too large for one workgroup of the solve kernel
+    # (a single system of that size is allowed: bt_solve_grid spans the grid)
+    big = np.array([0, 8, 8 + (1 << 20)], dtype=np.int64)
+    rc = lib.bt_batch_setup(ctypes.byref(h), 2,
                             big.ctypes.data_as(ctypes.c_void_p), 48,
                             bt.DT_F64, bogus, bogus, ctypes.byref(good), bogus,
                             1 << 40, None)
@@ -113,6 +114,9 @@ def test_setup_rejects_before_touching_memory(lib):
     assert lib.bt_solve_adjoint(None, bogus, bogus, bogus, None, None, 1e-10,
                                 10, bogus, None) == bt.EINVAL
     assert lib.bt_refactor(None, None) == bt.EINVAL
+    assert lib.bt_solve_grid(None, bogus, bogus, 1e-10, 10, bogus, bogus,
+                             1 << 20, None) == bt.EINVAL
+    assert lib.bt_grid_workspace_bytes(None) == 0
 
 
 def test_kernel_configs_listed(lib):

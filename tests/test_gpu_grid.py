@@ -1,0 +1,151 @@
+"""The grid-wide single-system solve (bt_solve_grid) against the oracle.
+
+Float64: iteration counts equal the oracle's PCG (same rule as the other
+parity tests) and solutions agree with it to 1e-10; the single-workgroup
+path (bt_solve) gives the same count. Float32 + refinement: the float64
+residual of the record reaches 1e-10 and the error against the oracle's
+block Cholesky solve stays within the float32 bound. Sizes span several
+workgroups with a ragged last one, a system above the single-workgroup
+capacity, and the degenerate cases.
+"""
+import numpy as np
+import pytest
+
+import lqrgen
+import oracle as orc
+import paper_2503_15269_amd as bt
+from gpu_util import iteration_match, oracle_kind, rel, to_dev, workload
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu(oracle_lib):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    bt.load_library()
+
+
+def grid_solve(D, O, b, params, tol=1e-10, maxit=None, record="f64"):
+    import torch
+    dt = torch.float64 if record == "f64" else torch.float32
+    n = D.shape[1]
+    h = bt.Handle(to_dev(D, dt), to_dev(O, dt) if len(O) else None, None,
+                  params)
+    x, info = h.solve_grid(to_dev(np.asarray(b).reshape(-1), torch.float64),
+                           tol, maxit)
+    torch.cuda.synchronize()
+    return x.cpu().numpy().reshape(-1, n), bt.infos_to_numpy(info), h
+
+
+VARIANTS = {
+    "polycoeff_m2": bt.Params.polycoeff(2),
+    "polycoeff_m3": bt.Params.polycoeff(3),
+    "opt_m1": bt.Params(a=1.0, m=1),
+    "jacobi_m2": bt.Params.block_jacobi(2),
+    "stairs_m2": bt.Params(a=0.5, m=2),
+    "none": bt.Params(pc="none", m=1),
+}
+
+# (N, n): one workgroup, several with a ragged last one, many
+SHAPES = [(7, 6), (45, 12), (130, 5), (300, 12)]
+
+
+@pytest.mark.parametrize("N,n", SHAPES)
+@pytest.mark.parametrize("name", sorted(VARIANTS))
+def test_grid_f64_matches_oracle(N, n, name):
+    P = VARIANTS[name]
+    d = lqrgen.lqr_instance(N, n, max(1, n // 3), 11, N + n)
+    x, info, _ = grid_solve(d["D"], d["O"], d["b"], P)
+    xr, ri = orc.pcg(d["D"], d["O"], d["b"], tol=1e-10, maxit=10 * N * n,
+                     **oracle_kind(P))
+    assert ri["status"] == orc.OK
+    assert info[0]["status"] == bt.OK, info
+    # plain CG (no preconditioner) runs past the dimension of the system and
+    # its count depends on the rounding order of the dot products (here the
+    # grid's per-workgroup partial sums): 3% slack there; every
+    # preconditioner of the paper must match exactly
+    slack = max(2, 3 * ri["iters"] // 100) if P.pc == "none" else 0
+    assert iteration_match(int(info[0]["iters"]), ri, slack=slack), (info, ri)
+    if info[0]["iters"] == ri["iters"]:
+        assert rel(x, xr) <= 1e-10, rel(x, xr)
+    else:  # both converged iterates agree to the conditioning bound
+        assert rel(x, orc.btchol_solve(d["D"], d["O"], d["b"])) <= 1e-6
+    assert info[0]["relres"] <= 1e-10
+    assert info[0]["relres_true"] <= 1e-9
+
+
+@pytest.mark.parametrize("name", ["polycoeff_m2", "jacobi_m2"])
+def test_grid_same_count_as_single_workgroup_path(name):
+    import torch
+    d = workload("single_n12")
+    P = VARIANTS[name]
+    x, info, h = grid_solve(d["D"], d["O"], d["b"], P)
+    x1, i1 = h.solve(to_dev(d["b"].reshape(-1), torch.float64), 1e-10)
+    i1 = bt.infos_to_numpy(i1)
+    assert info[0]["iters"] == i1[0]["iters"]
+    assert rel(x, x1.cpu().numpy().reshape(x.shape)) <= 1e-11
+
+
+@pytest.mark.parametrize("record", ["f32", "f64"])
+def test_grid_f32_refinement(record):
+    d = workload("single_n12")
+    D, O = d["D"], d["O"]
+    if record == "f32":
+        D = D.astype(np.float32).astype(np.float64)
+        O = O.astype(np.float32).astype(np.float64)
+    P = bt.Params.polycoeff(2, prec="f32_ir", inner_tol=1e-4)
+    x, info, _ = grid_solve(D, O, d["b"], P, record=record)
+    assert info[0]["status"] == bt.OK, info
+    assert info[0]["relres_true"] <= 1e-10
+    assert info[0]["outer"] >= 2
+    xd = orc.btchol_solve(D, O, d["b"])
+    assert rel(x, xd) <= 1e-5, rel(x, xd)
+
+
+def test_grid_above_single_workgroup_capacity():
+    # 2048 x 12 = 24576 unknowns: bt_solve cannot hold it, bt_solve_grid can
+    import torch
+    d = lqrgen.lqr_instance(2048, 12, 4, 3, 0)
+    P = bt.Params.polycoeff(2)
+    x, info, h = grid_solve(d["D"], d["O"], d["b"], P)
+    assert info[0]["status"] == bt.OK, info
+    assert info[0]["relres_true"] <= 1e-9
+    xd = orc.btchol_solve(d["D"], d["O"], d["b"])
+    assert rel(x, xd) <= 1e-8
+    with pytest.raises(bt.BtError):
+        h.solve(to_dev(d["b"].reshape(-1), torch.float64), 1e-10)
+
+
+def test_grid_zero_rhs_and_iteration_cap():
+    d = lqrgen.lqr_instance(45, 12, 4, 5, 1)
+    P = bt.Params.polycoeff(2)
+    x, info, _ = grid_solve(d["D"], d["O"], np.zeros_like(d["b"]), P)
+    assert info[0]["status"] == bt.OK and info[0]["iters"] == 0
+    assert not np.any(x)
+    x, info, _ = grid_solve(d["D"], d["O"], d["b"], P, maxit=3)
+    assert info[0]["status"] == bt.NOT_CONVERGED and info[0]["iters"] == 3
+    # the iterate after 3 steps equals the oracle's
+    xr, ri = orc.pcg(d["D"], d["O"], d["b"], tol=1e-30, maxit=3,
+                     **oracle_kind(P))
+    assert ri["iters"] == 3
+    assert rel(x, xr) <= 1e-10
+
+
+def test_grid_not_spd_block():
+    d = lqrgen.lqr_instance(45, 6, 2, 6, 2)
+    D = d["D"].copy()
+    D[20] = -np.eye(6)
+    x, info, _ = grid_solve(D, d["O"], d["b"], bt.Params.polycoeff(2))
+    assert info[0]["status"] == bt.ENOTSPD
+    assert info[0]["fail_index"] == 20
+
+
+def test_grid_argument_checks():
+    import torch
+    d = workload("batch_ragged_n12", instances=3)
+    h = bt.Handle(to_dev(d["D"], torch.float64), to_dev(d["O"], torch.float64),
+                  d["offsets"], bt.Params.polycoeff(2))
+    with pytest.raises(bt.BtError):  # more than one system
+        h.solve_grid(to_dev(d["b"].reshape(-1), torch.float64))
