@@ -80,26 +80,46 @@ __device__ __forceinline__ double rec(const void* P, size_t i, int dtype) {
                             : (double)((const float*)P)[i];
 }
 
-// Sum over the workgroup, every thread gets it (fixed order).
-__device__ __forceinline__ double wg_sum(double v, double* red) {
-  red[threadIdx.x] = v;
+// Sums over the workgroup of K values per thread, every thread gets them:
+// a wavefront butterfly (lane 0's result is taken), then the four
+// wavefronts in a fixed order. Deterministic and the same in every
+// workgroup for the same inputs. ``red`` holds at least 4 K doubles.
+template <int K>
+__device__ __forceinline__ void wg_sums(double (&v)[K], double* red) {
+#pragma unroll
+  for (int k = 0; k < K; ++k)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) red[4 * k + wv] = v[k];
+  }
   __syncthreads();
 #pragma unroll
-  for (int h = NT / 2; h > 0; h >>= 1) {
-    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-    __syncthreads();
-  }
-  const double r = red[0];
+  for (int k = 0; k < K; ++k)
+    v[k] = (red[4 * k] + red[4 * k + 1]) + (red[4 * k + 2] + red[4 * k + 3]);
   __syncthreads();
-  return r;
 }
 
-// Sum of one partial slot over all workgroups, fixed order.
-__device__ __forceinline__ double slot_sum(const double* part, int slot,
-                                           int nwg, double* red) {
-  double s = 0.0;
-  for (int i = threadIdx.x; i < nwg; i += NT) s += part[slot * nwg + i];
-  return wg_sum(s, red);
+__device__ __forceinline__ double wg_sum(double v, double* red) {
+  double t[1] = {v};
+  wg_sums<1>(t, red);
+  return t[0];
+}
+
+// Sums of K partial slots over all workgroups (fixed order).
+template <int K>
+__device__ __forceinline__ void slot_sums(const double* part,
+                                          const int (&slot)[K], int nwg,
+                                          double* red, double (&out)[K]) {
+#pragma unroll
+  for (int k = 0; k < K; ++k) out[k] = 0.0;
+  for (int i = threadIdx.x; i < nwg; i += NT) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[k] += part[slot[k] * nwg + i];
+  }
+  wg_sums<K>(out, red);
 }
 
 // Settle the solve (workgroup 0 writes; the others took the same decision).
@@ -120,12 +140,39 @@ __device__ __forceinline__ Win window(int R, int rb, int d) {
   return w;
 }
 
+// The blocks F_b, b in [fb0, fb0 + cnt), of a workgroup: staged in LDS when
+// they fit (then C reads them from there), else read from memory.
+template <typename T>
+struct FBlocks {
+  const T* base;  // LDS copy, or F itself
+  int fb0;        // first block of the LDS copy (0 for F itself)
+  __device__ __forceinline__ const T* blk(int b, size_t nn) const {
+    return base + (size_t)(b - fb0) * nn;
+  }
+};
+
+constexpr size_t FSTAGE_MAX = 48 * 1024;  // bytes of staged blocks at most
+
+template <typename T>
+__device__ FBlocks<T> stage_F(const GArgs<T>& a, int b0, int b1, T* lds) {
+  const size_t nn = (size_t)a.n * a.n;
+  b0 = max(b0, 0);
+  b1 = min(b1, a.R - 1);  // F_b exists for b <= R - 2
+  FBlocks<T> f{a.F, 0};
+  if (lds == nullptr || b1 <= b0) return f;
+  const size_t cnt = (size_t)(b1 - b0) * nn;
+  const T* src = a.F + (size_t)b0 * nn;
+  for (size_t e = threadIdx.x; e < cnt; e += NT) lds[e] = src[e];
+  __syncthreads();
+  return FBlocks<T>{lds, b0};
+}
+
 // out = C v on rows [lo, hi); v valid on the rows it needs; both in the
 // window layout (row k at (k - w0) n). Same arithmetic order as the other
 // solve kernels: the F_{k-1}^T term, then the F_k term, in order j.
 template <typename T>
-__device__ void applyC(const GArgs<T>& a, const T* v, T* out, int w0, int lo,
-                       int hi) {
+__device__ void applyC(const GArgs<T>& a, const FBlocks<T>& F, const T* v,
+                       T* out, int w0, int lo, int hi) {
   const int n = a.n;
   const size_t nn = (size_t)n * n;
   const int cnt = (hi - lo) * n;
@@ -133,13 +180,13 @@ __device__ void applyC(const GArgs<T>& a, const T* v, T* out, int w0, int lo,
     const int k = lo + e / n, i = e % n;
     T acc = T(0);
     if (k > 0) {
-      const T* Fm = a.F + (size_t)(k - 1) * nn + i;
+      const T* Fm = F.blk(k - 1, nn) + i;
       const T* vm = v + (k - 1 - w0) * n;
 #pragma unroll 4
       for (int j = 0; j < n; ++j) acc += Fm[(size_t)j * n] * vm[j];
     }
     if (k < a.R - 1) {
-      const T* Fk = a.F + (size_t)k * nn + (size_t)i * n;
+      const T* Fk = F.blk(k, nn) + (size_t)i * n;
       const T* vp = v + (k + 1 - w0) * n;
 #pragma unroll 4
       for (int j = 0; j < n; ++j) acc += Fk[j] * vp[j];
@@ -157,15 +204,15 @@ __device__ __forceinline__ void shrink(int R, int& lo, int& hi) {
 // z = M^{-1} r on the own rows; r known on the whole window (LDS), y, w1,
 // w2, z window buffers. Returns with z valid on [k0, k1).
 template <typename T>
-__device__ void precond(const GArgs<T>& a, const Win& W, const T* r, T* y,
-                        T* w1, T* w2, T* z) {
+__device__ void precond(const GArgs<T>& a, const FBlocks<T>& F, const Win& W,
+                        const T* r, T* y, T* w1, T* w2, T* z) {
   const int n = a.n, w0 = W.w0;
   const T av = (T)a.a, om = (T)(1.0 - a.a);
   int lo = W.w0, hi = W.w1;
   // y_0 = r + a C r
   if (a.a != 0.0) {
     shrink(a.R, lo, hi);
-    applyC(a, r, w1, w0, lo, hi);
+    applyC(a, F, r, w1, w0, lo, hi);
     __syncthreads();
     for (int e = threadIdx.x; e < (hi - lo) * n; e += NT) {
       const int o = (lo - w0) * n + e;
@@ -182,11 +229,11 @@ __device__ void precond(const GArgs<T>& a, const Win& W, const T* r, T* y,
   __syncthreads();
   for (int m = 1; m < a.m; ++m) {
     shrink(a.R, lo, hi);
-    applyC(a, y, w1, w0, lo, hi);
+    applyC(a, F, y, w1, w0, lo, hi);
     __syncthreads();
     if (a.a != 0.0) {
       shrink(a.R, lo, hi);
-      applyC(a, w1, w2, w0, lo, hi);
+      applyC(a, F, w1, w2, w0, lo, hi);
       __syncthreads();
     }
     const T al = (T)a.alpha[m];
@@ -231,8 +278,8 @@ __device__ __forceinline__ void put_partial(const GArgs<T>& a, int slot,
 // BT_PC_NONE (M = I on the original system) z = L^T L r, a row-local map.
 // Returns the rho partial r'z (the accumulator of the precision).
 template <typename T>
-__device__ double precond_own(const GArgs<T>& a, const Win& W, T* r, T* y,
-                              T* w1, T* w2, T* z) {
+__device__ double precond_own(const GArgs<T>& a, const FBlocks<T>& F,
+                              const Win& W, T* r, T* y, T* w1, T* w2, T* z) {
   const int n = a.n, w0 = W.w0;
   if (a.pc == BT_PC_NONE) {
     for (int e = threadIdx.x; e < (W.k1 - W.k0) * n; e += NT) {
@@ -246,7 +293,7 @@ __device__ double precond_own(const GArgs<T>& a, const Win& W, T* r, T* y,
     }
     __syncthreads();
   } else {
-    precond(a, W, r, y, w1, w2, z);
+    precond(a, F, W, r, y, w1, w2, z);
   }
   typename AccOf<T>::type acc;
   acc.zero();
@@ -263,6 +310,30 @@ __device__ __forceinline__ T* lds_vec(double* red, int slot, int len) {
   return reinterpret_cast<T*>(red + NT) + (size_t)slot * len;
 }
 
+// Entries of one window vector in LDS: rb rows and the halo on both sides
+// (at least one row: k_g_q forms p on the neighbour rows).
+__host__ __device__ __forceinline__ int wlen(int rb, int depth, int n) {
+  return (rb + 2 * (depth > 1 ? depth : 1)) * n;
+}
+
+// Bytes of staged blocks: the window's (rb + 2 depth - 1) or, in k_g_q,
+// rb + 1 blocks.
+template <typename T>
+__host__ __device__ __forceinline__ size_t fstage_bytes(int rb, int depth,
+                                                        int n) {
+  return (size_t)(rb + 2 * depth + 1) * n * n * sizeof(T);
+}
+
+// LDS for staged blocks (after the five window vectors), or null when they
+// do not fit
+template <typename T>
+__device__ __forceinline__ T* lds_F(const GArgs<T>& a, double* red) {
+  const int lmax = wlen(a.rb, a.depth, a.n);
+  return fstage_bytes<T>(a.rb, a.depth, a.n) <= FSTAGE_MAX
+             ? lds_vec<T>(red, 5, lmax)
+             : nullptr;
+}
+
 // r = L^{-1} s on the window (s = a.src, float64, cast to T first),
 // z = M^{-1} r, partials rho (both rho slots of step 0), ||s||^2.
 template <typename T>
@@ -270,7 +341,7 @@ __global__ void __launch_bounds__(NT) k_g_init(GArgs<T> a) {
   extern __shared__ double red[];
   const Win W = window(a.R, a.rb, a.depth);
   const int n = a.n, len = (W.w1 - W.w0) * n;
-  const int lmax = (a.rb + 2 * a.depth) * n;
+  const int lmax = wlen(a.rb, a.depth, n);
   T* r = lds_vec<T>(red, 0, lmax);
   T* y = lds_vec<T>(red, 1, lmax);
   T* w1 = lds_vec<T>(red, 2, lmax);
@@ -280,6 +351,7 @@ __global__ void __launch_bounds__(NT) k_g_init(GArgs<T> a) {
     a.ctl->status = BT_NOT_CONVERGED;
     a.ctl->it = 0;
   }
+  const FBlocks<T> F = stage_F(a, W.w0, W.w1 - 1, lds_F(a, red));
   for (int e = threadIdx.x; e < len; e += NT)
     y[e] = (T)a.src[(size_t)W.w0 * n + e];
   __syncthreads();
@@ -296,7 +368,7 @@ __global__ void __launch_bounds__(NT) k_g_init(GArgs<T> a) {
   }
   __syncthreads();
   put_partial(a, P_NB2, nb, red);
-  const double rho = precond_own(a, W, r, y, w1, w2, z);
+  const double rho = precond_own(a, F, W, r, y, w1, w2, z);
   const double s = wg_sum(rho, red);
   if (threadIdx.x == 0) {
     a.part[P_RHO0 * a.nwg + blockIdx.x] = s;
@@ -306,23 +378,35 @@ __global__ void __launch_bounds__(NT) k_g_init(GArgs<T> a) {
 
 // Step i: the stopping test on the state after step i - 1, beta,
 // p = z + beta p (own rows and both neighbour rows), q = p - C p, sigma.
+// Everything the step reads is requested before the decisions.
 template <typename T>
 __global__ void __launch_bounds__(NT) k_g_q(GArgs<T> a, int i) {
   extern __shared__ double red[];
-  if (a.ctl->status != BT_NOT_CONVERGED) return;
+  const int st = a.ctl->status;
   const Win W = window(a.R, a.rb, 1);
   const int n = a.n, len = (W.w1 - W.w0) * n;
-  const int lmax = (a.rb + 2 * a.depth) * n;
+  const int lmax = wlen(a.rb, a.depth, n);
   T* p = lds_vec<T>(red, 0, lmax);
-  T* cp = lds_vec<T>(red, 1, lmax);
-  const double rho = slot_sum(a.part, i & 1, a.nwg, red);
+  T* zb = lds_vec<T>(red, 1, lmax);
+  T* cp = lds_vec<T>(red, 2, lmax);
+  const T* pin = a.pb[(i + 1) & 1];
+  T* pout = a.pb[i & 1];
+  for (int e = threadIdx.x; e < len; e += NT) {
+    const size_t g = (size_t)W.w0 * n + e;
+    zb[e] = a.z[g];
+    p[e] = i == 0 ? T(0) : pin[g];
+  }
+  const FBlocks<T> F = stage_F(a, W.k0 - 1, W.k1, lds_F(a, red));
+  double S[5];
+  slot_sums<5>(a.part, {i & 1, (i + 1) & 1, P_NB2, P_NR2, P_RHOF}, a.nwg,
+               red, S);
+  if (st != BT_NOT_CONVERGED) return;
+  const double rho = S[0], rprev = S[1], nb2 = S[2], nr2 = S[3], rho0 = S[4];
   if (!a.ir) {
-    const double nb2 = slot_sum(a.part, P_NB2, a.nwg, red);
     if (i == 0) {
       if (!(nb2 < INFINITY)) { settle(a.ctl, BT_ENONFINITE); return; }
       if (nb2 == 0.0) { settle(a.ctl, BT_OK); return; }
     } else {
-      const double nr2 = slot_sum(a.part, P_NR2, a.nwg, red);
       if (nr2 <= a.tol * a.tol * nb2) { settle(a.ctl, BT_OK); return; }
       if (!(nr2 < INFINITY)) { settle(a.ctl, BT_ENONFINITE); return; }
     }
@@ -332,26 +416,16 @@ __global__ void __launch_bounds__(NT) k_g_q(GArgs<T> a, int i) {
     }
   } else {  // inner solve of a refinement step: stop when r'z fell enough
     if (!(rho > 0.0)) { settle(a.ctl, BT_OK); return; }
-    if (i > 0) {
-      const double rho0 = slot_sum(a.part, P_RHOF, a.nwg, red);
-      if (rho <= a.itol * a.itol * rho0) { settle(a.ctl, BT_OK); return; }
+    if (i > 0 && rho <= a.itol * a.itol * rho0) {
+      settle(a.ctl, BT_OK);
+      return;
     }
   }
-  const T* pin = a.pb[(i + 1) & 1];
-  T* pout = a.pb[i & 1];
-  if (i == 0) {
-    for (int e = threadIdx.x; e < len; e += NT)
-      p[e] = a.z[(size_t)W.w0 * n + e];
-  } else {
-    const double rprev = slot_sum(a.part, (i + 1) & 1, a.nwg, red);
-    const T be = (T)(rho / rprev);
-    for (int e = threadIdx.x; e < len; e += NT) {
-      const size_t g = (size_t)W.w0 * n + e;
-      p[e] = a.z[g] + be * pin[g];
-    }
-  }
+  const T be = i == 0 ? T(0) : (T)(rho / rprev);
+  for (int e = threadIdx.x; e < len; e += NT)
+    p[e] = i == 0 ? zb[e] : zb[e] + be * p[e];
   __syncthreads();
-  applyC(a, p, cp, W.w0, W.k0, W.k1);
+  applyC(a, F, p, cp, W.w0, W.k0, W.k1);
   __syncthreads();
   typename AccOf<T>::type acc;
   acc.zero();
@@ -374,14 +448,26 @@ __global__ void __launch_bounds__(NT) k_g_u(GArgs<T> a, int i) {
   if (a.ctl->status != BT_NOT_CONVERGED) return;
   const Win W = window(a.R, a.rb, a.depth);
   const int n = a.n, len = (W.w1 - W.w0) * n;
-  const int lmax = (a.rb + 2 * a.depth) * n;
+  const int lmax = wlen(a.rb, a.depth, n);
   T* r = lds_vec<T>(red, 0, lmax);
   T* y = lds_vec<T>(red, 1, lmax);
   T* w1 = lds_vec<T>(red, 2, lmax);
   T* w2 = lds_vec<T>(red, 3, lmax);
   T* z = lds_vec<T>(red, 4, lmax);
-  const double sigma = slot_sum(a.part, P_SIG, a.nwg, red);
-  const double rho = slot_sum(a.part, i & 1, a.nwg, red);
+  const int st = a.ctl->status;
+  const T* rin = a.rbuf[i & 1];
+  T* rout = a.rbuf[(i + 1) & 1];
+  const T* p = a.pb[i & 1];
+  for (int e = threadIdx.x; e < len; e += NT) {
+    const size_t g = (size_t)W.w0 * n + e;
+    r[e] = rin[g];
+    y[e] = a.q[g];
+  }
+  const FBlocks<T> F = stage_F(a, W.w0, W.w1 - 1, lds_F(a, red));
+  double S[2];
+  slot_sums<2>(a.part, {P_SIG, i & 1}, a.nwg, red, S);
+  if (st != BT_NOT_CONVERGED) return;
+  const double sigma = S[0], rho = S[1];
   if (!(sigma > 0.0)) {
     settle(a.ctl, a.ir ? BT_OK : (sigma == sigma ? BT_EBREAKDOWN
                                                  : BT_ENONFINITE));
@@ -389,13 +475,10 @@ __global__ void __launch_bounds__(NT) k_g_u(GArgs<T> a, int i) {
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->it = i + 1;
   const T al = (T)(rho / sigma);
-  const T* rin = a.rbuf[i & 1];
-  T* rout = a.rbuf[(i + 1) & 1];
-  const T* p = a.pb[i & 1];
   for (int e = threadIdx.x; e < len; e += NT) {
     const int k = W.w0 + e / n;
     const size_t g = (size_t)W.w0 * n + e;
-    r[e] = rin[g] - al * a.q[g];
+    r[e] = r[e] - al * y[e];
     if (k >= W.k0 && k < W.k1) {
       a.xh[g] += al * p[g];
       rout[g] = r[e];
@@ -414,7 +497,7 @@ __global__ void __launch_bounds__(NT) k_g_u(GArgs<T> a, int i) {
     t2 = acc.value();
     put_partial(a, P_NR2, t2, red);
   }
-  const double rz = precond_own(a, W, r, y, w1, w2, z);
+  const double rz = precond_own(a, F, W, r, y, w1, w2, z);
   put_partial(a, (i + 1) & 1, rz, red);
 }
 
@@ -424,7 +507,7 @@ __global__ void __launch_bounds__(NT) k_g_x(GArgs<T> a, int add) {
   extern __shared__ double red[];
   const Win W = window(a.R, a.rb, 0);
   const int n = a.n;
-  T* v = lds_vec<T>(red, 0, (a.rb + 2 * a.depth) * n);
+  T* v = lds_vec<T>(red, 0, wlen(a.rb, a.depth, n));
   for (int e = threadIdx.x; e < (W.k1 - W.k0) * n; e += NT)
     v[e] = a.xh[(size_t)W.k0 * n + e];
   __syncthreads();
@@ -565,7 +648,9 @@ int run(const bt_handle* h, const double* b, double* x, double tol, int maxit,
   a.ctl = (Ctl*)((unsigned char*)scratch + sl.ctl);
   pl.grid = a.nwg;
   pl.lds = NT * sizeof(double) +
-           5 * (size_t)(a.rb + 2 * a.depth) * n * sizeof(T);
+           5 * (size_t)wlen(a.rb, a.depth, n) * sizeof(T);
+  const size_t fb = fstage_bytes<T>(a.rb, a.depth, n);
+  if (fb <= FSTAGE_MAX) pl.lds += fb;
   if (set_lds<T>(pl.lds) != hipSuccess) return BT_EHIP;
 
   std::vector<double> hp((size_t)P_SLOTS * a.nwg);
