@@ -241,6 +241,25 @@ def workloads_secondary(bt, torch, dev, only=SECONDARY):
                     "block_gemvs": int(inf["iters"]) *
                     gemv_count(p.a, p.m, p.pc),
                     "relres_true": float(inf["relres_true"])}
+                if name == "single_n12":
+                    # the same system with every PCG step a kernel over all
+                    # block rows (host-driven, wall-clock timed)
+                    xg, ig = h.solve_grid(b, tol)
+                    torch.cuda.synchronize()
+                    reps = 10
+                    t0 = time.perf_counter()
+                    for _ in range(reps):
+                        h.refactor()
+                        h.solve_grid(b, tol, x=xg, info=ig)
+                    torch.cuda.synchronize()
+                    msg = (time.perf_counter() - t0) * 1e3 / reps
+                    ing = bt.infos_to_numpy(ig)[0]
+                    rows[f"{vname}/{prec}/grid"] = {
+                        "solves_per_s": 1e3 / msg, "ms": msg,
+                        "iters": int(ing["iters"]),
+                        "outer": int(ing["outer"]),
+                        "status": int(ing["status"]),
+                        "relres_true": float(ing["relres_true"])}
         res[name] = rows
 
     if "batch_grad_n24" in only:
@@ -486,7 +505,18 @@ def main():
         hh.refactor()
         hh.solve(bb, tol)
     torch.cuda.synchronize()
-    plain_f64 = len(sample) / (time.perf_counter() - tp0)
+    plain_f64_wg = len(sample) / (time.perf_counter() - tp0)
+    # the same systems through the grid-wide single-system solve
+    for hh, bb in handles[:2]:
+        hh.solve_grid(bb, tol)
+    torch.cuda.synchronize()
+    tp0 = time.perf_counter()
+    for hh, bb in handles:
+        hh.refactor()
+        hh.solve_grid(bb, tol)
+    torch.cuda.synchronize()
+    plain_f64_grid = len(sample) / (time.perf_counter() - tp0)
+    plain_f64 = max(plain_f64_wg, plain_f64_grid)  # the faster path
     # batched FP64 on the same GPU (same kernels, float64 iteration)
     h64 = bt.Handle(Dd, Od, offs, p64)
     x64, i64 = h64.solve(b, tol)
@@ -580,6 +610,8 @@ def main():
             "batched_f64_solves_per_s": batched_f64,
             "f64_iters_mean": float(it64["iters"].mean()),
             "speedup_vs_plain_f64": value / plain_f64,
+            "plain_f64_single_instance_workgroup_solves_per_s": plain_f64_wg,
+            "plain_f64_single_instance_grid_solves_per_s": plain_f64_grid,
             "speedup_vs_batched_f64": value / batched_f64,
             "polynomial_order_sweep": order_sweep,
             "direct_block_cholesky_solves_per_s": (B * 1e3 / direct_ms
