@@ -485,25 +485,32 @@ hipError_t launch_offdiag_nb(const SetupArgs& a, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// Larger blocks (n = 16 ... 64): one wavefront per block row for the factors,
-// one workgroup per block row for F.
+// Larger blocks (n = 16 ... 64): half a wavefront (n <= 32) or a wavefront
+// per block row for the factors, one workgroup per block row for F.
 // ---------------------------------------------------------------------------
 
-// L_g = chol(D_g), Li_g = L_g^{-1}, float64, one wavefront per block row.
-// Cholesky by columns with lane r holding row r in registers: after the
-// pivot step of column j each lane publishes its entry of column j in LDS
-// and updates the rest of its row from that column (broadcast reads). The
-// inverse by forward substitution with lane c forming column c in
-// registers from the rows of L in LDS.
+// L_g = chol(D_g), Li_g = L_g^{-1}, float64; two block rows per wavefront
+// for n <= 32 (lanes 0..31 and 32..63), else one. Cholesky by columns with
+// lane r holding row r in registers: after the pivot step of column j each
+// lane publishes its entry of column j in LDS and updates the rest of its
+// row from that column (broadcast reads). The inverse row by row: lane r
+// holds row r of X = L^{-1}, row k is published once final and every later
+// row subtracts its multiple.
 template <int NB, typename T, typename Rec>
 __global__ void __launch_bounds__(64) k_factor_wave(SetupArgs a) {
+  // blocks per wavefront: two when a block row fits in half a wavefront
+  constexpr int BPW = NB <= 32 ? 2 : 1, LW = 64 / BPW;
   constexpr int NN = NB * NB, P = NB + 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  double* Ls = reinterpret_cast<double*>(smem_raw);  // [NB][P]: L, then X^T
-  double* rdiag = Ls + NB * P;                        // [NB]
-  const int64_t g = blockIdx.x;
-  const int r = threadIdx.x;
+  const int sub = threadIdx.x / LW;        // which block of the wavefront
+  const int r = threadIdx.x % LW;          // row of this lane in its block
+  double* Ls = reinterpret_cast<double*>(smem_raw) + sub * (NB * P + NB);
+  double* rdiag = Ls + NB * P;             // [NB]
+  const int64_t gb = (int64_t)blockIdx.x * BPW + sub;
+  const bool real = gb < a.R;              // the last wavefront may hold one
+  const int64_t g = real ? gb : a.R - 1;   // (always valid memory)
   const int rr = r < NB ? r : NB - 1;  // lanes past the block mirror the last row
+  const int base = sub * LW;           // lane 0 of this block
   double m[NB];
   {
     const Rec* D = (const Rec*)a.D + (size_t)g * NN + (size_t)rr * NB;
@@ -513,7 +520,7 @@ __global__ void __launch_bounds__(64) k_factor_wave(SetupArgs a) {
   bool ok = true;
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
-    double djj = __shfl(m[j], j);  // pivot from lane j
+    double djj = __shfl(m[j], base + j);  // pivot from lane j of the block
     if (!(djj > 0.0 && djj < INFINITY)) {
       ok = false;
       djj = 1.0;
@@ -530,14 +537,14 @@ __global__ void __launch_bounds__(64) k_factor_wave(SetupArgs a) {
       if (rr >= c) m[c] = fma(-m[j], lcj, m[c]);
     }
   }
-  if (!ok && r == 0) {
+  if (!ok && r == 0 && real) {
     const int inst = a.rowinst[g];
     atomicMin(&a.fail[inst], (int)(g - a.off[inst]));
   }
   __syncthreads();
-  if (a.L) {
+  if (a.L && real) {
     T* L = (T*)a.L + (size_t)g * NN;
-    for (int e = r; e < NN; e += 64) {
+    for (int e = r; e < NN; e += LW) {
       const int i = e / NB, j = e % NB;
       L[e] = (T)(j <= i ? Ls[i * P + j] : 0.0);
     }
@@ -568,7 +575,7 @@ __global__ void __launch_bounds__(64) k_factor_wave(SetupArgs a) {
       if (rr > k) x[c] = fma(-m[k], xk, x[c]);
     }
   }
-  if (r < NB) {
+  if (r < NB && real) {
     T* Li = (T*)a.Li + (size_t)g * NN + (size_t)r * NB;
 #pragma unroll
     for (int c = 0; c < NB; ++c) Li[c] = (T)x[c];
@@ -576,8 +583,12 @@ __global__ void __launch_bounds__(64) k_factor_wave(SetupArgs a) {
 }
 
 template <int NB>
+constexpr int factor_wave_bpw() { return NB <= 32 ? 2 : 1; }
+
+template <int NB>
 constexpr size_t factor_wave_lds() {
-  return sizeof(double) * ((size_t)NB * (NB + 1) + NB);
+  return factor_wave_bpw<NB>() * sizeof(double) *
+         ((size_t)NB * (NB + 1) + NB);
 }
 
 // F_g = Li_g O_g Li_{g+1}^T (zero for the last row of each instance), one
@@ -635,8 +646,10 @@ hipError_t launch_wave(const SetupArgs& a, hipStream_t s) {
     if (e0 != hipSuccess) return e0;
     fattr = true;
   }
-  hipLaunchKernelGGL((k_factor_wave<NB, T, Rec>), dim3((unsigned)a.R),
-                     dim3(64), flds, s, a);
+  constexpr int bpw = factor_wave_bpw<NB>();
+  hipLaunchKernelGGL((k_factor_wave<NB, T, Rec>),
+                     dim3((unsigned)((a.R + bpw - 1) / bpw)), dim3(64), flds,
+                     s, a);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !a.F) return e;
   if (NB == 24) return launch_offdiag<24, T, Rec>(a, s);
