@@ -118,6 +118,27 @@ def test_grid_above_single_workgroup_capacity():
         h.solve(to_dev(d["b"].reshape(-1), torch.float64), 1e-10)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32_ir"])
+def test_grid_n48_blocks_read_from_memory(prec):
+    # n = 48: the window's blocks do not fit the LDS staging area, so C reads
+    # them from memory; float32 record for the refinement case
+    d = lqrgen.lqr_instance(600, 48, 16, 9, 0, s=0.05)
+    D, O = d["D"], d["O"]
+    record = "f32" if prec == "f32_ir" else "f64"
+    if record == "f32":
+        D = D.astype(np.float32).astype(np.float64)
+        O = O.astype(np.float32).astype(np.float64)
+    P = bt.Params.polycoeff(2, prec=prec)
+    x, info, _ = grid_solve(D, O, d["b"], P, record=record)
+    assert info[0]["status"] == bt.OK, info
+    assert info[0]["relres_true"] <= (1e-10 if prec == "f32_ir" else 1e-9)
+    xd = orc.btchol_solve(D, O, d["b"])
+    assert rel(x, xd) <= 1e-6, rel(x, xd)
+    if prec == "f64":
+        xr, ri = orc.pcg(D, O, d["b"], tol=1e-10, **oracle_kind(P))
+        assert iteration_match(int(info[0]["iters"]), ri), (info, ri)
+
+
 def test_grid_zero_rhs_and_iteration_cap():
     d = lqrgen.lqr_instance(45, 12, 4, 5, 1)
     P = bt.Params.polycoeff(2)
