@@ -694,21 +694,27 @@ __global__ void k_setup_init(int B, int32_t* fail, int32_t* ctr) {
 }
 
 // dD_g = -lambda_g x_g^T ; dO_(g-i) = -(lambda_g x_{g+1}^T + x_g lambda_{g+1}^T)
+// ADJ_ROWS consecutive block rows per workgroup, the rows' entries as one
+// flat range (consecutive threads on consecutive entries of a row: coalesced
+// stores; fewer, longer workgroups than one per row).
+constexpr int ADJ_ROWS = 8;
 __global__ void __launch_bounds__(256)
-    k_adjoint_outer(int B, int n, const int64_t* off, const int32_t* rowinst,
-                    const double* x, const double* lam, double* dD,
-                    double* dO) {
-  const int64_t g = blockIdx.x;
-  const int inst = rowinst[g];
-  const bool has_next = g + 1 < off[inst + 1];
+    k_adjoint_outer(int B, int n, int64_t R, const int64_t* off,
+                    const int32_t* rowinst, const double* x, const double* lam,
+                    double* dD, double* dO) {
+  const int64_t g0 = (int64_t)blockIdx.x * ADJ_ROWS;
+  const int rows = (int)(R - g0 < ADJ_ROWS ? R - g0 : ADJ_ROWS);
   const int nn = n * n;
-  const double* xg = x + g * n;
-  const double* lg = lam + g * n;
-  for (int e = threadIdx.x; e < nn; e += 256) {
-    const int i = e / n, j = e - (e / n) * n;
-    if (dD) dD[(size_t)g * nn + e] = -lg[i] * xg[j];
-    if (dO && has_next)
-      dO[(size_t)(g - inst) * nn + e] = -(lg[i] * xg[n + j] + xg[i] * lg[n + j]);
+  for (int e = threadIdx.x; e < rows * nn; e += 256) {
+    const int rr = e / nn, w = e - rr * nn;
+    const int i = w / n, j = w - i * n;
+    const int64_t g = g0 + rr;
+    const int inst = rowinst[g];
+    const double* xg = x + g * n;
+    const double* lg = lam + g * n;
+    if (dD) dD[(size_t)g * nn + w] = -lg[i] * xg[j];
+    if (dO && g + 1 < off[inst + 1])
+      dO[(size_t)(g - inst) * nn + w] = -(lg[i] * xg[n + j] + xg[i] * lg[n + j]);
   }
 }
 
@@ -769,7 +775,8 @@ hipError_t bt_launch_adjoint_outer(int B, int n, int64_t R, const int64_t* off,
                                    const double* lam, double* dD, double* dO,
                                    hipStream_t s) {
   if (R <= 0) return hipSuccess;
-  hipLaunchKernelGGL(btk::k_adjoint_outer, dim3(R), dim3(256), 0, s, B, n, off,
-                     rowinst, x, lam, dD, dO);
+  const int64_t grid = (R + btk::ADJ_ROWS - 1) / btk::ADJ_ROWS;
+  hipLaunchKernelGGL(btk::k_adjoint_outer, dim3((unsigned)grid), dim3(256), 0,
+                     s, B, n, R, off, rowinst, x, lam, dD, dO);
   return hipGetLastError();
 }

@@ -154,6 +154,27 @@ def test_grid_zero_rhs_and_iteration_cap():
     assert rel(x, xr) <= 1e-10
 
 
+@pytest.mark.parametrize("N", [1, 2, 5])
+def test_grid_tiny_horizons(N):
+    d = lqrgen.lqr_instance(N, 6, 2, 12, N)
+    P = bt.Params.polycoeff(2)
+    x, info, _ = grid_solve(d["D"], d["O"], d["b"], P)
+    xr, ri = orc.pcg(d["D"], d["O"], d["b"], tol=1e-10, **oracle_kind(P))
+    assert info[0]["status"] == bt.OK, info
+    assert iteration_match(int(info[0]["iters"]), ri), (info, ri)
+    assert rel(x, orc.btchol_solve(d["D"], d["O"], d["b"])) <= 1e-9
+
+
+def test_grid_non_finite_rhs():
+    d = lqrgen.lqr_instance(45, 6, 2, 13, 0)
+    b = d["b"].copy()
+    b[7, 2] = np.nan
+    for prec in ("f64", "f32_ir"):
+        _, info, _ = grid_solve(d["D"], d["O"], b,
+                                bt.Params.polycoeff(2, prec=prec))
+        assert info[0]["status"] == bt.ENONFINITE, (prec, info)
+
+
 def test_grid_not_spd_block():
     d = lqrgen.lqr_instance(45, 6, 2, 6, 2)
     D = d["D"].copy()
