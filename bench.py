@@ -115,6 +115,17 @@ def copy_probe(mib):
     print(json.dumps({"copy_probe_bytes_each_way": n * 4, "launches": 3}))
 
 
+def copy_bandwidth(torch, mib=1024, reps=5):
+    """Measured device-to-device copy rate (read + write bytes per second):
+    the attainable HBM bandwidth next to the vendor's 8 TB/s."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    ms = _events_ms(lambda: dst.copy_(src), reps)
+    del src, dst
+    return 2 * n * 4 / (ms * 1e-3) / 1e9
+
+
 def apps_per_iteration(a, m):
     """Applications of the scaled off-diagonal operator per PCG iteration:
     one for A p, one for G_ab (if a != 0), then per extra polynomial term
@@ -539,6 +550,7 @@ def main():
 
     secondary = (None if args.no_workloads
                  else workloads_secondary(bt, torch, dev))
+    copy_gbps = copy_bandwidth(torch)
     # polynomial order on the same batch, kernel configuration and inner
     # tolerance (m = 2, alpha_1 = 7 is the timed configuration above; for
     # m = 3, 4 the last coefficient is the grid-search optimum 9)
@@ -600,6 +612,9 @@ def main():
             "solve_kernel_ms": solve_ms,
             "solve_kernel_source": kernel_source_hash(),
             "setup_plus_queue_ms": ms_per_step - solve_ms,
+            "copy_GBps": copy_gbps,
+            "solve_alg_frac_of_copy": nbytes / (solve_ms * 1e-3) / 1e9 /
+            copy_gbps,
             "solve_alg_GBps": nbytes / (solve_ms * 1e-3) / 1e9,
             "hbm_frac_of_alg_bytes": nbytes / (solve_ms * 1e-3) / 1e9 /
             PEAK_HBM_GBS,
