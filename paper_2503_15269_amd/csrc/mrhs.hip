@@ -45,13 +45,14 @@ typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int WG = 256;       // 4 wavefronts, 16 right-hand sides each
-// A block in LDS: rows of NB + 4 entries (the padding spreads the 16 rows a
-// wavefront reads at once over distinct banks), hi half then lo half.
+// A block in LDS: row r holds its NB / 4 groups of four columns as 16-byte
+// chunks (the four hi halves, then the four lo halves), so one 16-byte read
+// gives both A operands of a K step; rows are padded by one chunk, which
+// puts the 8 rows a quarter-wavefront reads at once on distinct banks.
 template <int NB>
 struct Lds {
-  static constexpr int LDR = NB + 4;    // row stride (bfloat16 entries)
-  static constexpr int HS = NB * LDR;   // one half
-  static constexpr int BLK = 2 * HS;    // one block
+  static constexpr int RS = 2 * NB + 8;  // row stride (bfloat16 entries)
+  static constexpr int BLK = NB * RS;    // one block
 };
 constexpr int CPW = 16;       // columns per wavefront
 constexpr int CPB = 64;       // columns per workgroup
@@ -126,13 +127,13 @@ __device__ __forceinline__ Spl<NB> split(const Pan<NB>& p) {
   return s;
 }
 
-// hi*hi + hi*lo + lo*hi into acc for one K step of 16 (A: 4 entries of the
-// block row in LDS at ``e``, hi and lo halves HS apart)
-template <int HS>
+// hi*hi + hi*lo + lo*hi into acc for one K step of 16; A: the 16-byte chunk
+// (4 hi, 4 lo entries of a block row) at ``e`` in LDS
 __device__ __forceinline__ f32x4 mma16(const unsigned short* A, int e,
                                        bf16x4 bh, bf16x4 bl, f32x4 acc) {
-  const bf16x4 ah = *reinterpret_cast<const bf16x4*>(A + e);
-  const bf16x4 al = *reinterpret_cast<const bf16x4*>(A + HS + e);
+  const uint4 c = *reinterpret_cast<const uint4*>(A + e);
+  const bf16x4 ah = __builtin_bit_cast(bf16x4, make_uint2(c.x, c.y));
+  const bf16x4 al = __builtin_bit_cast(bf16x4, make_uint2(c.z, c.w));
   acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc, 0, 0, 0);
   acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc, 0, 0, 0);
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
@@ -144,7 +145,7 @@ __device__ __forceinline__ void cprod_t(const unsigned short* Am,
                                         const unsigned short* Ap,
                                         const Spl<NB>& Vp, int l,
                                         f32x4 (&acc)[NB / 16]) {
-  constexpr int MT = NB / 16, LDR = Lds<NB>::LDR, HS = Lds<NB>::HS;
+  constexpr int MT = NB / 16, RS = Lds<NB>::RS;
   const int kq = 4 * (l >> 4);  // first K row of this lane in a K step
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -152,9 +153,10 @@ __device__ __forceinline__ void cprod_t(const unsigned short* Am,
   for (int ks = 0; ks < MT; ++ks) {
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
-      const int e = (16 * mt + (l & 15)) * LDR + 16 * ks + kq;  // 8-byte aligned
-      if constexpr (HP) acc[mt] = mma16<HS>(Ap, e, Vp.h[ks], Vp.lo[ks], acc[mt]);
-      if constexpr (HM) acc[mt] = mma16<HS>(Am, e, Vm.h[ks], Vm.lo[ks], acc[mt]);
+      // chunk of columns 16 ks + kq .. + 3 of row 16 mt + l mod 16
+      const int e = (16 * mt + (l & 15)) * RS + 2 * (16 * ks + kq);
+      if constexpr (HP) acc[mt] = mma16(Ap, e, Vp.h[ks], Vp.lo[ks], acc[mt]);
+      if constexpr (HM) acc[mt] = mma16(Am, e, Vm.h[ks], Vm.lo[ks], acc[mt]);
     }
   }
 }
@@ -211,12 +213,11 @@ struct Blocks {
     for (int q = 0; q < PER; ++q) {
       const int e = threadIdx.x + q * WG;
       if (NC % WG == 0 || e < NC) {
-        const int o = (e / PR) * Lds<NB>::LDR + 8 * (e % PR);  // 8-byte aligned
+        // 8 entries = two chunks of 4: (hi 0..3, lo 0..3), (hi 4..7, lo 4..7)
+        const int o = (e / PR) * Lds<NB>::RS + 16 * (e % PR);
         const uint4 h = vh[s * PER + q], w = vl[s * PER + q];
-        *reinterpret_cast<uint2*>(dst + o) = make_uint2(h.x, h.y);
-        *reinterpret_cast<uint2*>(dst + o + 4) = make_uint2(h.z, h.w);
-        *reinterpret_cast<uint2*>(dst + Lds<NB>::HS + o) = make_uint2(w.x, w.y);
-        *reinterpret_cast<uint2*>(dst + Lds<NB>::HS + o + 4) = make_uint2(w.z, w.w);
+        *reinterpret_cast<uint4*>(dst + o) = make_uint4(h.x, h.y, w.x, w.y);
+        *reinterpret_cast<uint4*>(dst + o + 8) = make_uint4(h.z, h.w, w.z, w.w);
       }
     }
   }
