@@ -500,12 +500,16 @@ template <int NB, typename T, typename Rec>
 __global__ void __launch_bounds__(64) k_factor_wave(SetupArgs a) {
   // blocks per wavefront: two when a block row fits in half a wavefront
   constexpr int BPW = NB <= 32 ? 2 : 1, LW = 64 / BPW;
-  constexpr int NN = NB * NB, P = NB + 1;
+  constexpr int NN = NB * NB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int sub = threadIdx.x / LW;        // which block of the wavefront
   const int r = threadIdx.x % LW;          // row of this lane in its block
-  double* Ls = reinterpret_cast<double*>(smem_raw) + sub * (NB * P + NB);
-  double* rdiag = Ls + NB * P;             // [NB]
+  // per block: two column buffers (Cholesky step j uses col[j & 1]) and two
+  // row buffers (inverse step k uses row[k & 1]); alternating buffers let a
+  // step write while the previous one's readers may still be reading, so
+  // each step needs one barrier
+  double* col = reinterpret_cast<double*>(smem_raw) + sub * 4 * NB;
+  double* row = col + 2 * NB;
   const int64_t gb = (int64_t)blockIdx.x * BPW + sub;
   const bool real = gb < a.R;              // the last wavefront may hold one
   const int64_t g = real ? gb : a.R - 1;   // (always valid memory)
@@ -518,6 +522,7 @@ __global__ void __launch_bounds__(64) k_factor_wave(SetupArgs a) {
     for (int j = 0; j < NB; ++j) m[j] = (double)D[j];
   }
   bool ok = true;
+  double myrd = 1.0;  // 1 / L[rr][rr]
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
     double djj = __shfl(m[j], base + j);  // pivot from lane j of the block
@@ -526,28 +531,24 @@ __global__ void __launch_bounds__(64) k_factor_wave(SetupArgs a) {
       djj = 1.0;
     }
     const double dj = sqrt(djj), rd = 1.0 / dj;
-    if (rr > j) m[j] *= rd;
-    if (rr == j) m[j] = dj;
-    if (r < NB) Ls[r * P + j] = m[j];
-    if (r == 0) rdiag[j] = rd;
+    // the entries above the diagonal of a lane's row are never read, so the
+    // updates below run unmasked (no branches in the unrolled loops)
+    m[j] = rr == j ? dj : m[j] * rd;
+    if (rr == j) myrd = rd;
+    double* cj = col + (j & 1) * NB;
+    if (r < NB) cj[r] = m[j];  // column j of L (rows above j never read)
     __syncthreads();
 #pragma unroll
-    for (int c = j + 1; c < NB; ++c) {
-      const double lcj = Ls[c * P + j];
-      if (rr >= c) m[c] = fma(-m[j], lcj, m[c]);
-    }
+    for (int c = j + 1; c < NB; ++c) m[c] = fma(-m[j], cj[c], m[c]);
   }
   if (!ok && r == 0 && real) {
     const int inst = a.rowinst[g];
     atomicMin(&a.fail[inst], (int)(g - a.off[inst]));
   }
-  __syncthreads();
-  if (a.L && real) {
-    T* L = (T*)a.L + (size_t)g * NN;
-    for (int e = r; e < NN; e += LW) {
-      const int i = e / NB, j = e % NB;
-      L[e] = (T)(j <= i ? Ls[i * P + j] : 0.0);
-    }
+  if (a.L && real && r < NB) {  // row r of L is in this lane's registers
+    T* L = (T*)a.L + (size_t)g * NN + (size_t)r * NB;
+#pragma unroll
+    for (int c = 0; c < NB; ++c) L[c] = (T)(c <= r ? m[c] : 0.0);
   }
   // X = L^{-1} by the same scheme, lane r holding row r of X: at step k
   // row k is final (scaled by 1 / L[k][k]) and published; every row i > k
@@ -555,25 +556,20 @@ __global__ void __launch_bounds__(64) k_factor_wave(SetupArgs a) {
   double x[NB];
 #pragma unroll
   for (int c = 0; c < NB; ++c) x[c] = (c == rr) ? 1.0 : 0.0;
-  double* Xs = Ls;  // L is no longer read from LDS
 #pragma unroll
   for (int k = 0; k < NB; ++k) {
-    if (rr == k) {
-      const double rk = rdiag[k];
+    const double sc = rr == k ? myrd : 1.0;  // row k becomes final
 #pragma unroll
-      for (int c = 0; c <= k; ++c) x[c] *= rk;
-    }
-    __syncthreads();  // previous readers of row k-1 are done
+    for (int c = 0; c <= k; ++c) x[c] *= sc;
+    double* rk = row + (k & 1) * NB;
     if (r == k) {
 #pragma unroll
-      for (int c = 0; c <= k; ++c) Xs[k * P + c] = x[c];
+      for (int c = 0; c <= k; ++c) rk[c] = x[c];
     }
     __syncthreads();
+    const double f = rr > k ? m[k] : 0.0;  // rows below k subtract it
 #pragma unroll
-    for (int c = 0; c <= k; ++c) {
-      const double xk = Xs[k * P + c];
-      if (rr > k) x[c] = fma(-m[k], xk, x[c]);
-    }
+    for (int c = 0; c <= k; ++c) x[c] = fma(-f, rk[c], x[c]);
   }
   if (r < NB && real) {
     T* Li = (T*)a.Li + (size_t)g * NN + (size_t)r * NB;
@@ -587,8 +583,7 @@ constexpr int factor_wave_bpw() { return NB <= 32 ? 2 : 1; }
 
 template <int NB>
 constexpr size_t factor_wave_lds() {
-  return factor_wave_bpw<NB>() * sizeof(double) *
-         ((size_t)NB * (NB + 1) + NB);
+  return factor_wave_bpw<NB>() * sizeof(double) * 4 * (size_t)NB;
 }
 
 // F_g = Li_g O_g Li_{g+1}^T (zero for the last row of each instance), one
