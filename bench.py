@@ -333,8 +333,27 @@ def _multirhs_n48(bt, torch, dev, tol, one):
     D = torch.tensor(Dd, device=dev)
     O = torch.tensor(Od, device=dev)
     Bm = torch.tensor(d["b"], dtype=torch.float64, device=dev)
+    # inner tolerance tuned on this system: the bfloat16 split operator is
+    # accurate to ~1e-5, so every refinement step gains at most ~1e-4..1e-5
+    # and a looser inner solve costs fewer iterations for the same 3 steps
+    tuning = {}
+    best = None
+    for itol in (1e-4, 2e-4, 3e-4, 5e-4):
+        h = bt.Handle(D, O, None, bt.Params.polycoeff(2, prec="bf16x2_ir",
+                                                      inner_tol=itol))
+        X, minfo = h.solve_mrhs(Bm, tol)
+        torch.cuda.synchronize()
+        mi = bt.infos_to_numpy(minfo)
+        ok = bool(np.all(mi["status"] == bt.OK))
+        ms = _events_ms(lambda: (h.refactor(), h.solve_mrhs(Bm, tol, X=X)), 3)
+        tuning[f"{itol:g}"] = {"ms": ms, "ok": ok,
+                               "iters_mean": float(mi["iters"].mean())}
+        if ok and (best is None or ms < best[0]):
+            best = (ms, itol)
+        del h, X
+    assert best is not None
     h = bt.Handle(D, O, None, bt.Params.polycoeff(2, prec="bf16x2_ir",
-                                                  inner_tol=1e-4))
+                                                  inner_tol=best[1]))
     X, minfo = h.solve_mrhs(Bm, tol)
     torch.cuda.synchronize()
     mi = bt.infos_to_numpy(minfo)
@@ -342,6 +361,7 @@ def _multirhs_n48(bt, torch, dev, tol, one):
     mr_ms = _events_ms(lambda: (h.refactor(), h.solve_mrhs(Bm, tol, X=X)), 5)
     return {
         "ms": mr_ms, "rhs_solves_per_s": w["nrhs"] * 1e3 / mr_ms,
+        "inner_tol": best[1], "inner_tol_tuning": tuning,
         "iters_mean": float(mi["iters"].mean()),
         "outer_mean": float(mi["outer"].mean()),
         "relres_true_max": float(mi["relres_true"].max())}
