@@ -77,3 +77,16 @@ def test_bench_refuses_more_than_one_gpu():
     assert p.returncode == 2
     msg = json.loads(p.stdout.strip().splitlines()[-1])
     assert msg["n_gpus"] == 2 and "one GPU" in msg["error"]
+
+
+def test_complexity_slope_and_crossover():
+    from paper_2503_15269_amd import complexity as cx
+    k, c = cx.fit_slope([1, 2, 3, 4], [3.0, 5.0, 7.0, 9.0])
+    assert k == pytest.approx(2.0) and c == pytest.approx(1.0)
+    rows = [dict(N=8, d=1.0, p=2.0), dict(N=32, d=3.0, p=2.0),
+            dict(N=128, d=9.0, p=2.5), dict(N=512, d=30.0, p=3.0)]
+    assert cx.crossover(rows, "d", "p") == 32
+    # faster at one size but slower again above it: no lasting crossover
+    rows[-1]["p"] = 40.0
+    assert cx.crossover(rows, "d", "p") is None
+    assert cx.crossover(rows[:1], "d", "p") is None
