@@ -11,6 +11,7 @@
 
 #include "grid.h"
 #include "internal.h"
+#include "pack.h"
 
 namespace {
 
@@ -127,69 +128,6 @@ int config_for(const bt_handle* h) {
   for (int v = 0; v < BT_FAST_VARIANTS; ++v)  // 3 entries per lane first
     if (h->nbins[v] > 0) return fast_index() + v;
   return generic_config(h);
-}
-
-// First-fit-decreasing packing of the systems (longest first) into bins of
-// the register-resident kernel: each system takes its length rounded up to
-// whole wavefronts of rows; a bin holds at most ``cap`` rows.
-void pack_bins(const std::vector<int32_t>& order, const int64_t* off, int rpw,
-               int cap, int maxper, std::vector<int32_t>& bins,
-               std::vector<int32_t>& items) {
-  std::vector<int> used;
-  std::vector<std::vector<int32_t>> members;
-  for (int32_t id : order) {
-    const int len = (int)(off[id + 1] - off[id]);
-    const int pad = (len + rpw - 1) / rpw * rpw;
-    size_t b = 0;
-    for (; b < used.size(); ++b)
-      if (used[b] + pad <= cap && (int)members[b].size() < maxper) break;
-    if (b == used.size()) {
-      used.push_back(0);
-      members.emplace_back();
-    }
-    used[b] += pad;
-    members[b].push_back(id);
-  }
-  bins.clear();
-  items.clear();
-  for (size_t b = 0; b < members.size(); ++b) {
-    bins.push_back((int32_t)items.size());
-    bins.push_back((int32_t)members[b].size());
-    items.insert(items.end(), members[b].begin(), members[b].end());
-  }
-}
-
-// Bin capacity for ``slots`` workgroups resident at once. Bins of the full
-// capacity can leave compute units idle: a batch of few rows fills only a few
-// bins, and the last round of a longer queue is partial. The smallest
-// capacity (whole wavefronts, at least the longest system) that packs the
-// systems into no more bins than those rounds of ``slots`` hold spreads the
-// same rows over more workgroups with less work each.
-int balanced_capacity(const std::vector<int32_t>& order, const int64_t* off,
-                      int rpw, int full, int maxper, int slots, int nbins,
-                      std::vector<int32_t>& bins, std::vector<int32_t>& items) {
-  if (slots < 1 || nbins < 1) return full;
-  int64_t total = 0;
-  int longest = 0;
-  for (int32_t id : order) {
-    const int len = (int)(off[id + 1] - off[id]);
-    const int pad = (len + rpw - 1) / rpw * rpw;
-    total += pad;
-    longest = std::max(longest, pad);
-  }
-  const int64_t target = (int64_t)((nbins + slots - 1) / slots) * slots;
-  const int64_t even = (total + target - 1) / target;
-  int cap = (int)std::max<int64_t>(longest, (even + rpw - 1) / rpw * rpw);
-  std::vector<int32_t> b2, i2;
-  for (; cap < full; cap += rpw) {
-    pack_bins(order, off, rpw, cap, maxper, b2, i2);
-    if ((int64_t)(b2.size() / 2) <= target) {
-      bins.swap(b2);
-      items.swap(i2);
-      return cap;
-    }
-  }
-  return full;
 }
 
 int hip_status(hipError_t e) { return e == hipSuccess ? BT_OK : BT_EHIP; }
@@ -369,12 +307,13 @@ int bt_batch_setup(bt_handle** h, int B, const int64_t* offsets_host, int n,
     if (bt_fast_params(p) && bt_fast_supported(n, p->prec, v) &&
         maxN <= bt_fast_rows_per_bin(n)) {
       const int rpw = bt_fast_rows_per_wave(n, v);
-      pack_bins(order, offsets_host, rpw, bt_fast_rows_per_bin(n),
-                bt_fast_max_systems_per_bin(), bins[v], items[v]);
-      balanced_capacity(order, offsets_host, rpw, bt_fast_rows_per_bin(n),
-                        bt_fast_max_systems_per_bin(),
-                        bt_fast_max_grid(n, v), (int)(bins[v].size() / 2),
-                        bins[v], items[v]);
+      const int full = bt_fast_rows_per_bin(n);
+      const int maxper = bt_fast_max_systems_per_bin();
+      btpack::pack_bins(order, offsets_host, rpw, full, maxper, bins[v],
+                        items[v]);
+      btpack::balanced_capacity(order, offsets_host, rpw, full, maxper,
+                                bt_fast_max_grid(n, v),
+                                (int)(bins[v].size() / 2), bins[v], items[v]);
       hh->nbins[v] = (int)(bins[v].size() / 2);
     }
   }
