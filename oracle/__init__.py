@@ -55,7 +55,7 @@ def _bind(path):
         "or_apply_Gab": (I, [I, I, Dd, Dd, P, P, P, P]),
         "or_apply_Hab": (I, [I, I, Dd, Dd, P, P, P, P]),
         "or_precond": (I, [I, I, I, Dd, Dd, I, P, P, P, P, P]),
-        "or_pcg": (I, [I, I, P, P, P, I, Dd, Dd, I, P, Dd, I, P, P, P]),
+        "or_pcg": (I, [I, I, P, P, P, I, Dd, Dd, I, P, Dd, I, P, P, P, P]),
         "or_adjoint": (I, [I, I, P, P, P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
@@ -248,8 +248,9 @@ def polycoeff(m):
 
 
 def pcg(D, O, bvec, kind=PC_OPT, a=1.0, b=-1.0, m=2, alpha=None,
-        tol=1e-10, maxit=None, history=False):
-    """Textbook PCG from x0 = 0 with the preconditioner of ``precond``.
+        tol=1e-10, maxit=None, history=False, x0=None):
+    """Textbook PCG from x0 = 0 (or the initial guess ``x0``) with the
+    preconditioner of ``precond``; the test is ||r_j|| <= tol ||b||.
 
     Returns (x, info) with info = dict(status, iters, relres, ratio_last,
     ratio_prev[, hist]); ratio_* = ||r_j|| / (tol ||b||) at the last two
@@ -265,7 +266,8 @@ def pcg(D, O, bvec, kind=PC_OPT, a=1.0, b=-1.0, m=2, alpha=None,
     st = _load().or_pcg(N, n, _p(_c(D)), _p(_c(O)),
                         _p(_c(bvec).reshape(N, n)), int(kind), float(a),
                         float(b), int(m), _p(al), float(tol), int(maxit),
-                        _p(x), _p(out), _p(hist) if history else None)
+                        _p(x), _p(out), _p(hist) if history else None,
+                        _p(_c(x0).reshape(N, n)) if x0 is not None else None)
     info = dict(status=int(st), iters=int(out[0]), relres=float(out[1]),
                 ratio_last=float(out[2]), ratio_prev=float(out[3]))
     if history:

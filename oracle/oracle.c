@@ -535,8 +535,9 @@ int or_precond(int kind, int N, int n, double a, double b, int m,
 /* ------------------------------------------------------------------ */
 /* Preconditioned conjugate gradient (textbook form; the paper cites    */
 /* Saad's and Nocedal-Wright's statements of it, Sections I and IV-C).  */
-/* x_0 = 0. Stops when ||r_j||_2 <= tol ||b||_2 on the recursive        */
-/* residual. Iteration count = number of products A p.                  */
+/* x_0 = 0, or the initial guess x0 when x0 is not NULL (then          */
+/* r_0 = b - A x_0). Stops when ||r_j||_2 <= tol ||b||_2 on the         */
+/* recursive residual. Iteration count = number of products A p.        */
 /*                                                                      */
 /* out[0] = iterations, out[1] = ||r_final||/||b||, out[2] = last ratio */
 /* ||r_j||/(tol||b||), out[3] = the ratio one iteration earlier.         */
@@ -545,23 +546,28 @@ int or_precond(int kind, int N, int n, double a, double b, int m,
 /* ------------------------------------------------------------------ */
 int or_pcg(int N, int n, const double *D, const double *O, const double *bv,
            int kind, double a, double b, int m, const double *alpha,
-           double tol, int maxit, double *x, double *out, double *hist) {
+           double tol, int maxit, double *x, double *out, double *hist,
+           const double *x0) {
   size_t len = (size_t)N * n;
   pc_t pc;
   int rc = pc_init(&pc, kind, N, n, a, b, m, alpha, D, O);
   for (int i = 0; i < 4; ++i) out[i] = 0.0;
-  for (size_t i = 0; i < len; ++i) x[i] = 0.0;
+  for (size_t i = 0; i < len; ++i) x[i] = x0 ? x0[i] : 0.0;
   if (rc) { pc_free(&pc); return OR_ENOTSPD; }
   double *r = (double *)malloc(sizeof(double) * len);
   double *z = (double *)malloc(sizeof(double) * len);
   double *p = (double *)malloc(sizeof(double) * len);
   double *q = (double *)malloc(sizeof(double) * len);
   memcpy(r, bv, sizeof(double) * len);
+  if (x0) { /* r_0 = b - A x_0 */
+    or_spmv(N, n, D, O, x0, q);
+    for (size_t i = 0; i < len; ++i) r[i] -= q[i];
+  }
   double nb = sqrt(dot(len, bv, bv));
-  double nr = nb;
+  double nr = sqrt(dot(len, r, r));
   int j = 0, status = OR_NOT_CONVERGED;
   double prev_ratio = 0.0;
-  if (hist) hist[0] = (nb > 0.0) ? 1.0 : 0.0;
+  if (hist) hist[0] = (nb > 0.0) ? nr / nb : 0.0;
   if (nr <= tol * nb) {
     status = OR_OK;
     goto finish;

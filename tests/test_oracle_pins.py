@@ -529,3 +529,60 @@ def test_adjoint_matches_finite_differences():
             fd = (loss(D, Op, b) - loss(D, Om, b)) / (2 * h)
             g = dO[k, i, j]
         assert abs(fd - g) <= max(1e-6 * abs(g), 1e-7), (which, fd, g)
+
+
+# ------------------------------------------------------- initial guess x0
+@pytest.mark.parametrize("kind", ["none", "opt"])
+def test_pcg_from_x0_is_the_krylov_galerkin_iterate(kind):
+    """PCG from x0 (textbook: r0 = b - A x0): after k steps the iterate is
+    x0 + V y with V a basis of K_k(M^-1 A, M^-1 r0) and y from the Galerkin
+    condition V^T (b - A (x0 + V y)) = 0, i.e. the A-norm-optimal point of
+    the affine Krylov space; built densely from the paper's definitions."""
+    N, n = 4, 3
+    D, O = random_bt(N, n, 5)
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal((N, n))
+    x0 = rng.standard_normal((N, n))
+    A = dense_A(D, O)
+    if kind == "none":
+        Minv, kw = np.eye(N * n), dict(kind=orc.PC_NONE)
+    else:
+        G, H = G_H_ab(D, O, 1.0, -1.0)
+        Minv, kw = M_inv(G, H, 2, alpha=[1.0, 7.0]), dict(m=2,
+                                                          alpha=[1.0, 7.0])
+    r0 = b.reshape(-1) - A @ x0.reshape(-1)
+    w = Minv @ r0
+    for k in (1, 2, 3, 4):
+        x, info = orc.pcg(D, O, b, tol=1e-30, maxit=k, x0=x0, **kw)
+        assert info["iters"] == k and info["status"] == orc.NOT_CONVERGED
+        V = np.empty((N * n, k))
+        v = w
+        for j in range(k):
+            V[:, j] = v / np.linalg.norm(v)
+            v = Minv @ (A @ V[:, j])
+        y = np.linalg.solve(V.T @ A @ V, V.T @ r0)
+        xk = x0.reshape(-1) + V @ y
+        assert np.linalg.norm(x.reshape(-1) - xk) <= \
+            1e-9 * np.linalg.norm(xk), k
+
+
+def test_pcg_from_x0_limits():
+    D, O, b = lqr(16, 4, 2)
+    A = dense_A(D, O)
+    xd = np.linalg.solve(A, b.reshape(-1)).reshape(b.shape)
+    # the solution itself: the test passes before any iteration
+    x, info = orc.pcg(D, O, b, tol=1e-10, x0=xd)
+    assert info["status"] == orc.OK and info["iters"] == 0
+    assert np.array_equal(x, xd)
+    # x0 = 0 is the default start, bit for bit
+    x1, i1 = orc.pcg(D, O, b, tol=1e-10)
+    x2, i2 = orc.pcg(D, O, b, tol=1e-10, x0=np.zeros_like(b))
+    assert i1 == i2 and np.array_equal(x1, x2)
+    # a start near the solution needs fewer iterations; the test stays
+    # relative to ||b||
+    rng = np.random.default_rng(4)
+    xn = xd + 1e-6 * rng.standard_normal(xd.shape)
+    x3, i3 = orc.pcg(D, O, b, tol=1e-10, x0=xn)
+    assert i3["status"] == orc.OK and i3["iters"] < i1["iters"]
+    r = np.linalg.norm(b.reshape(-1) - A @ x3.reshape(-1))
+    assert r <= 1.01e-10 * np.linalg.norm(b)
