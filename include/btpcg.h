@@ -93,10 +93,18 @@ typedef struct bt_params {
   int max_outer;          /* BT_F32_IR: cap on refinement steps */
   double inner_tol;       /* BT_F32_IR: each inner solve stops when its
                              residual fell by this factor */
+  int warm_start;         /* 0: x0 = 0. 1: x holds the initial guess x0 on
+                             entry to bt_solve, bt_solve_batched,
+                             bt_solve_grid and bt_solve_mrhs; PCG then starts
+                             from r0 = b - A x0 (float64, from the system of
+                             record) and the test stays ||r|| <= tol ||b||.
+                             b = 0 still gives x = 0. bt_solve_adjoint and
+                             bt_precondition ignore it. */
 } bt_params;
 
 /* Defaults: a = 1, b = -1, m = 2, alpha = {1, 7} (the paper's "PolyCoeff"
- * choice, Section V), BT_PC_POLY, BT_F64, max_outer = 30, inner_tol = 1e-4. */
+ * choice, Section V), BT_PC_POLY, BT_F64, max_outer = 30, inner_tol = 1e-4,
+ * warm_start = 0. */
 void bt_default_params(bt_params* p);
 
 /* Per-instance outcome, written on the device (32 bytes). */

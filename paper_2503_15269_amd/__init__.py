@@ -35,7 +35,8 @@ class _Params(ctypes.Structure):
     _fields_ = [("a", ctypes.c_double), ("b", ctypes.c_double),
                 ("m", ctypes.c_int), ("pc", ctypes.c_int),
                 ("alpha", ctypes.c_double * MAX_M), ("prec", ctypes.c_int),
-                ("max_outer", ctypes.c_int), ("inner_tol", ctypes.c_double)]
+                ("max_outer", ctypes.c_int), ("inner_tol", ctypes.c_double),
+                ("warm_start", ctypes.c_int)]
 
 
 class BtError(RuntimeError):
@@ -123,7 +124,9 @@ class Params:
 
     a, b: splitting weights on 2a+b = 1, a >= 0, b >= -1 (b defaults to
     1-2a); m: polynomial order; alpha[i] multiplies H^i (alpha[0] ignored;
-    default: all ones); pc: "poly" or "none"; prec: "f64", "f32", "f32_ir".
+    default: all ones); pc: "poly" or "none"; prec: "f64", "f32", "f32_ir";
+    warm_start: the solves start from the x passed in (initial guess)
+    instead of 0.
     """
     a: float = 1.0
     b: Optional[float] = None
@@ -133,6 +136,7 @@ class Params:
     prec: str = "f64"
     max_outer: int = 30
     inner_tol: float = 1e-4
+    warm_start: bool = False
 
     @staticmethod
     def polycoeff(m: int = 2, **kw) -> "Params":
@@ -159,6 +163,7 @@ class Params:
                   "bf16x2_ir": BF16X2_IR}[self.prec]
         p.max_outer = int(self.max_outer)
         p.inner_tol = float(self.inner_tol)
+        p.warm_start = 1 if self.warm_start else 0
         return p
 
 
@@ -283,16 +288,24 @@ class Handle:
             raise ValueError(f"{name} must have {self.R * self.n} entries")
         return v
 
+    def _start(self, x, b):
+        """Output buffer; under ``warm_start`` also the initial guess."""
+        if x is None:
+            if self.params.warm_start:
+                raise ValueError("warm_start: pass the initial guess as x")
+            return _torch().empty_like(b)
+        return self._vec(x, "x")
+
     def default_maxit(self):
         return 10 * int(np.max(np.diff(self.offsets))) * self.n
 
     def solve(self, b, tol: float = 1e-10, maxit: Optional[int] = None,
               x=None, info=None, stream=None):
-        """x = A^{-1} b for every system; returns (x, info) on the device."""
+        """x = A^{-1} b for every system; returns (x, info) on the device.
+        With ``warm_start`` the iteration starts from the ``x`` passed in."""
         torch = _torch()
         b = self._vec(b, "b")
-        if x is None:
-            x = torch.empty_like(b)
+        x = self._start(x, b)
         if info is None:
             info = torch.empty(self.B * INFO_DTYPE.itemsize, dtype=torch.uint8,
                                device=self.device)
@@ -319,7 +332,13 @@ class Handle:
             raise BtError(EINVAL, "bt_mrhs_workspace_bytes")
         scratch = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         if X is None:
+            if self.params.warm_start:
+                raise ValueError("warm_start: pass the initial guess as X")
             X = torch.empty_like(B)
+        elif (X.shape != B.shape or X.dtype != torch.float64 or
+              not X.is_contiguous() or not X.is_cuda):
+            raise ValueError("X must be a contiguous float64 cuda tensor "
+                             "shaped like B")
         info = torch.empty(nrhs * INFO_DTYPE.itemsize, dtype=torch.uint8,
                            device=self.device)
         maxit = self.default_maxit() if maxit is None else int(maxit)
@@ -362,8 +381,7 @@ class Handle:
             raise BtError(EINVAL, "bt_grid_workspace_bytes")
         if scratch is None:
             scratch = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
-        if x is None:
-            x = torch.empty_like(b)
+        x = self._start(x, b)
         if info is None:
             info = torch.empty(INFO_DTYPE.itemsize, dtype=torch.uint8,
                                device=self.device)

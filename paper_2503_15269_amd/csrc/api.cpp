@@ -32,6 +32,7 @@ bool params_ok(const bt_params* p) {
     return false;
   for (int i = 1; i < p->m; ++i)
     if (!std::isfinite(p->alpha[i])) return false;
+  if (p->warm_start != 0 && p->warm_start != 1) return false;
   if (p->prec == BT_F32_IR || p->prec == BT_BF16X2_IR) {
     if (p->max_outer < 1) return false;
     if (!(p->inner_tol > 0.0 && p->inner_tol < 1.0)) return false;
@@ -172,6 +173,7 @@ SolveArgs base_args(const bt_handle* h) {
   for (int i = 0; i < BT_MAX_M; ++i) a.alpha[i] = i == 0 ? 1.0 : h->p.alpha[i];
   a.inner_tol = h->p.inner_tol;
   a.max_outer = h->p.max_outer;
+  a.warm = h->p.warm_start;
   a.off = h->off;
   a.order = h->order;
   a.ctr = h->ctr;
@@ -372,23 +374,33 @@ int bt_precondition(const bt_handle* h, const double* r, double* z,
   if (!h || !r || !z) return BT_EINVAL;
   SolveArgs a = base_args(h);
   a.mode = 1;
+  a.warm = 0;
   a.b = r;
   a.x = z;
   a.info = nullptr;
   return run(h, a, (hipStream_t)stream);
 }
 
-int bt_solve(const bt_handle* h, const double* b, double* x, double tol,
-             int maxit, bt_info* info, void* stream) {
+// bt_solve with the start chosen by the caller (warm: x holds x0 on entry)
+static int solve_from(const bt_handle* h, const double* b, double* x,
+                      double tol, int maxit, bt_info* info, int warm,
+                      void* stream) {
   if (!h || !b || !x || !info || !(tol >= 0.0) || maxit < 0) return BT_EINVAL;
   SolveArgs a = base_args(h);
   a.mode = 0;
+  a.warm = warm;
   a.b = b;
   a.x = x;
   a.info = info;
   a.tol = tol;
   a.maxit = maxit;
   return run(h, a, (hipStream_t)stream);
+}
+
+int bt_solve(const bt_handle* h, const double* b, double* x, double tol,
+             int maxit, bt_info* info, void* stream) {
+  return solve_from(h, b, x, tol, maxit, info, h ? h->p.warm_start : 0,
+                    stream);
 }
 
 int bt_solve_batched(const bt_handle* h, const double* b, double* x,
@@ -401,7 +413,7 @@ int bt_solve_adjoint(const bt_handle* h, const double* x, const double* g,
                      int maxit, bt_info* info, void* stream) {
   if (!h || !x || !g || !lambda) return BT_EINVAL;
   if (dO && h->R == h->B) dO = nullptr;  // no upper blocks at all
-  int rc = bt_solve(h, g, lambda, tol, maxit, info, stream);
+  int rc = solve_from(h, g, lambda, tol, maxit, info, 0, stream);
   if (rc != BT_OK) return rc;
   if (!dD && !dO) return BT_OK;
   return hip_status(bt_launch_adjoint_outer(h->B, h->n, h->R, h->off,
@@ -430,7 +442,7 @@ int bt_solve_mrhs(const bt_handle* h, int nrhs, const double* b, double* x,
   return bt_mrhs_run(h->R, h->n, nrhs, h->Fhi, h->Flo, (const float*)h->Li,
                      h->D, h->O, h->dtype, b, x, tol, maxit, h->p.max_outer,
                      h->p.inner_tol, h->p.m, h->p.m > 1 ? h->p.alpha[1] : 0.0,
-                     scratch, info, (hipStream_t)stream);
+                     h->p.warm_start, scratch, info, (hipStream_t)stream);
 }
 
 size_t bt_direct_workspace_bytes(const bt_handle* h) {

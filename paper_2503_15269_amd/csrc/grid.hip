@@ -526,7 +526,7 @@ __global__ void __launch_bounds__(NT) k_g_res(GArgs<T> a) {
   const Win W = window(a.R, a.rb, 0);
   const int n = a.n;
   const size_t nn = (size_t)n * n;
-  double s2 = 0.0;
+  double s2 = 0.0, b2 = 0.0;
   for (int e = threadIdx.x; e < (W.k1 - W.k0) * n; e += NT) {
     const int k = W.k0 + e / n, i = e % n;
     const double* xk = a.x + (size_t)k * n;
@@ -547,8 +547,10 @@ __global__ void __launch_bounds__(NT) k_g_res(GArgs<T> a) {
     const double rv = a.b[g] - acc;
     if (a.r64) a.r64[g] = rv;
     s2 += rv * rv;
+    b2 += a.b[g] * a.b[g];
   }
   put_partial(a, P_RES, s2, red);
+  put_partial(a, P_NB2, b2, red);
 }
 
 template <typename T>
@@ -689,7 +691,46 @@ int run(const bt_handle* h, const double* b, double* x, double tol, int maxit,
   int status = BT_NOT_CONVERGED, total = 0, outer = 0;
   double nb2 = 0.0, nr2 = 0.0, nrt2 = 0.0;
   const bool refine = h->p.prec == BT_F32_IR || h->p.prec == BT_BF16X2_IR;
-  if (!refine) {
+  const bool warm = h->p.warm_start != 0;
+  if (!refine && warm) {
+    // from the initial guess x0 (held in x): plain PCG on the correction,
+    // A d = r0 = b - A x0, with the test ||r|| <= tol ||b|| carried over to
+    // the correction's right-hand side
+    if (launch(k_g_res<T>, pl, s) != hipSuccess || !sync_state(true))
+      return BT_EHIP;
+    nb2 = host_slot(P_NB2);
+    const double nr02 = host_slot(P_RES);
+    nr2 = nrt2 = nr02;
+    outer = 1;
+    if (!(nb2 < INFINITY) || !(nr02 < INFINITY)) {
+      status = BT_ENONFINITE;
+    } else if (nb2 == 0.0) {  // b = 0: x = 0
+      if (hipMemsetAsync(x, 0, v * sizeof(double), s) != hipSuccess)
+        return BT_EHIP;
+      status = BT_OK;
+      nr2 = nrt2 = 0.0;
+    } else if (nr02 <= tol * tol * nb2) {
+      status = BT_OK;
+    } else {
+      a.src = a.r64;
+      a.tol = tol * std::sqrt(nb2 / nr02);
+      if (launch(k_g_init<T>, pl, s) != hipSuccess) return BT_EHIP;
+      int steps = 0;
+      if (!iterate(maxit, &steps)) return BT_EHIP;
+      status = ctl.status;
+      total = steps;
+      double* r64 = a.r64;
+      a.r64 = nullptr;
+      if (launch(k_g_x<T>, pl, s, 1) != hipSuccess ||
+          launch(k_g_res<T>, pl, s) != hipSuccess || !sync_state(true))
+        return BT_EHIP;
+      a.r64 = r64;
+      nr2 = total > 0 ? host_slot(P_NR2) : nr02;
+      nrt2 = host_slot(P_RES);
+      if (status == BT_NOT_CONVERGED && total > 0 && nr2 <= tol * tol * nb2)
+        status = BT_OK;
+    }
+  } else if (!refine) {
     // plain PCG in the precision of the factors
     a.src = b;
     if (launch(k_g_init<T>, pl, s) != hipSuccess) return BT_EHIP;
@@ -712,14 +753,21 @@ int run(const bt_handle* h, const double* b, double* x, double tol, int maxit,
   } else {
     // float inner PCG inside float64 refinement on the record
     a.ir = 1;
-    if (hipMemsetAsync(x, 0, v * sizeof(double), s) != hipSuccess)
+    if (!warm && hipMemsetAsync(x, 0, v * sizeof(double), s) != hipSuccess)
       return BT_EHIP;
     for (;;) {
       if (launch(k_g_res<T>, pl, s) != hipSuccess || !sync_state(true))
         return BT_EHIP;
       nr2 = host_slot(P_RES);
-      if (outer == 0) nb2 = nr2;
+      if (outer == 0) nb2 = host_slot(P_NB2);
       nrt2 = nr2;
+      if (warm && outer == 0 && nb2 == 0.0) {  // b = 0: x = 0
+        if (hipMemsetAsync(x, 0, v * sizeof(double), s) != hipSuccess)
+          return BT_EHIP;
+        nr2 = nrt2 = 0.0;
+        status = BT_OK;
+        break;
+      }
       if (nr2 <= tol * tol * nb2) { status = BT_OK; break; }
       if (!(nr2 < INFINITY)) { status = BT_ENONFINITE; break; }
       if (outer >= h->p.max_outer || total >= maxit) break;

@@ -51,6 +51,7 @@ struct SolveArgs {
   double alpha[BT_MAX_M];
   double tol, inner_tol;
   int maxit, max_outer;
+  int warm;          // mode 0: x holds an initial guess on entry
   const int64_t* off;
   const int32_t* order;
   const int32_t* bins;       // register-resident kernel: [nbins][2] (start, count)
@@ -111,7 +112,8 @@ int bt_mrhs_run(int64_t R, int n, int nrhs, const unsigned short* Fhi,
                 const unsigned short* Flo, const float* Li, const void* D,
                 const void* O, int dtype, const double* b, double* x,
                 double tol, int maxit, int max_outer, double inner_tol, int m,
-                double alpha1, void* scratch, bt_info* info, hipStream_t s);
+                double alpha1, int warm, void* scratch, bt_info* info,
+                hipStream_t s);
 size_t bt_direct_scratch_bytes(int64_t R, int n);
 bool bt_direct_supported(int n);
 hipError_t bt_launch_direct(int B, int n, int dtype, const int64_t* off,

@@ -557,7 +557,7 @@ __global__ void k_mr_bnorm(MrArgs a) {
   }
 }
 
-__global__ void k_mr_init_cols(MrArgs a) {
+__global__ void k_mr_init_cols(MrArgs a, int warm) {
   __shared__ double s[256];
   const int c = blockIdx.x;
   double v = 0.0;
@@ -568,6 +568,9 @@ __global__ void k_mr_init_cols(MrArgs a) {
     if (threadIdx.x < h) s[threadIdx.x] += s[threadIdx.x + h];
     __syncthreads();
   }
+  if (warm && s[0] == 0.0)  // b = 0: x = 0 whatever the initial guess
+    for (size_t e = threadIdx.x; e < (size_t)a.R * a.n; e += 256)
+      a.x[e * a.nrhs + c] = 0.0;
   if (threadIdx.x == 0) {
     const double nb = s[0];
     a.nb2[c] = nb;
@@ -807,8 +810,8 @@ hipError_t inner_iteration(MrArgs& a, hipStream_t s) {
 }
 
 template <int NB>
-int solve(const MrArgs& a0, double* r64, int max_outer, bt_info* info,
-          hipStream_t s) {
+int solve(const MrArgs& a0, double* r64, int max_outer, int warm,
+          bt_info* info, hipStream_t s) {
   MrArgs a = a0;
   const size_t N = (size_t)a.R * a.n * a.nrhs;
   const int grid_ew = (int)std::min<size_t>((N + 255) / 256, 4096);
@@ -825,16 +828,17 @@ int solve(const MrArgs& a0, double* r64, int max_outer, bt_info* info,
     *out = o;
     return true;
   };
-  hipLaunchKernelGGL(k_mr_zero_x, dim3(grid_ew), dim3(256), 0, s, a);
+  // x holds the initial guess on entry (warm), else the iteration starts at 0
+  if (!warm) hipLaunchKernelGGL(k_mr_zero_x, dim3(grid_ew), dim3(256), 0, s, a);
   hipLaunchKernelGGL(k_mr_bnorm, dim3(a.R), dim3(64), 0, s, a);
-  hipLaunchKernelGGL(k_mr_init_cols, dim3(a.nrhs), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_mr_init_cols, dim3(a.nrhs), dim3(256), 0, s, a, warm);
   for (int outer = 0;; ++outer) {
     if (a.dtype == BT_DT_F64)
       hipLaunchKernelGGL((k_mr_resid<NB, double>), dim3(a.R, a.nrhs / CPB),
-                         dim3(256), 0, s, a, r64, outer == 0 ? 1 : 0);
+                         dim3(256), 0, s, a, r64, outer == 0 && !warm);
     else
       hipLaunchKernelGGL((k_mr_resid<NB, float>), dim3(a.R, a.nrhs / CPB),
-                         dim3(256), 0, s, a, r64, outer == 0 ? 1 : 0);
+                         dim3(256), 0, s, a, r64, outer == 0 && !warm);
     hipLaunchKernelGGL((k_mr_colsum<SUM_RES>), dim3(a.nrhs), dim3(256), 0, s, a);
     if (!read_any(&hany)) return BT_EHIP;
     if (hany == 0 || outer >= max_outer) break;
@@ -884,7 +888,8 @@ int bt_mrhs_run(int64_t R, int n, int nrhs, const unsigned short* Fhi,
                 const unsigned short* Flo, const float* Li, const void* D,
                 const void* O, int dtype, const double* b, double* x,
                 double tol, int maxit, int max_outer, double inner_tol, int m,
-                double alpha1, void* scratch, bt_info* info, hipStream_t s) {
+                double alpha1, int warm, void* scratch, bt_info* info,
+                hipStream_t s) {
   btm::MrArgs a{};
   a.R = (int)R;
   a.n = n;
@@ -931,9 +936,9 @@ int bt_mrhs_run(int64_t R, int n, int nrhs, const unsigned short* Fhi,
   a.total = is + 4 * nrhs;
   a.outer = is + 5 * nrhs;
   a.status = is + 6 * nrhs;
-  if (n == 48) return btm::solve<48>(a, r64, max_outer, info, s);
-  if (n == 32) return btm::solve<32>(a, r64, max_outer, info, s);
-  if (n == 16) return btm::solve<16>(a, r64, max_outer, info, s);
-  if (n == 64) return btm::solve<64>(a, r64, max_outer, info, s);
+  if (n == 48) return btm::solve<48>(a, r64, max_outer, warm, info, s);
+  if (n == 32) return btm::solve<32>(a, r64, max_outer, warm, info, s);
+  if (n == 16) return btm::solve<16>(a, r64, max_outer, warm, info, s);
+  if (n == 64) return btm::solve<64>(a, r64, max_outer, warm, info, s);
   return BT_EINVAL;
 }

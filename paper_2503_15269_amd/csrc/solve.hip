@@ -278,17 +278,35 @@ __device__ __forceinline__ void solve_direct(const SolveArgs& a, Shared<T>& sh,
   double* x = a.x + in.r0 * in.n;
   bt_info* info = a.info + in.inst;
 
-  // bhat = L^{-1} b and ||b||^2
+  // ||b||^2; from an initial guess x0 (held in x on entry) the iteration
+  // solves for the correction: r0 = b - A x0 in float64 from the record
   T r[S], xh[S], p[S], q[S], z[S], t[S];
-  double nbp = 0.0;
+  double x0[S], r0[S];
+  double nbp = 0.0, nrp = 0.0;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const double bv = in.act[s] ? b[in.pidx(s)] : 0.0;
+    nbp += bv * bv;
+    x0[s] = a.warm && in.act[s] ? x[in.pidx(s)] : 0.0;
+    r0[s] = bv;
+  }
+  if (a.warm) {
+    const double* xd = op.stage_d(x0);
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+      if (in.act[s]) {
+        r0[s] = op.resid(a, xd, s);
+        nrp += r0[s] * r0[s];
+      }
+  }
+  const double nb2 = op.sumd(nbp);
+  const double nr02 = a.warm ? op.sumd(nrp) : nb2;
+  __syncthreads();  // the T buffers overlap the float64 view
+  // rhat = L^{-1} r0
   {
     T bt[S];
 #pragma unroll
-    for (int s = 0; s < S; ++s) {
-      double bv = in.act[s] ? b[in.pidx(s)] : 0.0;
-      nbp += bv * bv;
-      bt[s] = (T)bv;
-    }
+    for (int s = 0; s < S; ++s) bt[s] = (T)r0[s];
     const T* bs = op.stage(bt);
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -297,7 +315,6 @@ __device__ __forceinline__ void solve_direct(const SolveArgs& a, Shared<T>& sh,
       xh[s] = T(0);
     }
   }
-  const double nb2 = op.sumd(nbp);
   if (!(nb2 < INFINITY)) {  // NaN or Inf in b
 #pragma unroll
     for (int s = 0; s < S; ++s)
@@ -315,18 +332,19 @@ __device__ __forceinline__ void solve_direct(const SolveArgs& a, Shared<T>& sh,
   const double tol2 = a.tol * a.tol * nb2;
 
   int status = BT_NOT_CONVERGED, it = 0;
-  double nr2 = nb2;
-  // t = L r is only needed for BT_PC_NONE at the start (r = bhat, L r = b)
+  double nr2 = nr02;
+  if (nr02 <= tol2) status = BT_OK;  // the test before any step
+  // t = L r is only needed for BT_PC_NONE at the start (r = rhat, L r = r0)
   if (a.pc == BT_PC_NONE) {
 #pragma unroll
-    for (int s = 0; s < S; ++s)
-      t[s] = in.act[s] ? (T)b[in.pidx(s)] : T(0);
+    for (int s = 0; s < S; ++s) t[s] = in.act[s] ? (T)r0[s] : T(0);
   }
   op.precond(a, r, nullptr, t, z);
   double rho = op.dot(r, z);
 #pragma unroll
   for (int s = 0; s < S; ++s) p[s] = z[s];
-  if (!(rho > 0.0)) status = (rho == rho) ? BT_EBREAKDOWN : BT_ENONFINITE;
+  if (status == BT_NOT_CONVERGED && !(rho > 0.0))
+    status = (rho == rho) ? BT_EBREAKDOWN : BT_ENONFINITE;
 
   while (status == BT_NOT_CONVERGED && it < a.maxit) {
     // q = Ahat p = p - C p
@@ -373,14 +391,15 @@ __device__ __forceinline__ void solve_direct(const SolveArgs& a, Shared<T>& sh,
     rho = rho1;
   }
 
-  // x = L^{-T} xhat, then the float64 residual of the record
+  // x = x0 + L^{-T} xhat, then the float64 residual of the record
   double xo[S];
   {
     const T* xs = op.stage(xh);
 #pragma unroll
     for (int s = 0; s < S; ++s)
       xo[s] = in.act[s]
-                  ? (double)apply_lowerT<T>(in.Li, xs, in.n, in.k[s], in.i[s])
+                  ? x0[s] + (double)apply_lowerT<T>(in.Li, xs, in.n, in.k[s],
+                                                    in.i[s])
                   : 0.0;
   }
   const double* xd = op.stage_d(xo);
@@ -413,7 +432,7 @@ __device__ __forceinline__ void solve_ir(const SolveArgs& a, Shared<T>& sh,
   for (int s = 0; s < S; ++s) {
     double bv = in.act[s] ? b[in.pidx(s)] : 0.0;
     r64[s] = bv;
-    x64[s] = 0.0;
+    x64[s] = a.warm && in.act[s] ? x[in.pidx(s)] : 0.0;  // initial guess
     nbp += bv * bv;
   }
   const double nb2 = op.sumd(nbp);
@@ -434,7 +453,7 @@ __device__ __forceinline__ void solve_ir(const SolveArgs& a, Shared<T>& sh,
   for (int s = 0; s < S; ++s) t[s] = T(0);
 
   for (;;) {
-    if (outer > 0) {
+    if (outer > 0 || a.warm) {
       const double* xd = op.stage_d(x64);
       double rp = 0.0;
 #pragma unroll

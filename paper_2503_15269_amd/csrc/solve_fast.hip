@@ -438,6 +438,14 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
     const double tol2 = a.tol * a.tol * nb2;
     int outer = 0, total = 0;
     double nr2 = nb2;
+    if (a.warm) {  // initial guess x0 (held in x on entry) of running systems
+      if (!done && c.row_ok) {
+#pragma unroll
+        for (int e = 0; e < EPT; ++e)
+          sm.xs[c.lrow * NB + e0 + e] = a.x[g * NB + e0 + e];
+      }
+      __syncthreads();  // neighbour rows of xs are read by the residual
+    }
 
     for (;;) {
       // float64 residual of the record for the current iterate
@@ -451,7 +459,7 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
           if (c.row_ok && !done) {
             const int i = e0 + e;
             double acc = 0.0;
-            if (outer > 0) {
+            if (outer > 0 || a.warm) {
               const size_t db = (size_t)g * nn + (size_t)i * NB;
 #pragma unroll
               for (int jj = 0; jj < NB; ++jj)
@@ -478,7 +486,7 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
           r64f[e] = (float)r64;
         }
         const double s = c.sumd(rp);  // its barrier also orders xs reads
-        if (!done && outer > 0) nr2 = s;
+        if (!done && (outer > 0 || a.warm)) nr2 = s;
       }
       if (!done) {
         if (nr2 <= tol2) {

@@ -45,9 +45,36 @@ def test_strerror_and_defaults(lib):
     assert p.alpha[1] == 7.0 and p.max_outer == 30 and p.inner_tol == 1e-4
 
 
-def test_struct_sizes_match_header(lib):
-    assert ctypes.sizeof(bt._Params) == 104
-    assert bt.INFO_DTYPE.itemsize == 32
+def test_struct_sizes_match_header(lib, tmp_path):
+    """The ctypes mirror of bt_params and the numpy record of bt_info have
+    the header's sizes and field offsets (the C compiler's, via gcc)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no gcc")
+    fields = [f[0] for f in bt._Params._fields_]
+    info = list(bt.INFO_DTYPE.names)
+    src = tmp_path / "abi.c"
+    src.write_text(
+        "#include <stdio.h>\n#include <stddef.h>\n#include \"btpcg.h\"\n"
+        "int main(void) {\n"
+        '  printf("%zu\\n", sizeof(bt_params));\n' +
+        "".join(f'  printf("%zu\\n", offsetof(bt_params, {f}));\n'
+                for f in fields) +
+        '  printf("%zu\\n", sizeof(bt_info));\n' +
+        "".join(f'  printf("%zu\\n", offsetof(bt_info, {f}));\n'
+                for f in info) +
+        "  return 0;\n}\n")
+    exe = str(tmp_path / "abi")
+    subprocess.run([gcc, "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    exe], check=True)
+    got = [int(v) for v in subprocess.run([exe], capture_output=True,
+                                          text=True, check=True).stdout.split()]
+    want = [ctypes.sizeof(bt._Params)] + \
+        [getattr(bt._Params, f).offset for f in fields] + \
+        [bt.INFO_DTYPE.itemsize] + [bt.INFO_DTYPE.fields[f][1] for f in info]
+    assert got == want
 
 
 def _ws(lib, B, off, n, params):
@@ -69,6 +96,12 @@ def test_workspace_bytes_validation(lib):
     assert _ws(lib, 1, [0, 8], 4, bt.Params(m=0)) == 0
     assert _ws(lib, 1, [0, 8], 4, bt.Params(m=9)) == 0
     assert _ws(lib, 1, [0, 8], 4, bt.Params(prec="f32_ir", inner_tol=1.5)) == 0
+    assert _ws(lib, 1, [0, 8], 4, bt.Params(warm_start=True)) > 0
+    bad = bt.Params().to_c()
+    bad.warm_start = 2                                  # neither 0 nor 1
+    off = np.asarray([0, 8], dtype=np.int64)
+    assert lib.bt_workspace_bytes(1, off.ctypes.data_as(ctypes.c_void_p), 4,
+                                  ctypes.byref(bad)) == 0
     # f32 factors take half the bytes of f64 ones
     w64 = _ws(lib, 1, [0, 1000], 12, bt.Params(prec="f64"))
     w32 = _ws(lib, 1, [0, 1000], 12, bt.Params(prec="f32_ir"))
