@@ -12,7 +12,8 @@ import pytest
 import lqrgen
 import oracle as orc
 import paper_2503_15269_amd as bt
-from gpu_util import gpu_solve, iteration_match, oracle_kind, rel, workload
+from gpu_util import (gpu_solve, iteration_match, oracle_kind, rel, to_dev,
+                      workload)
 
 pytestmark = pytest.mark.gpu
 
@@ -101,6 +102,30 @@ def test_shapes_and_ragged_tails(N, n):
     """Sizes spanning several elements per thread and ragged tails."""
     d = lqrgen.lqr_instance(N, n, max(1, n // 3), 4242, N * 100 + n)
     _check_f64(d["D"], d["O"], d["b"], bt.Params.polycoeff(2))
+
+
+@pytest.mark.parametrize("N,n", [(682, 12), (256, 32), (128, 64)])
+def test_single_system_at_workgroup_capacity(N, n):
+    """The largest single systems one workgroup holds (N n <= 8192 unknowns):
+    float64 parity with the oracle and float32 + refinement to 1e-10; one
+    block row more is refused by bt_solve (bt_solve_grid takes it)."""
+    import torch
+    d = lqrgen.lqr_instance(N, n, max(1, n // 3), 4343, N + n, s=0.05)
+    _check_f64(d["D"], d["O"], d["b"], bt.Params.polycoeff(2))
+    x, info, _ = gpu_solve(d["D"], d["O"], d["b"],
+                           params=bt.Params.polycoeff(2, prec="f32_ir"))
+    assert info[0]["status"] == bt.OK and info[0]["relres_true"] <= 1e-10
+    big = lqrgen.lqr_instance(N + 1, n, max(1, n // 3), 4343, 0, s=0.05)
+    assert (N + 1) * n > 8192
+    h = bt.Handle(to_dev(big["D"], torch.float64),
+                  to_dev(big["O"], torch.float64), None,
+                  bt.Params.polycoeff(2))
+    bb = to_dev(big["b"].reshape(-1), torch.float64)
+    with pytest.raises(bt.BtError):
+        h.solve(bb)
+    xg, ig = h.solve_grid(bb)
+    torch.cuda.synchronize()
+    assert bt.infos_to_numpy(ig)[0]["status"] == bt.OK
 
 
 def test_batch_f64_per_instance_parity():
