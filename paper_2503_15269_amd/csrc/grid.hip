@@ -594,8 +594,9 @@ hipError_t launch(K kernel, const Plan<T>& pl, hipStream_t s, Args... args) {
 
 template <typename T>
 hipError_t set_lds(size_t lds) {
-  static size_t done = 0;  // largest size the attributes were raised to
-  if (lds <= 65536 || lds <= done) return hipSuccess;
+  // the size depends on the system, so the limit is set on every call that
+  // needs more than the default (a few runtime calls per solve)
+  if (lds <= 65536) return hipSuccess;
   const void* fns[] = {(const void*)k_g_init<T>, (const void*)k_g_q<T>,
                        (const void*)k_g_u<T>, (const void*)k_g_x<T>,
                        (const void*)k_g_res<T>};
@@ -604,7 +605,6 @@ hipError_t set_lds(size_t lds) {
         f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  done = lds;
   return hipSuccess;
 }
 

@@ -2,6 +2,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <atomic>
 #include <stdint.h>
 
 #include <vector>
@@ -42,6 +44,23 @@ struct bt_handle {
 };
 
 // Arguments of the persistent solve kernel (passed by value).
+// Raise the dynamic-LDS limit of kernel ``fn`` to ``bytes`` on the current
+// device, once per device: ``done`` holds one bit per device ordinal, set
+// after the attribute call succeeded (device ordinals past 63 make the call
+// every time). Safe to call from several host threads.
+inline hipError_t lds_limit(const void* fn, size_t bytes,
+                            std::atomic<uint64_t>& done) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const uint64_t bit = dev >= 0 && dev < 64 ? (uint64_t)1 << dev : 0;
+  if (bit && (done.load(std::memory_order_acquire) & bit)) return hipSuccess;
+  e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)bytes);
+  if (e == hipSuccess && bit) done.fetch_or(bit, std::memory_order_acq_rel);
+  return e;
+}
+
 struct SolveArgs {
   int B, n, dtype;
   int mode;          // 0 solve, 1 apply the preconditioner once

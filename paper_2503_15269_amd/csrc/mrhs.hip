@@ -774,14 +774,10 @@ hipError_t qu(const MrArgs& a, hipStream_t s) {
 template <int NB, int M, bool UPD>
 hipError_t post_m(const MrArgs& a, hipStream_t s) {
   constexpr size_t lds = (M >= 2 ? 6 : 2) * Lds<NB>::BLK * sizeof(unsigned short);
-  static bool attr = false;  // above 64 KiB of LDS the limit must be raised
-  if (!attr) {
-    const hipError_t e = hipFuncSetAttribute(
-        (const void*)k_mr_post<NB, M, UPD>,
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  // above 64 KiB of LDS the limit must be raised
+  static std::atomic<uint64_t> attr{0};
+  const hipError_t e = lds_limit((const void*)k_mr_post<NB, M, UPD>, lds, attr);
+  if (e != hipSuccess) return e;
   const int rows = 8 * ((a.R + 7) / 8);
   hipLaunchKernelGGL((k_mr_post<NB, M, UPD>), dim3(rows, a.nrhs / CPB),
                      dim3(WG), lds, s, a);

@@ -441,14 +441,10 @@ __global__ void __launch_bounds__((64 * OffdiagGeo<NB, T>::WPB))
 template <int NB, typename T, typename Rec>
 hipError_t launch_offdiag(const SetupArgs& a, hipStream_t s) {
   using G = OffdiagGeo<NB, T>;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(
-        (const void*)k_offdiag_rows<NB, T, Rec>,
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)G::LDS);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  static std::atomic<uint64_t> attr{0};
+  hipError_t e =
+      lds_limit((const void*)k_offdiag_rows<NB, T, Rec>, G::LDS, attr);
+  if (e != hipSuccess) return e;
   const int64_t rows_per_block = (int64_t)G::WPB * G::RPW;
   hipLaunchKernelGGL((k_offdiag_rows<NB, T, Rec>),
                      dim3((unsigned)((a.R + rows_per_block - 1) / rows_per_block)),
@@ -459,17 +455,12 @@ hipError_t launch_offdiag(const SetupArgs& a, hipStream_t s) {
 template <int NB, typename T, typename Rec>
 hipError_t launch_lane(const SetupArgs& a, hipStream_t s) {
   constexpr size_t lds = factor_lds<NB, T, Rec>();
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(
-        (const void*)k_factor_lane<NB, T, Rec>,
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  static std::atomic<uint64_t> attr{0};
+  hipError_t e = lds_limit((const void*)k_factor_lane<NB, T, Rec>, lds, attr);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_factor_lane<NB, T, Rec>), dim3((a.R + 63) / 64),
                      dim3(64), lds, s, a);
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   return launch_offdiag<NB, T, Rec>(a, s);
 }
@@ -633,14 +624,10 @@ __global__ void __launch_bounds__(256) k_offdiag_block(SetupArgs a) {
 template <int NB, typename T, typename Rec>
 hipError_t launch_wave(const SetupArgs& a, hipStream_t s) {
   constexpr size_t flds = factor_wave_lds<NB>();
-  static bool fattr = false;
-  if (!fattr) {
-    hipError_t e0 = hipFuncSetAttribute(
-        (const void*)k_factor_wave<NB, T, Rec>,
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)flds);
-    if (e0 != hipSuccess) return e0;
-    fattr = true;
-  }
+  static std::atomic<uint64_t> fattr{0};
+  const hipError_t e0 =
+      lds_limit((const void*)k_factor_wave<NB, T, Rec>, flds, fattr);
+  if (e0 != hipSuccess) return e0;
   constexpr int bpw = factor_wave_bpw<NB>();
   hipLaunchKernelGGL((k_factor_wave<NB, T, Rec>),
                      dim3((unsigned)((a.R + bpw - 1) / bpw)), dim3(64), flds,
@@ -649,14 +636,9 @@ hipError_t launch_wave(const SetupArgs& a, hipStream_t s) {
   if (e != hipSuccess || !a.F) return e;
   if (NB == 24) return launch_offdiag<24, T, Rec>(a, s);
   constexpr size_t lds = 4 * sizeof(double) * (size_t)NB * NB;
-  static bool attr = false;
-  if (!attr) {
-    e = hipFuncSetAttribute((const void*)k_offdiag_block<NB, T, Rec>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)lds);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  static std::atomic<uint64_t> attr{0};
+  e = lds_limit((const void*)k_offdiag_block<NB, T, Rec>, lds, attr);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_offdiag_block<NB, T, Rec>), dim3((unsigned)a.R),
                      dim3(256), lds, s, a);
   return hipGetLastError();

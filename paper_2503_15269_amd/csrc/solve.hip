@@ -650,15 +650,10 @@ size_t smem_bytes() {
 
 template <typename T, int NT, int S, int MODE>
 hipError_t launch_mode(const SolveArgs& a, int grid, hipStream_t st) {
-  static bool attr = false;
+  static std::atomic<uint64_t> attr{0};
   const size_t sm = smem_bytes<T, NT, S>();
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(
-        (const void*)k_solve<T, NT, S, MODE>,
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm);
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  const hipError_t e = lds_limit((const void*)k_solve<T, NT, S, MODE>, sm, attr);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_solve<T, NT, S, MODE>), dim3(grid), dim3(NT), sm, st,
                      a);
   return hipGetLastError();

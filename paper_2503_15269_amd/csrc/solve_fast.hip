@@ -650,14 +650,10 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
 template <int NB, int EPT, int M, typename Rec>
 hipError_t launch_one(const SolveArgs& a, int grid, hipStream_t s) {
   using G = Geo<NB, EPT>;
-  static bool attr = false;
-  if (!attr) {
-    hipError_t e = hipFuncSetAttribute(
-        (const void*)k_fast_ir<NB, EPT, M, Rec>,
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(Smem<NB, EPT>));
-    if (e != hipSuccess) return e;
-    attr = true;
-  }
+  static std::atomic<uint64_t> attr{0};
+  const hipError_t e = lds_limit((const void*)k_fast_ir<NB, EPT, M, Rec>,
+                                 sizeof(Smem<NB, EPT>), attr);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_fast_ir<NB, EPT, M, Rec>), dim3(grid), dim3(G::NT),
                      sizeof(Smem<NB, EPT>), s, a);
   return hipGetLastError();
