@@ -151,10 +151,15 @@ int launch_setup(const bt_handle* h, hipStream_t s, bool full) {
   a.F = h->F;
   a.L = full ? h->L : nullptr;
   a.Li = h->Li;
+  // only the register-resident kernel reads Li between a setup without L
+  // and the next full one; at n = 12 it takes the packed triangles
+  a.li_packed = !full && h->n == 12 && h->p.prec == BT_F32_IR;
   if (a.prec == BT_BF16X2_IR) a.prec = BT_F32_IR;  // float32 factors first
   h->full_valid = false;
+  h->li_packed = false;
   if (bt_launch_setup(a, s) != hipSuccess) return BT_EHIP;
   h->full_valid = full;
+  h->li_packed = a.li_packed != 0;
   if (h->Fhi)
     return hip_status(
         bt_mrhs_split((const float*)h->F, h->Fhi, h->Flo, h->R, h->n, s));
@@ -194,6 +199,7 @@ int run(const bt_handle* h, SolveArgs& a, hipStream_t s) {
     const int rc = launch_setup(h, s, true);
     if (rc != BT_OK) return rc;
   }
+  a.li_packed = h->li_packed;
   if (is_fast(cfg)) {
     const int v = cfg - fast_index();
     a.bins = h->bins[v];

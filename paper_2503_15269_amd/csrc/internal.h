@@ -15,6 +15,11 @@
 #define BT_FAST_VARIANTS 3
 
 // Host-side handle. Device pointers point into the caller's workspace.
+// Entries of a packed lower triangle of an n x n block, rows one after the
+// other (row i holds entries (i, 0..i)), padded to whole 16-byte chunks of
+// float32 (n = 12: 78 entries, 80 stored).
+constexpr int li_packed_len(int n) { return (n * (n + 1) / 2 + 3) / 4 * 4; }
+
 struct bt_handle {
   int B = 0, n = 0, dtype = 0, maxN = 0;
   int64_t R = 0;
@@ -33,17 +38,20 @@ struct bt_handle {
   int nbins[BT_FAST_VARIANTS] = {};
   void* F = nullptr;        // [R][n][n] scaled off-diagonal blocks
   void* L = nullptr;        // [R][n][n] Cholesky factors of D_k
-  void* Li = nullptr;       // [R][n][n] their inverses
+  void* Li = nullptr;       // [R][n][n] their inverses (packed, see below)
   unsigned short* Fhi = nullptr;  // BT_BF16X2_IR: [2][R][n][n], F then F^T
   unsigned short* Flo = nullptr;  // blockwise, split into bfloat16 hi + lo
   int cfg = -1;             // solve-kernel configuration, -1 = automatic
   // L is current (the register-resident kernel does not read it; for the
   // other kernels it is computed on first use)
   mutable bool full_valid = false;
+  // Li holds the packed lower triangles (li_packed_len(n) entries per block)
+  // instead of full blocks: written by the setup of the register-resident
+  // kernel at n = 12, the only reader besides the setup itself
+  mutable bool li_packed = false;
   std::vector<int64_t> off_host;
 };
 
-// Arguments of the persistent solve kernel (passed by value).
 // Raise the dynamic-LDS limit of kernel ``fn`` to ``bytes`` on the current
 // device, once per device: ``done`` holds one bit per device ordinal, set
 // after the attribute call succeeded (device ordinals past 63 make the call
@@ -61,6 +69,7 @@ inline hipError_t lds_limit(const void* fn, size_t bytes,
   return e;
 }
 
+// Arguments of the persistent solve kernel (passed by value).
 struct SolveArgs {
   int B, n, dtype;
   int mode;          // 0 solve, 1 apply the preconditioner once
@@ -71,6 +80,7 @@ struct SolveArgs {
   double tol, inner_tol;
   int maxit, max_outer;
   int warm;          // mode 0: x holds an initial guess on entry
+  int li_packed;     // Li in packed lower-triangular form
   const int64_t* off;
   const int32_t* order;
   const int32_t* bins;       // register-resident kernel: [nbins][2] (start, count)
@@ -91,6 +101,7 @@ struct SolveArgs {
 // Arguments of the setup kernel. L or F null: not computed.
 struct SetupArgs {
   int B, n, dtype, prec;
+  int li_packed;           // write (and read back) Li packed
   int64_t R;
   const int64_t* off;
   const int32_t* rowinst;  // [R] instance of each block row

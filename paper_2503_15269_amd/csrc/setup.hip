@@ -282,6 +282,16 @@ __global__ void __launch_bounds__(64) k_factor_lane(SetupArgs a) {
     }
     M[tri<NB>(i, i)] = di;
   }
+  if (a.li_packed) {
+    // packed lower triangle, rows one after the other, zero padding
+    constexpr int NP = li_packed_len(NB);
+    T* tp = tout + (size_t)l * (NP + 1);
+#pragma unroll
+    for (int t = 0; t < NP; ++t) tp[t] = (T)(t < NL ? M[t] : 0.0);
+    __syncthreads();
+    stage_out<NP>(tout, (T*)a.Li + (size_t)g0 * NP, nblk);
+    return;
+  }
 #pragma unroll
   for (int i = 0; i < NB; ++i)
 #pragma unroll
@@ -316,7 +326,7 @@ struct OffdiagGeo {
   static constexpr size_t LDS = (size_t)WPB * (2 * RPW + 1) * NN * sizeof(T);
 };
 
-template <int NB, typename T, typename Rec>
+template <int NB, typename T, typename Rec, bool PK>
 __global__ void __launch_bounds__((64 * OffdiagGeo<NB, T>::WPB))
     k_offdiag_rows(SetupArgs a) {
   using G = OffdiagGeo<NB, T>;
@@ -330,15 +340,18 @@ __global__ void __launch_bounds__((64 * OffdiagGeo<NB, T>::WPB))
   const int64_t g = g0 + r;
   const int64_t nO = a.R - a.B;  // upper blocks in all
   const int64_t ob0 = g0 < a.R ? g0 - a.rowinst[g0] : 0;
-  // Li blocks g0 .. g0 + RPW and O blocks ob0 .. ob0 + RPW - 1, all loads of
-  // a lane issued before any LDS store
+  // Li blocks g0 .. g0 + RPW (full, or packed lower triangles of LP entries)
+  // and O blocks ob0 .. ob0 + RPW - 1, all loads of a lane issued before any
+  // LDS store
+  constexpr int LB = PK ? li_packed_len(NB) : NN;  // Li entries per block
   {
     using V = Vec16<T>;
     using W = Vec16<Rec>;
     constexpr int EPC = 16 / sizeof(T), EPR = 16 / sizeof(Rec);
     constexpr int CL = (RPW + 1) * NN / EPC, CO = RPW * NN / EPR;
     constexpr int PL = (CL + 63) / 64, PO = (CO + 63) / 64;
-    const V* srcl = reinterpret_cast<const V*>((const T*)a.Li + (size_t)g0 * NN);
+    constexpr int cl = (RPW + 1) * LB / EPC;  // chunks of the staged Li range
+    const V* srcl = reinterpret_cast<const V*>((const T*)a.Li + (size_t)g0 * LB);
     const W* srco = reinterpret_cast<const W*>((const Rec*)a.O + (size_t)ob0 * NN);
     V bl[PL];
     W bo[PO];
@@ -346,7 +359,7 @@ __global__ void __launch_bounds__((64 * OffdiagGeo<NB, T>::WPB))
     for (int i = 0; i < PL; ++i) {
       const int c = l + 64 * i;
       bl[i] = V{};
-      if (c < CL && g0 + (c * EPC) / NN < a.R) bl[i] = srcl[c];
+      if (c < cl && g0 + (c * EPC) / LB < a.R) bl[i] = srcl[c];
     }
 #pragma unroll
     for (int i = 0; i < PO; ++i) {
@@ -357,7 +370,7 @@ __global__ void __launch_bounds__((64 * OffdiagGeo<NB, T>::WPB))
 #pragma unroll
     for (int i = 0; i < PL; ++i) {
       const int c = l + 64 * i;
-      if (c < CL) reinterpret_cast<V*>(Ls)[c] = bl[i];
+      if (c < cl) reinterpret_cast<V*>(Ls)[c] = bl[i];
     }
 #pragma unroll
     for (int i = 0; i < PO; ++i) {
@@ -375,9 +388,14 @@ __global__ void __launch_bounds__((64 * OffdiagGeo<NB, T>::WPB))
   __syncthreads();
   T f[3][NB];
   if (has_next) {
-    const T* lk = Ls + (size_t)r * NN;        // Li_g
-    const T* ln = Ls + (size_t)(r + 1) * NN;  // Li_{g+1}
+    const T* lk = Ls + (size_t)r * LB;        // Li_g
+    const T* ln = Ls + (size_t)(r + 1) * LB;  // Li_{g+1}
     const T* ok = Os + (size_t)lo * NN;       // O_g
+    // entry (i, j) of a staged Li block (zero above the diagonal)
+    auto li = [&](const T* blk, int i, int j) -> double {
+      if constexpr (PK) return j <= i ? (double)blk[i * (i + 1) / 2 + j] : 0.0;
+      return (double)blk[i * NB + j];
+    };
     double t[3][NB];
 #pragma unroll
     for (int e = 0; e < 3; ++e)
@@ -388,7 +406,7 @@ __global__ void __launch_bounds__((64 * OffdiagGeo<NB, T>::WPB))
     for (int p = 0; p < NB; ++p) {
       double lp[3];
 #pragma unroll
-      for (int e = 0; e < 3; ++e) lp[e] = (double)lk[(3 * q + e) * NB + p];
+      for (int e = 0; e < 3; ++e) lp[e] = li(lk, 3 * q + e, p);
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
         const double o = (double)ok[p * NB + j];
@@ -402,7 +420,7 @@ __global__ void __launch_bounds__((64 * OffdiagGeo<NB, T>::WPB))
       double s3[3] = {0.0, 0.0, 0.0};
 #pragma unroll
       for (int c = 0; c < NB; ++c) {
-        const double lv = (double)ln[j * NB + c];
+        const double lv = li(ln, j, c);
 #pragma unroll
         for (int e = 0; e < 3; ++e) s3[e] = fma(t[e][c], lv, s3[e]);
       }
@@ -438,18 +456,25 @@ __global__ void __launch_bounds__((64 * OffdiagGeo<NB, T>::WPB))
   }
 }
 
-template <int NB, typename T, typename Rec>
-hipError_t launch_offdiag(const SetupArgs& a, hipStream_t s) {
+template <int NB, typename T, typename Rec, bool PK>
+hipError_t launch_offdiag_pk(const SetupArgs& a, hipStream_t s) {
   using G = OffdiagGeo<NB, T>;
   static std::atomic<uint64_t> attr{0};
   hipError_t e =
-      lds_limit((const void*)k_offdiag_rows<NB, T, Rec>, G::LDS, attr);
+      lds_limit((const void*)k_offdiag_rows<NB, T, Rec, PK>, G::LDS, attr);
   if (e != hipSuccess) return e;
   const int64_t rows_per_block = (int64_t)G::WPB * G::RPW;
-  hipLaunchKernelGGL((k_offdiag_rows<NB, T, Rec>),
+  hipLaunchKernelGGL((k_offdiag_rows<NB, T, Rec, PK>),
                      dim3((unsigned)((a.R + rows_per_block - 1) / rows_per_block)),
                      dim3(64 * G::WPB), G::LDS, s, a);
   return hipGetLastError();
+}
+
+template <int NB, typename T, typename Rec>
+hipError_t launch_offdiag(const SetupArgs& a, hipStream_t s) {
+  if (NB == 12 && a.li_packed)  // L^{-1} packed (register-resident solve)
+    return launch_offdiag_pk<NB, T, Rec, true>(a, s);
+  return launch_offdiag_pk<NB, T, Rec, false>(a, s);
 }
 
 template <int NB, typename T, typename Rec>

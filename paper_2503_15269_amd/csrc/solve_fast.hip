@@ -339,6 +339,7 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
   __syncthreads();
   c.seen = 0;
   const size_t nn = (size_t)NB * NB;
+  constexpr size_t LP = li_packed_len(NB);  // packed L_k^{-1} entries
   const double itol2 = a.inner_tol * a.inner_tol;
   const float* F = (const float*)a.F;
   const float* Li = (const float*)a.Li;
@@ -513,7 +514,10 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
           const int i = e0 + e;
           float acc = 0.f;
           if (c.row_ok && !done) {
-            const float* lr = Li + (size_t)g * nn + (size_t)i * NB;
+            // row i of L_k^{-1}: full blocks, or packed lower triangles
+            const float* lr =
+                Li + (a.li_packed ? (size_t)g * LP + (size_t)(i * (i + 1) / 2)
+                                  : (size_t)g * nn + (size_t)i * NB);
 #pragma unroll
             for (int jj = 0; jj < NB; ++jj)
               if (jj <= i) acc = __fmaf_rn(lr[jj], rk[spos(jj)], acc);
@@ -601,12 +605,16 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
           for (int e = 0; e < EPT; ++e) {
             const int i = e0 + e;
             if (c.row_ok) {
-              const float* lc = Li + (size_t)g * nn + i;
+              // column i of L_k^{-1}
+              const float* lc =
+                  Li + (a.li_packed ? (size_t)g * LP : (size_t)g * nn) + i;
               float acc = 0.f;
 #pragma unroll
               for (int jj = 0; jj < NB; ++jj)
                 if (jj >= i)
-                  acc = __fmaf_rn(lc[(size_t)jj * NB], dk[spos(jj)], acc);
+                  acc = __fmaf_rn(
+                      lc[a.li_packed ? jj * (jj + 1) / 2 : jj * NB],
+                      dk[spos(jj)], acc);
               sm.xs[c.lrow * NB + i] += (double)acc;
             }
           }
