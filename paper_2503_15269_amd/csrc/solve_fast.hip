@@ -323,7 +323,7 @@ struct Ctx {
   }
 };
 
-template <int NB, int EPT, int M, typename Rec>
+template <int NB, int EPT, int M, typename Rec, bool PK>
 __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
   using G = Geo<NB, EPT>;
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -516,8 +516,8 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
           if (c.row_ok && !done) {
             // row i of L_k^{-1}: full blocks, or packed lower triangles
             const float* lr =
-                Li + (a.li_packed ? (size_t)g * LP + (size_t)(i * (i + 1) / 2)
-                                  : (size_t)g * nn + (size_t)i * NB);
+                Li + (PK ? (size_t)g * LP + (size_t)(i * (i + 1) / 2)
+                         : (size_t)g * nn + (size_t)i * NB);
 #pragma unroll
             for (int jj = 0; jj < NB; ++jj)
               if (jj <= i) acc = __fmaf_rn(lr[jj], rk[spos(jj)], acc);
@@ -606,14 +606,13 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
             const int i = e0 + e;
             if (c.row_ok) {
               // column i of L_k^{-1}
-              const float* lc =
-                  Li + (a.li_packed ? (size_t)g * LP : (size_t)g * nn) + i;
+              const float* lc = Li + (PK ? (size_t)g * LP : (size_t)g * nn) + i;
               float acc = 0.f;
 #pragma unroll
               for (int jj = 0; jj < NB; ++jj)
                 if (jj >= i)
                   acc = __fmaf_rn(
-                      lc[a.li_packed ? jj * (jj + 1) / 2 : jj * NB],
+                      lc[PK ? jj * (jj + 1) / 2 : jj * NB],
                       dk[spos(jj)], acc);
               sm.xs[c.lrow * NB + i] += (double)acc;
             }
@@ -655,26 +654,35 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
   }
 }
 
-template <int NB, int EPT, int M, typename Rec>
+template <int NB, int EPT, int M, typename Rec, bool PK>
 hipError_t launch_one(const SolveArgs& a, int grid, hipStream_t s) {
   using G = Geo<NB, EPT>;
   static std::atomic<uint64_t> attr{0};
-  const hipError_t e = lds_limit((const void*)k_fast_ir<NB, EPT, M, Rec>,
+  const hipError_t e = lds_limit((const void*)k_fast_ir<NB, EPT, M, Rec, PK>,
                                  sizeof(Smem<NB, EPT>), attr);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_fast_ir<NB, EPT, M, Rec>), dim3(grid), dim3(G::NT),
-                     sizeof(Smem<NB, EPT>), s, a);
+  hipLaunchKernelGGL((k_fast_ir<NB, EPT, M, Rec, PK>), dim3(grid),
+                     dim3(G::NT), sizeof(Smem<NB, EPT>), s, a);
   return hipGetLastError();
 }
 
+template <int NB, int EPT, typename Rec, bool PK>
+hipError_t launch_m(const SolveArgs& a, int grid, hipStream_t s) {
+  switch (a.m) {
+    case 1: return launch_one<NB, EPT, 1, Rec, PK>(a, grid, s);
+    case 2: return launch_one<NB, EPT, 2, Rec, PK>(a, grid, s);
+    case 3: return launch_one<NB, EPT, 3, Rec, PK>(a, grid, s);
+    default: return launch_one<NB, EPT, 4, Rec, PK>(a, grid, s);
+  }
+}
+
+// L^{-1} as full blocks or (block size 12 only) packed lower triangles
 template <int NB, int EPT, typename Rec>
 hipError_t launch_rec(const SolveArgs& a, int grid, hipStream_t s) {
-  switch (a.m) {
-    case 1: return launch_one<NB, EPT, 1, Rec>(a, grid, s);
-    case 2: return launch_one<NB, EPT, 2, Rec>(a, grid, s);
-    case 3: return launch_one<NB, EPT, 3, Rec>(a, grid, s);
-    default: return launch_one<NB, EPT, 4, Rec>(a, grid, s);
+  if constexpr (NB == 12) {
+    if (a.li_packed) return launch_m<NB, EPT, Rec, true>(a, grid, s);
   }
+  return launch_m<NB, EPT, Rec, false>(a, grid, s);
 }
 
 template <int NB, int EPT>
@@ -692,7 +700,7 @@ int max_grid() {
                             dev) != hipSuccess)
     cus = 256;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per, (const void*)k_fast_ir<NB, EPT, 2, float>, G::NT,
+          &per, (const void*)k_fast_ir<NB, EPT, 2, float, false>, G::NT,
           sizeof(Smem<NB, EPT>)) != hipSuccess ||
       per < 1)
     per = 1;
