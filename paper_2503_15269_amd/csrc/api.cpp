@@ -152,8 +152,8 @@ int launch_setup(const bt_handle* h, hipStream_t s, bool full) {
   a.L = full ? h->L : nullptr;
   a.Li = h->Li;
   // only the register-resident kernel reads Li between a setup without L
-  // and the next full one; at n = 12 it takes the packed triangles
-  a.li_packed = !full && h->n == 12 && h->p.prec == BT_F32_IR;
+  // and the next full one; it takes the packed triangles
+  a.li_packed = !full && (h->n == 12 || h->n == 24) && h->p.prec == BT_F32_IR;
   if (a.prec == BT_BF16X2_IR) a.prec = BT_F32_IR;  // float32 factors first
   h->full_valid = false;
   h->li_packed = false;

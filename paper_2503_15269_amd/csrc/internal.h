@@ -47,7 +47,7 @@ struct bt_handle {
   mutable bool full_valid = false;
   // Li holds the packed lower triangles (li_packed_len(n) entries per block)
   // instead of full blocks: written by the setup of the register-resident
-  // kernel at n = 12, the only reader besides the setup itself
+  // kernel (n = 12, 24), its only reader besides the setup itself
   mutable bool li_packed = false;
   std::vector<int64_t> off_host;
 };

@@ -472,7 +472,7 @@ hipError_t launch_offdiag_pk(const SetupArgs& a, hipStream_t s) {
 
 template <int NB, typename T, typename Rec>
 hipError_t launch_offdiag(const SetupArgs& a, hipStream_t s) {
-  if (NB == 12 && a.li_packed)  // L^{-1} packed (register-resident solve)
+  if ((NB == 12 || NB == 24) && a.li_packed)  // packed (register-resident)
     return launch_offdiag_pk<NB, T, Rec, true>(a, s);
   return launch_offdiag_pk<NB, T, Rec, false>(a, s);
 }
@@ -588,9 +588,16 @@ __global__ void __launch_bounds__(64) k_factor_wave(SetupArgs a) {
     for (int c = 0; c <= k; ++c) x[c] = fma(-f, rk[c], x[c]);
   }
   if (r < NB && real) {
-    T* Li = (T*)a.Li + (size_t)g * NN + (size_t)r * NB;
+    if (a.li_packed) {  // row r of the packed lower triangle
+      T* Li = (T*)a.Li + (size_t)g * li_packed_len(NB) + (size_t)(r * (r + 1) / 2);
 #pragma unroll
-    for (int c = 0; c < NB; ++c) Li[c] = (T)x[c];
+      for (int c = 0; c < NB; ++c)
+        if (c <= r) Li[c] = (T)x[c];
+    } else {
+      T* Li = (T*)a.Li + (size_t)g * NN + (size_t)r * NB;
+#pragma unroll
+      for (int c = 0; c < NB; ++c) Li[c] = (T)x[c];
+    }
   }
 }
 

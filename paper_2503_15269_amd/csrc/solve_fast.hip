@@ -676,10 +676,10 @@ hipError_t launch_m(const SolveArgs& a, int grid, hipStream_t s) {
   }
 }
 
-// L^{-1} as full blocks or (block size 12 only) packed lower triangles
+// L^{-1} as full blocks or packed lower triangles
 template <int NB, int EPT, typename Rec>
 hipError_t launch_rec(const SolveArgs& a, int grid, hipStream_t s) {
-  if constexpr (NB == 12) {
+  if constexpr (NB == 12 || NB == 24) {
     if (a.li_packed) return launch_m<NB, EPT, Rec, true>(a, grid, s);
   }
   return launch_m<NB, EPT, Rec, false>(a, grid, s);
