@@ -418,11 +418,32 @@ __global__ void __launch_bounds__((64 * OffdiagGeo<NB, T>::WPB))
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       double s3[3] = {0.0, 0.0, 0.0};
+      if constexpr (PK) {
+        // row j of the packed Li_{g+1} (entries j(j+1)/2 .. j(j+1)/2 + j,
+        // the columns c <= j), read as the aligned 16-byte chunks covering it
+        using V = Vec16<T>;
+        constexpr int EPC = 16 / sizeof(T);
+        constexpr int KMAX = (NB + 2 * EPC - 2) / EPC;
+        const int t0 = j * (j + 1) / 2, k0 = t0 / EPC, nk = (t0 + j) / EPC - k0;
+        V ch[KMAX];
 #pragma unroll
-      for (int c = 0; c < NB; ++c) {
-        const double lv = li(ln, j, c);
+        for (int k = 0; k < KMAX; ++k)
+          if (k <= nk) ch[k] = reinterpret_cast<const V*>(ln)[k0 + k];
 #pragma unroll
-        for (int e = 0; e < 3; ++e) s3[e] = fma(t[e][c], lv, s3[e]);
+        for (int c = 0; c < NB; ++c) {
+          if (c > j) break;
+          const int u = t0 + c - k0 * EPC;
+          const double lv = (double)ch[u / EPC][u % EPC];
+#pragma unroll
+          for (int e = 0; e < 3; ++e) s3[e] = fma(t[e][c], lv, s3[e]);
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+          const double lv = li(ln, j, c);
+#pragma unroll
+          for (int e = 0; e < 3; ++e) s3[e] = fma(t[e][c], lv, s3[e]);
+        }
       }
 #pragma unroll
       for (int e = 0; e < 3; ++e) f[e][j] = (T)s3[e];
