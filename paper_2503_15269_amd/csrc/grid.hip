@@ -671,11 +671,16 @@ int run(const bt_handle* h, const double* b, double* x, double tol, int maxit,
     for (int i = 0; i < a.nwg; ++i) t += hp[(size_t)slot * a.nwg + i];
     return t;
   };
-  // inner loop: steps until the control block is settled or ``cap`` steps
+  // inner loop: steps until the control block is settled or ``cap`` steps.
+  // The first check comes after as many steps as the last inner solve on
+  // this handle took (steps launched after the settling return at once),
+  // later ones every CHUNK steps.
   auto iterate = [&](int cap, int* steps) -> bool {
     int i = 0;
+    int chunk = std::max(CHUNK, h->grid_hint);
     for (;;) {
-      const int stop = std::min(cap, i + CHUNK);
+      const int stop = std::min(cap, i + chunk);
+      chunk = CHUNK;
       for (; i < stop; ++i) {
         if (launch(k_g_q<T>, pl, s, i) != hipSuccess ||
             launch(k_g_u<T>, pl, s, i) != hipSuccess)
@@ -685,6 +690,7 @@ int run(const bt_handle* h, const double* b, double* x, double tol, int maxit,
       if (ctl.status != BT_NOT_CONVERGED || i >= cap) break;
     }
     *steps = ctl.it;
+    h->grid_hint = ctl.it;
     return true;
   };
 

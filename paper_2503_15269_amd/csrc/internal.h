@@ -49,6 +49,9 @@ struct bt_handle {
   // instead of full blocks: written by the setup of the register-resident
   // kernel (n = 12, 24), its only reader besides the setup itself
   mutable bool li_packed = false;
+  // grid-wide solve: PCG steps of the last inner solve on this handle, the
+  // number of steps launched before the first check of the next one
+  mutable int grid_hint = 0;
   std::vector<int64_t> off_host;
 };
 
