@@ -8,8 +8,9 @@ counts if every system converges. The fastest choice is cached per device
 and problem signature in a JSON file (``$BTPCG_TUNE_CACHE``, default
 ``~/.cache/btpcg/autotune.json``).
 
-The preconditioner itself (weights, order, coefficients) is never changed:
-it is the method the caller asked for.
+``tune`` never changes the preconditioner itself (weights, order,
+coefficients): it is the method the caller asked for. ``tune_order`` is the
+opt-in that also picks the polynomial order m for the caller's systems.
 """
 from __future__ import annotations
 
@@ -118,3 +119,36 @@ def tune(D, O, offsets, b, params: Params, tol: float = 1e-10,
         os.replace(tmp, path)
     return dict(params=replace(params, inner_tol=best[0]),
                 kernel_config=best[1], ms=best[2], table=table, cached=False)
+
+
+def tune_order(D, O, offsets, b, params: Params, tol: float = 1e-10,
+               orders: Sequence[int] = (1, 2, 3, 4),
+               alpha_last: Optional[float] = None, **kw):
+    """Also choose the polynomial order m for these systems (an explicit
+    opt-in: unlike ``tune`` it changes the preconditioner). Each order runs
+    with the caller's weights (a, b) and the "PolyCoeff" coefficients of
+    Section V (alpha_{m-1} = ``alpha_last``, default 7, the others 1), and
+    goes through ``tune`` (kernel configuration and inner tolerance); the
+    fastest order whose every system converges wins.
+
+    Returns ``tune``'s dict for the winner plus ``orders``: {m: ms or None}.
+    """
+    results, best = {}, None
+    for m in orders:
+        alpha = [1.0] * m
+        if m > 1:
+            alpha[m - 1] = 7.0 if alpha_last is None else float(alpha_last)
+        p = replace(params, m=int(m), alpha=alpha)
+        try:
+            r = tune(D, O, offsets, b, p, tol, **kw)
+        except RuntimeError:          # no configuration converged
+            results[int(m)] = None
+            continue
+        results[int(m)] = r["ms"]
+        if best is None or r["ms"] < best["ms"]:
+            best = r
+    if best is None:
+        raise RuntimeError("autotune: no polynomial order converged")
+    best = dict(best)
+    best["orders"] = results
+    return best

@@ -229,6 +229,30 @@ def test_autotune_picks_a_converging_config(tmp_path, monkeypatch):
     assert np.all(inf["status"] == bt.OK) and np.all(inf["relres_true"] <= 1e-10)
 
 
+def test_autotune_order_picks_the_fastest_converging_m(tmp_path, monkeypatch):
+    import torch
+    from paper_2503_15269_amd import autotune
+    monkeypatch.setenv("BTPCG_TUNE_CACHE", str(tmp_path / "tune.json"))
+    data = lqrgen.lqr_batch(32, (16, 200), 12, 4, seed=45, record="f32")
+    D = to_dev(data["D"], torch.float32)
+    O = to_dev(data["O"], torch.float32)
+    b = to_dev(data["b"].reshape(-1), torch.float64)
+    P = bt.Params.polycoeff(2, prec="f32_ir")
+    res = autotune.tune_order(D, O, data["offsets"], b, P, 1e-10,
+                              orders=(1, 2, 3), reps=1, inner_tols=(3e-6,))
+    times = {m: t for m, t in res["orders"].items() if t is not None}
+    assert set(times) == {1, 2, 3}
+    m = res["params"].m
+    assert res["ms"] == min(times.values()) == times[m]
+    assert res["params"].alpha[m - 1] == (7.0 if m > 1 else 1.0)
+    h = bt.Handle(D, O, data["offsets"], res["params"])
+    h.set_kernel_config(res["kernel_config"])
+    x, info = h.solve(b, 1e-10)
+    torch.cuda.synchronize()
+    inf = bt.infos_to_numpy(info)
+    assert np.all(inf["status"] == bt.OK) and np.all(inf["relres_true"] <= 1e-10)
+
+
 def test_factors_for_other_kernels_formed_on_first_use():
     """A handle set up for the register-resident kernel forms the Cholesky
     factors L (which only the other kernels read) when a solve, a
