@@ -191,3 +191,33 @@ def test_grid_argument_checks():
                   d["offsets"], bt.Params.polycoeff(2))
     with pytest.raises(bt.BtError):  # more than one system
         h.solve_grid(to_dev(d["b"].reshape(-1), torch.float64))
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32_ir"])
+def test_grid_repeated_solves_and_cap_below_the_hint(prec):
+    """A handle launches as many steps as its last solve took before the
+    first check: repeated solves give the same result bit for bit, and an
+    iteration cap below that count still stops the iteration exactly."""
+    import torch
+    d = lqrgen.lqr_instance(300, 12, 4, 17, 3)
+    P = bt.Params.polycoeff(2, prec=prec)
+    h = bt.Handle(to_dev(d["D"], torch.float64), to_dev(d["O"], torch.float64),
+                  None, P)
+    b = to_dev(d["b"].reshape(-1), torch.float64)
+    out = []
+    for _ in range(3):
+        x, info = h.solve_grid(b)
+        torch.cuda.synchronize()
+        out.append((x.cpu().numpy(), bt.infos_to_numpy(info)[0]))
+    assert out[0][1]["status"] == bt.OK
+    for x, inf in out[1:]:
+        assert np.array_equal(x, out[0][0])
+        assert inf["iters"] == out[0][1]["iters"]
+    x, info = h.solve_grid(b, maxit=3)
+    torch.cuda.synchronize()
+    inf = bt.infos_to_numpy(info)[0]
+    assert inf["status"] == bt.NOT_CONVERGED and inf["iters"] == 3
+    if prec == "f64":
+        xr, ri = orc.pcg(d["D"], d["O"], d["b"], tol=1e-30, maxit=3,
+                         **oracle_kind(P))
+        assert rel(x.cpu().numpy().reshape(xr.shape), xr) <= 1e-10
