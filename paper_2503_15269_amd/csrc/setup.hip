@@ -189,6 +189,44 @@ __device__ __forceinline__ void stage_in(const S* src, D* lds, int nblk) {
   }
 }
 
+// As stage_in, keeping only the lower triangles: entry (r, q <= r) of block
+// blk goes to lds[blk (NL + 1) + r (r + 1) / 2 + q], NL = NB (NB + 1) / 2.
+// A 16-byte chunk never spans two rows (NB is a multiple of its entries).
+template <int NB, typename S, typename D>
+__device__ __forceinline__ void stage_in_lower(const S* src, D* lds,
+                                               int nblk) {
+  constexpr int NN = NB * NB, NL = NB * (NB + 1) / 2;
+  constexpr int EPC = 16 / sizeof(S);
+  constexpr int PER = NN / EPC;
+  constexpr int BAT = 16;
+  static_assert(NB % EPC == 0, "chunks stay inside a row");
+  using V = Vec16<S>;
+  const int l = threadIdx.x & 63;
+#pragma unroll
+  for (int i0 = 0; i0 < PER; i0 += BAT) {
+    V buf[BAT];
+#pragma unroll
+    for (int i = 0; i < BAT; ++i) {
+      const int c = l + 64 * (i0 + i);
+      buf[i] = V{};
+      if (i0 + i < PER && c * EPC < nblk * NN)
+        buf[i] = reinterpret_cast<const V*>(src)[c];
+    }
+#pragma unroll
+    for (int i = 0; i < BAT; ++i) {
+      const int c = l + 64 * (i0 + i);
+      if (i0 + i < PER && c * EPC < nblk * NN) {
+        const int e0 = c * EPC, blk = e0 / NN, off = e0 - blk * NN;
+        const int r = off / NB, q0 = off - r * NB;
+        D* row = lds + blk * (NL + 1) + r * (r + 1) / 2;
+#pragma unroll
+        for (int k = 0; k < EPC; ++k)
+          if (q0 + k <= r) row[q0 + k] = (D)buf[i][k];
+      }
+    }
+  }
+}
+
 template <int NN, typename T>
 __device__ __forceinline__ void stage_out(const T* lds, T* dst, int nblk) {
   constexpr int EPC = 16 / sizeof(T);
@@ -221,15 +259,28 @@ __global__ void __launch_bounds__(64) k_factor_lane(SetupArgs a) {
   const int nblk = (int)(a.R - g0 < 64 ? a.R - g0 : 64);
   Rec* din = reinterpret_cast<Rec*>(smem_raw);
   T* tout = reinterpret_cast<T*>(smem_raw);
-  stage_in<NN>((const Rec*)a.D + (size_t)g0 * NN, din, nblk);
-  __syncthreads();
   double M[NL];
   const bool live = g < a.R;
-  const Rec* dl = din + (size_t)(live ? l : 0) * (NN + 1);
+  bool staged = false;
+  if constexpr (NB % (16 / (int)sizeof(Rec)) == 0) {
+    if (a.li_packed) {  // only the lower triangles pass through LDS
+      stage_in_lower<NB>((const Rec*)a.D + (size_t)g0 * NN, din, nblk);
+      __syncthreads();
+      const Rec* dl = din + (size_t)(live ? l : 0) * (NL + 1);
 #pragma unroll
-  for (int i = 0; i < NB; ++i)
+      for (int t = 0; t < NL; ++t) M[t] = (double)dl[t];
+      staged = true;
+    }
+  }
+  if (!staged) {
+    stage_in<NN>((const Rec*)a.D + (size_t)g0 * NN, din, nblk);
+    __syncthreads();
+    const Rec* dl = din + (size_t)(live ? l : 0) * (NN + 1);
 #pragma unroll
-    for (int j = 0; j <= i; ++j) M[tri<NB>(i, j)] = (double)dl[i * NB + j];
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int j = 0; j <= i; ++j) M[tri<NB>(i, j)] = (double)dl[i * NB + j];
+  }
   bool ok = true;
 #pragma unroll
   for (int j = 0; j < NB; ++j) {
@@ -305,6 +356,13 @@ template <int NB, typename T, typename Rec>
 constexpr size_t factor_lds() {
   return (size_t)64 * (NB * NB + 1) *
          (sizeof(T) > sizeof(Rec) ? sizeof(T) : sizeof(Rec));
+}
+// packed mode: lower triangles of D in, packed L^{-1} out
+template <int NB, typename T, typename Rec>
+constexpr size_t factor_lds_packed() {
+  constexpr size_t din = (size_t)64 * (NB * (NB + 1) / 2 + 1) * sizeof(Rec);
+  constexpr size_t dout = (size_t)64 * (li_packed_len(NB) + 1) * sizeof(T);
+  return din > dout ? din : dout;
 }
 
 // F_g = Li_g O_g Li_{g+1}^T for the rows g with a successor in their system,
@@ -500,9 +558,11 @@ hipError_t launch_offdiag(const SetupArgs& a, hipStream_t s) {
 
 template <int NB, typename T, typename Rec>
 hipError_t launch_lane(const SetupArgs& a, hipStream_t s) {
-  constexpr size_t lds = factor_lds<NB, T, Rec>();
+  const size_t lds = a.li_packed ? factor_lds_packed<NB, T, Rec>()
+                                 : factor_lds<NB, T, Rec>();
   static std::atomic<uint64_t> attr{0};
-  hipError_t e = lds_limit((const void*)k_factor_lane<NB, T, Rec>, lds, attr);
+  hipError_t e = lds_limit((const void*)k_factor_lane<NB, T, Rec>,
+                           factor_lds<NB, T, Rec>(), attr);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_factor_lane<NB, T, Rec>), dim3((a.R + 63) / 64),
                      dim3(64), lds, s, a);
