@@ -340,7 +340,7 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
   c.seen = 0;
   const size_t nn = (size_t)NB * NB;
   constexpr size_t LP = li_packed_len(NB);  // packed L_k^{-1} entries
-  const double itol2 = a.inner_tol * a.inner_tol;
+  const double itol2 = uni(a.inner_tol * a.inner_tol);  // scalar registers
   const float* F = (const float*)a.F;
   const float* Li = (const float*)a.Li;
 
