@@ -62,11 +62,17 @@ int64_t check_offsets(int B, const int64_t* off, int* maxN) {
 }
 
 struct Layout {
-  size_t off, order, rowinst, ctr, fail, bins, items, F, L, Li, Fhi, Flo,
+  size_t off, order, rowinst, ctr, fail, bins, items, F, L, Li, Lp, Fhi, Flo,
       total;
 };
 
-Layout layout(int B, int64_t R, int n, size_t es, bool split) {
+// The register-resident kernel can serve the handle (block size and
+// precision; whether its systems fit its bins is decided at setup).
+bool fast_capable(int n, const bt_params* p) {
+  return (n == 12 || n == 24) && p->prec == BT_F32_IR;
+}
+
+Layout layout(int B, int64_t R, int n, size_t es, bool split, bool packed) {
   Layout l{};
   size_t at = 0;
   l.off = at; at += align_up(sizeof(int64_t) * (B + 1));
@@ -80,6 +86,7 @@ Layout layout(int B, int64_t R, int n, size_t es, bool split) {
   l.F = at; at += blk;
   l.L = at; at += blk;
   l.Li = at; at += blk;
+  l.Lp = at; at += packed ? align_up(es * (size_t)R * li_packed_len(n)) : 0;
   // bfloat16 splits of F and of the transposed blocks
   const size_t hblk = split ? align_up(2 * 2 * (size_t)R * n * n) : 0;
   l.Fhi = at; at += hblk;
@@ -149,17 +156,16 @@ int launch_setup(const bt_handle* h, hipStream_t s, bool full) {
   a.O = h->O;
   a.fail = h->fail;
   a.F = h->F;
+  // the packed L^{-1} of the register-resident kernel on every setup; the
+  // full L and L^{-1} of the other kernels on full setups (without a packed
+  // copy to read back, the off-diagonal step needs the full one)
+  a.Lp = h->Lp;
   a.L = full ? h->L : nullptr;
-  a.Li = h->Li;
-  // only the register-resident kernel reads Li between a setup without L
-  // and the next full one; it takes the packed triangles
-  a.li_packed = !full && (h->n == 12 || h->n == 24) && h->p.prec == BT_F32_IR;
+  a.Li = full || !h->Lp ? h->Li : nullptr;
   if (a.prec == BT_BF16X2_IR) a.prec = BT_F32_IR;  // float32 factors first
   h->full_valid = false;
-  h->li_packed = false;
   if (bt_launch_setup(a, s) != hipSuccess) return BT_EHIP;
   h->full_valid = full;
-  h->li_packed = a.li_packed != 0;
   if (h->Fhi)
     return hip_status(
         bt_mrhs_split((const float*)h->F, h->Fhi, h->Flo, h->R, h->n, s));
@@ -199,7 +205,7 @@ int run(const bt_handle* h, SolveArgs& a, hipStream_t s) {
     const int rc = launch_setup(h, s, true);
     if (rc != BT_OK) return rc;
   }
-  a.li_packed = h->li_packed;
+  a.Lp = h->Lp;
   if (is_fast(cfg)) {
     const int v = cfg - fast_index();
     a.bins = h->bins[v];
@@ -251,7 +257,9 @@ size_t bt_workspace_bytes(int B, const int64_t* offsets_host, int n,
   if (!params_ok(p) || n < 1 || n > 64) return 0;
   const int64_t R = check_offsets(B, offsets_host, &maxN);
   if (R < 0) return 0;
-  return layout(B, R, n, elem_bytes(p), p->prec == BT_BF16X2_IR).total;
+  return layout(B, R, n, elem_bytes(p), p->prec == BT_BF16X2_IR,
+                fast_capable(n, p))
+      .total;
 }
 
 int bt_batch_setup(bt_handle** h, int B, const int64_t* offsets_host, int n,
@@ -271,7 +279,8 @@ int bt_batch_setup(bt_handle** h, int B, const int64_t* offsets_host, int n,
   if (B > 1 && p->prec != BT_BF16X2_IR &&
       auto_config(kernel_prec(p), (int64_t)maxN * n) < 0)
     return BT_EINVAL;
-  const Layout l = layout(B, R, n, elem_bytes(p), p->prec == BT_BF16X2_IR);
+  const Layout l = layout(B, R, n, elem_bytes(p), p->prec == BT_BF16X2_IR,
+                          fast_capable(n, p));
   if (ws_bytes < l.total) return BT_ENOSPACE;
 
   bt_handle* hh = new (std::nothrow) bt_handle();
@@ -297,6 +306,7 @@ int bt_batch_setup(bt_handle** h, int B, const int64_t* offsets_host, int n,
   hh->F = w + l.F;
   hh->L = w + l.L;
   hh->Li = w + l.Li;
+  hh->Lp = fast_capable(n, p) ? w + l.Lp : nullptr;
   if (p->prec == BT_BF16X2_IR) {
     hh->Fhi = (unsigned short*)(w + l.Fhi);
     hh->Flo = (unsigned short*)(w + l.Flo);

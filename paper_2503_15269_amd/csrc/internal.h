@@ -38,17 +38,16 @@ struct bt_handle {
   int nbins[BT_FAST_VARIANTS] = {};
   void* F = nullptr;        // [R][n][n] scaled off-diagonal blocks
   void* L = nullptr;        // [R][n][n] Cholesky factors of D_k
-  void* Li = nullptr;       // [R][n][n] their inverses (packed, see below)
+  void* Li = nullptr;       // [R][n][n] their inverses
+  // [R][li_packed_len(n)] the inverses as packed lower triangles, for the
+  // register-resident kernel (handles it can serve; else null)
+  void* Lp = nullptr;
   unsigned short* Fhi = nullptr;  // BT_BF16X2_IR: [2][R][n][n], F then F^T
   unsigned short* Flo = nullptr;  // blockwise, split into bfloat16 hi + lo
   int cfg = -1;             // solve-kernel configuration, -1 = automatic
   // L is current (the register-resident kernel does not read it; for the
   // other kernels it is computed on first use)
   mutable bool full_valid = false;
-  // Li holds the packed lower triangles (li_packed_len(n) entries per block)
-  // instead of full blocks: written by the setup of the register-resident
-  // kernel (n = 12, 24), its only reader besides the setup itself
-  mutable bool li_packed = false;
   // grid-wide solve: PCG steps of the last inner solve on this handle, the
   // number of steps launched before the first check of the next one
   mutable int grid_hint = 0;
@@ -83,7 +82,7 @@ struct SolveArgs {
   double tol, inner_tol;
   int maxit, max_outer;
   int warm;          // mode 0: x holds an initial guess on entry
-  int li_packed;     // Li in packed lower-triangular form
+  const void* Lp;    // packed L^{-1} (null: the kernel reads Li)
   const int64_t* off;
   const int32_t* order;
   const int32_t* bins;       // register-resident kernel: [nbins][2] (start, count)
@@ -104,7 +103,8 @@ struct SolveArgs {
 // Arguments of the setup kernel. L or F null: not computed.
 struct SetupArgs {
   int B, n, dtype, prec;
-  int li_packed;           // write (and read back) Li packed
+  void* Lp;                // packed L^{-1} out (null: not written); with Li
+                           // null the off-diagonal step reads it back
   int64_t R;
   const int64_t* off;
   const int32_t* rowinst;  // [R] instance of each block row

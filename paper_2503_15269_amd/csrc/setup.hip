@@ -263,7 +263,7 @@ __global__ void __launch_bounds__(64) k_factor_lane(SetupArgs a) {
   const bool live = g < a.R;
   bool staged = false;
   if constexpr (NB % (16 / (int)sizeof(Rec)) == 0) {
-    if (a.li_packed) {  // only the lower triangles pass through LDS
+    if (!a.L && !a.Li) {  // only the lower triangles pass through LDS
       stage_in_lower<NB>((const Rec*)a.D + (size_t)g0 * NN, din, nblk);
       __syncthreads();
       const Rec* dl = din + (size_t)(live ? l : 0) * (NL + 1);
@@ -333,15 +333,16 @@ __global__ void __launch_bounds__(64) k_factor_lane(SetupArgs a) {
     }
     M[tri<NB>(i, i)] = di;
   }
-  if (a.li_packed) {
+  if (a.Lp) {
     // packed lower triangle, rows one after the other, zero padding
     constexpr int NP = li_packed_len(NB);
     T* tp = tout + (size_t)l * (NP + 1);
 #pragma unroll
     for (int t = 0; t < NP; ++t) tp[t] = (T)(t < NL ? M[t] : 0.0);
     __syncthreads();
-    stage_out<NP>(tout, (T*)a.Li + (size_t)g0 * NP, nblk);
-    return;
+    stage_out<NP>(tout, (T*)a.Lp + (size_t)g0 * NP, nblk);
+    if (!a.Li) return;
+    __syncthreads();  // the staging area is reused for the full blocks
   }
 #pragma unroll
   for (int i = 0; i < NB; ++i)
@@ -409,7 +410,8 @@ __global__ void __launch_bounds__((64 * OffdiagGeo<NB, T>::WPB))
     constexpr int CL = (RPW + 1) * NN / EPC, CO = RPW * NN / EPR;
     constexpr int PL = (CL + 63) / 64, PO = (CO + 63) / 64;
     constexpr int cl = (RPW + 1) * LB / EPC;  // chunks of the staged Li range
-    const V* srcl = reinterpret_cast<const V*>((const T*)a.Li + (size_t)g0 * LB);
+    const T* lsrc = (const T*)(PK ? a.Lp : a.Li);
+    const V* srcl = reinterpret_cast<const V*>(lsrc + (size_t)g0 * LB);
     const W* srco = reinterpret_cast<const W*>((const Rec*)a.O + (size_t)ob0 * NN);
     V bl[PL];
     W bo[PO];
@@ -551,15 +553,15 @@ hipError_t launch_offdiag_pk(const SetupArgs& a, hipStream_t s) {
 
 template <int NB, typename T, typename Rec>
 hipError_t launch_offdiag(const SetupArgs& a, hipStream_t s) {
-  if ((NB == 12 || NB == 24) && a.li_packed)  // packed (register-resident)
+  if ((NB == 12 || NB == 24) && !a.Li)  // only the packed L^{-1} is written
     return launch_offdiag_pk<NB, T, Rec, true>(a, s);
   return launch_offdiag_pk<NB, T, Rec, false>(a, s);
 }
 
 template <int NB, typename T, typename Rec>
 hipError_t launch_lane(const SetupArgs& a, hipStream_t s) {
-  const size_t lds = a.li_packed ? factor_lds_packed<NB, T, Rec>()
-                                 : factor_lds<NB, T, Rec>();
+  const size_t lds = a.L || a.Li ? factor_lds<NB, T, Rec>()
+                                 : factor_lds_packed<NB, T, Rec>();
   static std::atomic<uint64_t> attr{0};
   hipError_t e = lds_limit((const void*)k_factor_lane<NB, T, Rec>,
                            factor_lds<NB, T, Rec>(), attr);
@@ -669,12 +671,13 @@ __global__ void __launch_bounds__(64) k_factor_wave(SetupArgs a) {
     for (int c = 0; c <= k; ++c) x[c] = fma(-f, rk[c], x[c]);
   }
   if (r < NB && real) {
-    if (a.li_packed) {  // row r of the packed lower triangle
-      T* Li = (T*)a.Li + (size_t)g * li_packed_len(NB) + (size_t)(r * (r + 1) / 2);
+    if (a.Lp) {  // row r of the packed lower triangle
+      T* Lp = (T*)a.Lp + (size_t)g * li_packed_len(NB) + (size_t)(r * (r + 1) / 2);
 #pragma unroll
       for (int c = 0; c < NB; ++c)
-        if (c <= r) Li[c] = (T)x[c];
-    } else {
+        if (c <= r) Lp[c] = (T)x[c];
+    }
+    if (a.Li) {
       T* Li = (T*)a.Li + (size_t)g * NN + (size_t)r * NB;
 #pragma unroll
       for (int c = 0; c < NB; ++c) Li[c] = (T)x[c];

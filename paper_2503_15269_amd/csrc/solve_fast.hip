@@ -342,7 +342,8 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
   constexpr size_t LP = li_packed_len(NB);  // packed L_k^{-1} entries
   const double itol2 = uni(a.inner_tol * a.inner_tol);  // scalar registers
   const float* F = (const float*)a.F;
-  const float* Li = (const float*)a.Li;
+  // L^{-1}: packed lower triangles (PK) or full blocks
+  const float* Li = (const float*)(PK ? a.Lp : a.Li);
 
   for (;;) {
     if (t == 0) sm.bin = atomicAdd(&a.ctr[2], 1);
@@ -680,7 +681,7 @@ hipError_t launch_m(const SolveArgs& a, int grid, hipStream_t s) {
 template <int NB, int EPT, typename Rec>
 hipError_t launch_rec(const SolveArgs& a, int grid, hipStream_t s) {
   if constexpr (NB == 12 || NB == 24) {
-    if (a.li_packed) return launch_m<NB, EPT, Rec, true>(a, grid, s);
+    if (a.Lp) return launch_m<NB, EPT, Rec, true>(a, grid, s);
   }
   return launch_m<NB, EPT, Rec, false>(a, grid, s);
 }

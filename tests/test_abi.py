@@ -104,8 +104,12 @@ def test_workspace_bytes_validation(lib):
                                   ctypes.byref(bad)) == 0
     # f32 factors take half the bytes of f64 ones
     w64 = _ws(lib, 1, [0, 1000], 12, bt.Params(prec="f64"))
-    w32 = _ws(lib, 1, [0, 1000], 12, bt.Params(prec="f32_ir"))
+    w32 = _ws(lib, 1, [0, 1000], 12, bt.Params(prec="f32"))
     assert 1.9 < w64 / w32 < 2.1
+    # float32 + refinement at n = 12 adds the packed L^{-1} of the
+    # register-resident kernel: 80 floats per block row
+    wir = _ws(lib, 1, [0, 1000], 12, bt.Params(prec="f32_ir"))
+    assert 0 <= wir - w32 - 1000 * 80 * 4 < 512
 
 
 def test_setup_rejects_before_touching_memory(lib):

@@ -342,3 +342,48 @@ def test_graph_replays_match_eager(which):
     assert torch.equal(x, 2.0 * x_ref)
     i2, i1 = bt.infos_to_numpy(info), bt.infos_to_numpy(info_ref)
     assert np.array_equal(i2["iters"], i1["iters"])
+
+
+@pytest.mark.parametrize("n", [12, 24])
+def test_graph_replay_after_an_eager_full_setup(n):
+    """A captured refactor + solve of the register-resident kernel keeps
+    reading its own packed L^{-1} after an eager call on the same handle
+    switched it to the full factors (the preconditioner runs on the generic
+    kernel and sets up L and the full L^{-1} first): every replay reproduces
+    the eager result."""
+    import torch
+    data = batch(n, 24, (16, 120), seed=71)
+    P = bt.Params.polycoeff(2, prec="f32_ir")
+    D = to_dev(data["D"], torch.float32)
+    O = to_dev(data["O"], torch.float32)
+    b = to_dev(data["b"].reshape(-1), torch.float64)
+    h = bt.Handle(D, O, data["offsets"], P)
+    assert h.kernel_config() in fast_indices()
+    x = torch.empty_like(b)
+    info = torch.empty((len(data["offsets"]) - 1) * bt.INFO_DTYPE.itemsize,
+                       dtype=torch.uint8, device="cuda")
+    h.refactor()
+    h.solve(b, 1e-10, x=x, info=info)
+    torch.cuda.synchronize()
+    x_ref, info_ref = x.clone(), info.clone()
+    assert np.all(bt.infos_to_numpy(info)["status"] == bt.OK)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        h.refactor()
+        h.solve(b, 1e-10, x=x, info=info)
+    z = h.precondition(b)          # eager: full setup of the same handle
+    torch.cuda.synchronize()
+    assert torch.isfinite(z).all()
+    for rep in range(3):
+        x.zero_()
+        info.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(x, x_ref), rep
+        assert torch.equal(info, info_ref), rep
+        h.precondition(b)          # and again between replays
+    # an eager solve after all this agrees as well
+    x2, info2 = h.solve(b, 1e-10)
+    torch.cuda.synchronize()
+    assert torch.equal(x2, x_ref)
