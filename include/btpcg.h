@@ -148,7 +148,11 @@ int bt_batch_setup(bt_handle** h, int B, const int64_t* offsets_host, int n,
 /* Recompute the factors of an existing handle from the current contents of
  * its D and O buffers (same shapes, same pointers), e.g. after the caller
  * overwrote them with a new system. Enqueues kernels only (no copies), so it
- * can be captured into a HIP graph together with a solve. */
+ * can be captured into a HIP graph together with a solve. A replayed capture
+ * recomputes what the captured call computed: for a handle served by the
+ * register-resident kernel, the blocks that kernel reads. After replays with
+ * new D and O, call bt_refactor once without a graph before using the handle
+ * with bt_precondition, bt_solve_grid or another kernel configuration. */
 int bt_refactor(bt_handle* h, void* stream);
 
 /* Single system: bt_batch_setup with B = 1 and offsets {0, N}. */
