@@ -811,6 +811,38 @@ __global__ void __launch_bounds__(256)
   }
 }
 
+// The same for a block size known at compile time (even): each thread
+// writes two consecutive entries with one 16-byte store, and the index
+// arithmetic divides by constants.
+template <int NB>
+__global__ void __launch_bounds__(256)
+    k_adjoint_outer_nb(int64_t R, const int64_t* off, const int32_t* rowinst,
+                       const double* x, const double* lam, double* dD,
+                       double* dO) {
+  static_assert(NB % 2 == 0, "pairs of entries");
+  constexpr int NN = NB * NB, PR = NN / 2;
+  const int64_t g0 = (int64_t)blockIdx.x * ADJ_ROWS;
+  const int rows = (int)(R - g0 < ADJ_ROWS ? R - g0 : ADJ_ROWS);
+  for (int e = threadIdx.x; e < rows * PR; e += 256) {
+    const int rr = e / PR, w = 2 * (e - rr * PR);
+    const int i = w / NB, j = w - i * NB;  // j even, j + 1 < NB
+    const int64_t g = g0 + rr;
+    const int inst = rowinst[g];
+    const double* xg = x + g * NB;
+    const double* lg = lam + g * NB;
+    if (dD) {
+      const double2 v = make_double2(-lg[i] * xg[j], -lg[i] * xg[j + 1]);
+      *reinterpret_cast<double2*>(dD + (size_t)g * NN + w) = v;
+    }
+    if (dO && g + 1 < off[inst + 1]) {
+      const double2 v =
+          make_double2(-(lg[i] * xg[NB + j] + xg[i] * lg[NB + j]),
+                       -(lg[i] * xg[NB + j + 1] + xg[i] * lg[NB + j + 1]));
+      *reinterpret_cast<double2*>(dO + (size_t)(g - inst) * NN + w) = v;
+    }
+  }
+}
+
 }  // namespace btk
 
 hipError_t bt_launch_setup(const SetupArgs& a0, hipStream_t s) {
@@ -869,6 +901,26 @@ hipError_t bt_launch_adjoint_outer(int B, int n, int64_t R, const int64_t* off,
                                    hipStream_t s) {
   if (R <= 0) return hipSuccess;
   const int64_t grid = (R + btk::ADJ_ROWS - 1) / btk::ADJ_ROWS;
+  // 16-byte stores need 16-byte aligned outputs
+  const bool a16 = ((uintptr_t)dD % 16 == 0) && ((uintptr_t)dO % 16 == 0);
+#define BT_ADJ_NB(NB)                                                        \
+  case NB:                                                                  \
+    hipLaunchKernelGGL(btk::k_adjoint_outer_nb<NB>, dim3((unsigned)grid),   \
+                       dim3(256), 0, s, R, off, rowinst, x, lam, dD, dO);   \
+    return hipGetLastError();
+  if (a16) {
+    switch (n) {
+      BT_ADJ_NB(6)
+      BT_ADJ_NB(12)
+      BT_ADJ_NB(16)
+      BT_ADJ_NB(24)
+      BT_ADJ_NB(32)
+      BT_ADJ_NB(48)
+      BT_ADJ_NB(64)
+      default: break;
+    }
+  }
+#undef BT_ADJ_NB
   hipLaunchKernelGGL(btk::k_adjoint_outer, dim3((unsigned)grid), dim3(256), 0,
                      s, B, n, R, off, rowinst, x, lam, dD, dO);
   return hipGetLastError();
