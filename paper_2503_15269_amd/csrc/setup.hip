@@ -651,12 +651,15 @@ __global__ void __launch_bounds__(64) k_factor_wave(SetupArgs a) {
   }
   // X = L^{-1} by the same scheme, lane r holding row r of X: at step k
   // row k is final (scaled by 1 / L[k][k]) and published; every row i > k
-  // subtracts L[i][k] times it (L[i][k] is lane i's own m[k]).
-  double x[NB];
-#pragma unroll
-  for (int c = 0; c < NB; ++c) x[c] = (c == rr) ? 1.0 : 0.0;
+  // subtracts L[i][k] times it (L[i][k] is lane i's own m[k]). X overwrites
+  // L in place: before step k, x[c] holds X[rr][c] for c < k and L[rr][c]
+  // for c >= k; entry k of L is read for the last time at step k, where
+  // entry k of X (so far the unit row's) takes its place.
+  double (&x)[NB] = m;
 #pragma unroll
   for (int k = 0; k < NB; ++k) {
+    const double lk = x[k];                  // L[rr][k]
+    x[k] = k == rr ? 1.0 : 0.0;
     const double sc = rr == k ? myrd : 1.0;  // row k becomes final
 #pragma unroll
     for (int c = 0; c <= k; ++c) x[c] *= sc;
@@ -666,7 +669,7 @@ __global__ void __launch_bounds__(64) k_factor_wave(SetupArgs a) {
       for (int c = 0; c <= k; ++c) rk[c] = x[c];
     }
     __syncthreads();
-    const double f = rr > k ? m[k] : 0.0;  // rows below k subtract it
+    const double f = rr > k ? lk : 0.0;  // rows below k subtract it
 #pragma unroll
     for (int c = 0; c <= k; ++c) x[c] = fma(-f, rk[c], x[c]);
   }
