@@ -107,7 +107,7 @@ typedef struct bt_params {
  * warm_start = 0. */
 void bt_default_params(bt_params* p);
 
-/* Per-instance outcome, written on the device (32 bytes). */
+/* Per-instance outcome, written on the device (48 bytes). */
 typedef struct bt_info {
   int32_t status;      /* BT_OK, BT_NOT_CONVERGED, BT_ENOTSPD, BT_EBREAKDOWN,
                           BT_ENONFINITE */
@@ -118,6 +118,20 @@ typedef struct bt_info {
                           factorisation, else -1 */
   double relres;       /* ||r|| / ||b|| seen by the final stopping test */
   double relres_true;  /* ||b - A x|| / ||b|| in float64 from the record */
+  int64_t gemv_exec;   /* block-times-vector products the solve executed,
+                          summed over the instance's N block rows: two per
+                          row and application of the off-diagonal operator
+                          (one on the first and last row), one per row and
+                          triangular transform with L_k^{-1} or L_k, three
+                          per row and float64 residual of the record (two on
+                          the first and last row). Halo rows that a kernel
+                          recomputes are not counted. 0 for the direct
+                          solve. */
+  int64_t gemv_paper;  /* the paper's count iters * g_a(m) of Section IV-B
+                          (block gemvs per block row: g = 2m+2 at a = 0,
+                          5m+1 for 0 < a < 1, 3m+3 at a = 1; 3 without
+                          preconditioner, the product with A alone); 0 for
+                          the direct solve */
 } bt_info;
 
 typedef struct bt_handle bt_handle;
@@ -165,20 +179,32 @@ int bt_setup(bt_handle** h, int N, int n, int dtype, const void* D,
 int bt_precondition(const bt_handle* h, const double* r, double* z,
                     void* stream);
 
-/* Solve A x = b for every instance by PCG from x0 = 0 until
+/* Solve A x = b (eq. 1 of Section II-A) for every instance by the conjugate
+ * gradient method preconditioned with M_m^{-1} (the iteration the paper
+ * cites in Section I and whose per-iteration cost Section IV-B counts: one
+ * product with A and one application of M_m^{-1}, evaluated as y_0 = G r,
+ * y_i = H y_{i-1}), from x0 = 0 (or x0 = x under warm_start) until
  * ||b - A x|| <= tol ||b|| (recursive residual; under BT_F32_IR the test is
  * on the float64 residual of the record) or maxit iterations.
- * b, x: device [R][n] float64. info: device, B entries. */
+ * b, x: device [R][n] float64. info: device, B entries.
+ * Errors (returned): BT_EINVAL (NULL pointers, tol < 0, maxit < 0), BT_EHIP.
+ * Per-instance outcomes go to info. */
 int bt_solve(const bt_handle* h, const double* b, double* x, double tol,
              int maxit, bt_info* info, void* stream);
 
-/* Same as bt_solve; the name of the batched entry point. All instances run
- * in one persistent launch, each converging on its own. */
+/* Same as bt_solve; the name of the batched entry point. B independent
+ * instances of eq. 1 (Section II-A), each with its own horizon N_i, run in
+ * one persistent launch and each converges on its own (the paper's
+ * Section IV-C counts one workgroup per block row; here one workgroup holds
+ * whole instances). */
 int bt_solve_batched(const bt_handle* h, const double* b, double* x,
                      double tol, int maxit, bt_info* info, void* stream);
 
-/* Adjoint of x = A^{-1} b for an upstream gradient g = dL/dx:
- * lambda = A^{-1} g (same preconditioned solve; A is symmetric),
+/* Adjoint of x = A^{-1} b for an upstream gradient g = dL/dx. The solve is
+ * the same preconditioned iteration as bt_solve (A is symmetric, Section
+ * II-A, so A^{-T} = A^{-1}); the gradient identities are those of any
+ * linear solve (the paper has no adjoint):
+ * lambda = A^{-1} g,
  * dL/db = lambda, dL/dD_k = -lambda_k x_k^T,
  * dL/dO_k = -(lambda_k x_{k+1}^T + x_k lambda_{k+1}^T).
  * x, g, lambda: device [R][n]; dD: device [R][n][n]; dO: device
@@ -219,8 +245,11 @@ int bt_solve_direct(const bt_handle* h, const double* b, double* x,
                     bt_info* info, void* scratch, size_t scratch_bytes,
                     void* stream);
 
-/* One system spread over the whole GPU (Algorithm PCG of Section II with the
- * preconditioner of eq. Mminv-polynomial-coefficients, Section IV-B): every
+/* One system spread over the whole GPU (the preconditioned conjugate
+ * gradient iteration of bt_solve with the preconditioner of eq.
+ * Mminv-polynomial-coefficients evaluated as in Section IV-B; the
+ * parallel layout follows the n_blk workgroups over block rows of Section
+ * IV-C): every
  * step of the iteration is a kernel over all block rows, so a single long
  * horizon is not confined to one workgroup, and systems above the
  * single-workgroup capacity of bt_solve (N n > 8192) can be solved. Same

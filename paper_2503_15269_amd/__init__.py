@@ -28,7 +28,8 @@ MAX_M = 8
 
 INFO_DTYPE = np.dtype([("status", "<i4"), ("iters", "<i4"), ("outer", "<i4"),
                        ("fail_index", "<i4"), ("relres", "<f8"),
-                       ("relres_true", "<f8")])
+                       ("relres_true", "<f8"), ("gemv_exec", "<i8"),
+                       ("gemv_paper", "<i8")])
 
 
 class _Params(ctypes.Structure):
@@ -204,6 +205,19 @@ def infos_to_numpy(info_tensor):
     """Device bt_info array -> numpy structured array (synchronises)."""
     raw = info_tensor.detach().cpu().numpy().tobytes()
     return np.frombuffer(raw, dtype=INFO_DTYPE).copy()
+
+
+def check_infos(info_tensor, what="solve"):
+    """Raise BtError on the first instance whose status is not OK
+    (synchronises); returns the infos as a numpy structured array."""
+    inf = infos_to_numpy(info_tensor)
+    bad = np.nonzero(inf["status"] != OK)[0]
+    if len(bad):
+        i = int(bad[0])
+        raise BtError(int(inf["status"][i]),
+                      f"{what}: instance {i} of {len(inf)} "
+                      f"({len(bad)} not converged)")
+    return inf
 
 
 class Handle:
@@ -437,11 +451,13 @@ def _autograd():
 
         @staticmethod
         def forward(ctx, D, O, b, offsets=None, params=None, tol=1e-10,
-                    maxit=None):
+                    maxit=None, check=True):
             h = Handle(D.detach(), O.detach() if O is not None else None,
                        offsets, params)
             x, info = h.solve(b.detach().reshape(-1).contiguous(), tol, maxit)
-            ctx.h, ctx.tol, ctx.maxit = h, tol, maxit
+            if check:  # a failed solve must not reach autograd silently
+                check_infos(info, "BtSolve forward")
+            ctx.h, ctx.tol, ctx.maxit, ctx.check = h, tol, maxit, check
             ctx.bshape = b.shape
             ctx.info = info
             ctx.save_for_backward(x)
@@ -454,11 +470,13 @@ def _autograd():
             lam, dD, dO, info = ctx.h.adjoint(x, g, ctx.tol, ctx.maxit,
                                               need_dD=ctx.needs_input_grad[0],
                                               need_dO=ctx.needs_input_grad[1])
+            if ctx.check:
+                check_infos(info, "BtSolve backward (adjoint)")
             ctx.adj_info = info
             D, O = ctx.h.D, ctx.h.O
             gD = dD.to(D.dtype) if dD is not None else None
             gO = dO.to(O.dtype) if (dO is not None and O is not None) else None
-            return gD, gO, lam.view(ctx.bshape), None, None, None, None
+            return gD, gO, lam.view(ctx.bshape), None, None, None, None, None
 
     return BtSolve
 
@@ -466,12 +484,16 @@ def _autograd():
 _BtSolve = None
 
 
-def bt_solve(D, O, b, offsets=None, params=None, tol=1e-10, maxit=None):
-    """Differentiable solve (torch.autograd.Function ``BtSolve``)."""
+def bt_solve(D, O, b, offsets=None, params=None, tol=1e-10, maxit=None,
+             check=True):
+    """Differentiable solve (torch.autograd.Function ``BtSolve``). With
+    ``check`` (default) the forward and the adjoint raise BtError when an
+    instance did not converge (this synchronises; pass False under graph
+    capture and read the infos instead)."""
     global _BtSolve
     if _BtSolve is None:
         _BtSolve = _autograd()
-    return _BtSolve.apply(D, O, b, offsets, params, tol, maxit)
+    return _BtSolve.apply(D, O, b, offsets, params, tol, maxit, check)
 
 
 def BtSolve():

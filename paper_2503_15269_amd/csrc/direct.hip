@@ -203,6 +203,8 @@ __global__ void __launch_bounds__(64) k_direct(DirectArgs a) {
     inf->fail_index = fail;
     inf->relres = NAN;
     inf->relres_true = NAN;
+    inf->gemv_exec = 0;
+    inf->gemv_paper = 0;
   }
 }
 

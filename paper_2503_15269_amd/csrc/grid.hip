@@ -56,6 +56,9 @@ template <typename T>
 struct GArgs {
   int R, n, rb, depth, nwg, pc, m, ir, dtype;
   double a, tol, itol;
+  // k_g_init reads src * sscale (a power of two: the right-hand side of the
+  // inner solve at norm in [1, 2)); k_g_x adds L^{-T} d * xscale = 1/sscale
+  double sscale, xscale;
   double alpha[BT_MAX_M];
   const T* F;
   const T* L;
@@ -353,14 +356,14 @@ __global__ void __launch_bounds__(NT) k_g_init(GArgs<T> a) {
   }
   const FBlocks<T> F = stage_F(a, W.w0, W.w1 - 1, lds_F(a, red));
   for (int e = threadIdx.x; e < len; e += NT)
-    y[e] = (T)a.src[(size_t)W.w0 * n + e];
+    y[e] = (T)(a.src[(size_t)W.w0 * n + e] * a.sscale);
   __syncthreads();
   double nb = 0.0;
   for (int e = threadIdx.x; e < len; e += NT) {
     const int k = W.w0 + e / n, i = e % n;
     r[e] = lower(a.Li, y + (k - W.w0) * n, n, k, i);
     if (k >= W.k0 && k < W.k1) {
-      const double s = a.src[(size_t)W.w0 * n + e];
+      const double s = a.src[(size_t)W.w0 * n + e] * a.sscale;
       nb += s * s;
       a.rbuf[0][(size_t)k * n + i] = r[e];
       a.xh[(size_t)k * n + i] = T(0);
@@ -513,7 +516,8 @@ __global__ void __launch_bounds__(NT) k_g_x(GArgs<T> a, int add) {
   __syncthreads();
   for (int e = threadIdx.x; e < (W.k1 - W.k0) * n; e += NT) {
     const int k = W.k0 + e / n, i = e % n;
-    const double u = (double)lowerT(a.Li, v + (k - W.k0) * n, n, k, i);
+    const double u =
+        (double)lowerT(a.Li, v + (k - W.k0) * n, n, k, i) * a.xscale;
     const size_t g = (size_t)W.k0 * n + e;
     a.x[g] = add ? a.x[g] + u : u;
   }
@@ -628,6 +632,7 @@ int run(const bt_handle* h, const double* b, double* x, double tol, int maxit,
   a.dtype = h->dtype;
   a.tol = tol;
   a.itol = h->p.inner_tol;
+  a.sscale = a.xscale = 1.0;
   a.F = (const T*)h->F;
   a.L = (const T*)h->L;
   a.Li = (const T*)h->Li;
@@ -697,13 +702,34 @@ int run(const bt_handle* h, const double* b, double* x, double tol, int maxit,
   int status = BT_NOT_CONVERGED, total = 0, outer = 0;
   double nb2 = 0.0, nr2 = 0.0, nrt2 = 0.0;
   const bool refine = h->p.prec == BT_F32_IR || h->p.prec == BT_BF16X2_IR;
+  // executed block products: halves of applications of C, triangular
+  // transforms, float64 residuals (halo rows recomputed by a workgroup are
+  // not counted)
+  int64_t g_half = 0, g_tri = 0, g_res = 0;
+  const bool none = a.pc == BT_PC_NONE;
+  const int apc = none ? 0
+                       : (a.a != 0.0 ? 1 : 0) + (a.m - 1) * (a.a != 0.0 ? 2 : 1);
+  // one inner solve of ``steps`` steps: k_g_init (L^{-1} s, z = M^{-1} r),
+  // per step q = Ahat p and z = M^{-1} r (and ||L r|| without refinement),
+  // then k_g_x (L^{-T})
+  auto count_inner = [&](int steps) {
+    g_half += 2 * ((int64_t)apc * (steps + 1) + steps);
+    g_tri += 2 + (none ? 2 * (int64_t)(steps + 1) : 0) + (a.ir ? 0 : steps);
+  };
   const bool warm = h->p.warm_start != 0;
-  if (!refine && warm) {
+  // float32 without refinement also starts from the residual of x0 = 0,
+  // which gives ||b|| before the iteration, so that its right-hand side can
+  // be scaled (float64 needs no scaling and saves the pass)
+  const bool from_res = warm || sizeof(T) == sizeof(float);
+  if (!refine && from_res) {
     // from the initial guess x0 (held in x): plain PCG on the correction,
     // A d = r0 = b - A x0, with the test ||r|| <= tol ||b|| carried over to
     // the correction's right-hand side
+    if (!warm && hipMemsetAsync(x, 0, v * sizeof(double), s) != hipSuccess)
+      return BT_EHIP;
     if (launch(k_g_res<T>, pl, s) != hipSuccess || !sync_state(true))
       return BT_EHIP;
+    ++g_res;
     nb2 = host_slot(P_NB2);
     const double nr02 = host_slot(P_RES);
     nr2 = nrt2 = nr02;
@@ -720,18 +746,22 @@ int run(const bt_handle* h, const double* b, double* x, double tol, int maxit,
     } else {
       a.src = a.r64;
       a.tol = tol * std::sqrt(nb2 / nr02);
+      a.sscale = bt_unit_scale(nr02);
+      a.xscale = 1.0 / a.sscale;
       if (launch(k_g_init<T>, pl, s) != hipSuccess) return BT_EHIP;
       int steps = 0;
       if (!iterate(maxit, &steps)) return BT_EHIP;
       status = ctl.status;
       total = steps;
+      count_inner(steps);
       double* r64 = a.r64;
       a.r64 = nullptr;
       if (launch(k_g_x<T>, pl, s, 1) != hipSuccess ||
           launch(k_g_res<T>, pl, s) != hipSuccess || !sync_state(true))
         return BT_EHIP;
+      ++g_res;
       a.r64 = r64;
-      nr2 = total > 0 ? host_slot(P_NR2) : nr02;
+      nr2 = total > 0 ? host_slot(P_NR2) * a.xscale * a.xscale : nr02;
       nrt2 = host_slot(P_RES);
       if (status == BT_NOT_CONVERGED && total > 0 && nr2 <= tol * tol * nb2)
         status = BT_OK;
@@ -744,11 +774,13 @@ int run(const bt_handle* h, const double* b, double* x, double tol, int maxit,
     if (!iterate(maxit, &steps)) return BT_EHIP;
     status = ctl.status;
     total = steps;
+    count_inner(steps);
     outer = 1;
     a.r64 = nullptr;
     if (launch(k_g_x<T>, pl, s, 0) != hipSuccess ||
         launch(k_g_res<T>, pl, s) != hipSuccess || !sync_state(true))
       return BT_EHIP;
+    ++g_res;
     nb2 = host_slot(P_NB2);
     nr2 = total > 0 ? host_slot(P_NR2) : nb2;
     nrt2 = host_slot(P_RES);
@@ -764,6 +796,7 @@ int run(const bt_handle* h, const double* b, double* x, double tol, int maxit,
     for (;;) {
       if (launch(k_g_res<T>, pl, s) != hipSuccess || !sync_state(true))
         return BT_EHIP;
+      if (outer > 0 || warm) ++g_res;  // the first pass from 0 reads b only
       nr2 = host_slot(P_RES);
       if (outer == 0) nb2 = host_slot(P_NB2);
       nrt2 = nr2;
@@ -778,16 +811,20 @@ int run(const bt_handle* h, const double* b, double* x, double tol, int maxit,
       if (!(nr2 < INFINITY)) { status = BT_ENONFINITE; break; }
       if (outer >= h->p.max_outer || total >= maxit) break;
       a.src = a.r64;
+      a.sscale = bt_unit_scale(nr2);
+      a.xscale = 1.0 / a.sscale;
       if (launch(k_g_init<T>, pl, s) != hipSuccess) return BT_EHIP;
       int steps = 0;
       if (!iterate(maxit - total, &steps)) return BT_EHIP;
       total += steps;
+      count_inner(steps);
       if (launch(k_g_x<T>, pl, s, 1) != hipSuccess) return BT_EHIP;
       ++outer;
       if (steps == 0) {
         status = BT_EBREAKDOWN;
         if (launch(k_g_res<T>, pl, s) != hipSuccess || !sync_state(true))
           return BT_EHIP;
+        ++g_res;
         nrt2 = nr2 = host_slot(P_RES);
         break;
       }
@@ -800,6 +837,8 @@ int run(const bt_handle* h, const double* b, double* x, double tol, int maxit,
   hi.fail_index = -1;
   hi.relres = nb2 > 0.0 ? std::sqrt(nr2 / nb2) : 0.0;
   hi.relres_true = nb2 > 0.0 ? std::sqrt(nrt2 / nb2) : 0.0;
+  hi.gemv_exec = bt_gemv_rows(a.R, g_half, g_tri, g_res);
+  hi.gemv_paper = (int64_t)total * bt_gemv_g(a.pc, a.a, a.m);
   if (hipMemcpyAsync(info, &hi, sizeof(hi), hipMemcpyHostToDevice, s) !=
           hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)

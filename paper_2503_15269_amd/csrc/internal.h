@@ -116,6 +116,35 @@ struct SetupArgs {
   void* Li;
 };
 
+// The paper's block gemvs per block row and PCG iteration, g_a(m) of
+// Section IV-B (2m + 2 at a = 0, 5m + 1 for 0 < a < 1, 3m + 3 at a = 1);
+// 3 without preconditioner (the product with A alone).
+__host__ __device__ inline int bt_gemv_g(int pc, double a, int m) {
+  if (pc == BT_PC_NONE) return 3;
+  if (a == 0.0) return 2 * m + 2;
+  if (a == 1.0) return 3 * m + 3;
+  return 5 * m + 1;
+}
+
+// Block-times-vector products over the N block rows of one system, from the
+// counts of what a solve executed: ``halves`` halves of an application of
+// the off-diagonal operator C (the F_{k-1}^T half and the F_k half, each one
+// product on N - 1 rows), ``tri`` triangular transforms (one product per
+// row) and ``res`` float64 residuals of the record (D, O and O^T: 3N - 2).
+__host__ __device__ inline int64_t bt_gemv_rows(int N, int64_t halves,
+                                                int64_t tri, int64_t res) {
+  return halves * (N - 1) + tri * N + res * (3 * (int64_t)N - 2);
+}
+
+// Power of two 2^-e with 2^e <= sqrt(n2) < 2^(e+1): scales a float64
+// residual of squared norm n2 to norm in [1, 2) before it is rounded to
+// float32, so the inner float32 solve sees neither underflow nor overflow
+// whatever the scale of b; multiplying by a power of two is exact.
+__host__ __device__ inline double bt_unit_scale(double n2) {
+  if (!(n2 > 0.0) || !(n2 < INFINITY)) return 1.0;
+  return ldexp(1.0, -ilogb(sqrt(n2)));
+}
+
 struct KernelConfig {
   int nt, s, prec;  // prec: BT_F64 for double kernels, BT_F32 for float ones;
                     // s = 0: the register-resident bin kernel

@@ -667,10 +667,13 @@ __global__ void __launch_bounds__(256) k_mr_tohat(MrArgs a, const double* r64) {
 #pragma unroll
   for (int m = 0; m < MR; ++m) acc[m] = 0.f;
   if (a.act[c]) {
+    // the column's residual scaled by a power of two to norm in [1, 2)
+    // before it is rounded to float32 (undone in k_mr_xupd)
+    const double sc = bt_unit_scale(a.nr2[c]);
     const double* rk = r64 + (size_t)k * pn + c;
 #pragma unroll 4
     for (int j = 0; j < NB; ++j) {
-      const float rv = (float)rk[(size_t)j * L];
+      const float rv = (float)(rk[(size_t)j * L] * sc);
 #pragma unroll
       for (int m = 0; m < MR; ++m)  // L^{-1} is zero above the diagonal
         acc[m] = __fmaf_rn(sL[(w + 4 * m) * NB + j], rv, acc[m]);
@@ -707,9 +710,11 @@ __global__ void __launch_bounds__(256) k_mr_xupd(MrArgs a) {
     for (int m = 0; m < MR; ++m)  // (L^{-1})_{j i} = 0 for j < i
       acc[m] = __fmaf_rn(sL[j * NB + w + 4 * m], dv, acc[m]);
   }
+  const double unscale = 1.0 / bt_unit_scale(a.nr2[c]);
 #pragma unroll
   for (int m = 0; m < MR; ++m)
-    a.x[(size_t)k * pn + (size_t)(w + 4 * m) * L + c] += (double)acc[m];
+    a.x[(size_t)k * pn + (size_t)(w + 4 * m) * L + c] +=
+        (double)acc[m] * unscale;
 }
 
 __global__ void k_mr_outer_done(MrArgs a) {
@@ -729,7 +734,7 @@ __global__ void k_mr_zero_x(MrArgs a) {
     a.x[i] = 0.0;
 }
 
-__global__ void k_mr_info(MrArgs a, bt_info* info) {
+__global__ void k_mr_info(MrArgs a, bt_info* info, int warm) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= a.nrhs) return;
   const double nb = a.nb2[c];
@@ -740,6 +745,14 @@ __global__ void k_mr_info(MrArgs a, bt_info* info) {
   const double rr = nb > 0.0 ? sqrt(a.nr2[c] / nb) : 0.0;
   info[c].relres = rr;
   info[c].relres_true = rr;
+  // per refinement step: z = M^{-1} r (2m - 1 applications of C) and the
+  // two triangular transforms; per inner iteration: 2m applications; a
+  // float64 residual after every step (and before the first from a guess)
+  const int64_t halves =
+      2 * ((int64_t)(2 * a.m - 1) * a.outer[c] + (int64_t)2 * a.m * a.total[c]);
+  info[c].gemv_exec =
+      bt_gemv_rows(a.R, halves, 2 * a.outer[c], a.outer[c] + (warm ? 1 : 0));
+  info[c].gemv_paper = (int64_t)a.total[c] * bt_gemv_g(BT_PC_POLY, 1.0, a.m);
 }
 
 // F (float32) -> hi + lo (bfloat16 pair): entries [0, R NN) the split of the
@@ -856,7 +869,7 @@ int solve(const MrArgs& a0, double* r64, int max_outer, int warm,
                        s, a);
   }
   hipLaunchKernelGGL(k_mr_info, dim3((a.nrhs + 63) / 64), dim3(64), 0, s, a,
-                     info);
+                     info, warm);
   return hipGetLastError() == hipSuccess ? BT_OK : BT_EHIP;
 }
 

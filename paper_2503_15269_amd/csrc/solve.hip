@@ -133,8 +133,15 @@ struct Ops {
   using Acc = typename AccOf<T>::type;
   Shared<T>& sh;
   const Inst<T, NT, S>& in;
+  // what the system executed: halves of applications of C, triangular
+  // transforms, float64 residuals (the same in every thread)
+  int nh = 0, ntr = 0, nrs = 0;
 
   __device__ Ops(Shared<T>& s, const Inst<T, NT, S>& i) : sh(s), in(i) {}
+
+  __device__ __forceinline__ int64_t gemv_exec() const {
+    return bt_gemv_rows(in.N, nh, ntr, nrs);
+  }
 
   // Write v into the other staging buffer and publish it to the workgroup.
   __device__ __forceinline__ const T* stage(const T (&v)[S]) {
@@ -148,6 +155,7 @@ struct Ops {
   }
 
   __device__ __forceinline__ void C(const T* v, T (&out)[S]) {
+    nh += 2;
 #pragma unroll
     for (int s = 0; s < S; ++s)
       out[s] = in.act[s] ? apply_C<T>(in.F, v, in.N, in.n, in.k[s], in.i[s])
@@ -179,6 +187,7 @@ struct Ops {
                           const T (&t)[S], T (&z)[S]) {
     if (a.pc == BT_PC_NONE) {
       const T* ts = stage(t);
+      ++ntr;
 #pragma unroll
       for (int s = 0; s < S; ++s)
         z[s] = in.act[s] ? apply_lowerT<T>(in.L, ts, in.n, in.k[s], in.i[s])
@@ -256,7 +265,9 @@ struct Ops {
 
 __device__ __forceinline__ void write_info(bt_info* info, int status,
                                            int iters, int outer, int fail,
-                                           double relres, double relres_true) {
+                                           double relres, double relres_true,
+                                           int64_t gemv_exec = 0,
+                                           int64_t gemv_paper = 0) {
   if (threadIdx.x == 0) {
     info->status = status;
     info->iters = iters;
@@ -264,6 +275,8 @@ __device__ __forceinline__ void write_info(bt_info* info, int status,
     info->fail_index = fail;
     info->relres = relres;
     info->relres_true = relres_true;
+    info->gemv_exec = gemv_exec;
+    info->gemv_paper = gemv_paper;
   }
 }
 
@@ -292,6 +305,7 @@ __device__ __forceinline__ void solve_direct(const SolveArgs& a, Shared<T>& sh,
   }
   if (a.warm) {
     const double* xd = op.stage_d(x0);
+    ++op.nrs;
 #pragma unroll
     for (int s = 0; s < S; ++s)
       if (in.act[s]) {
@@ -302,12 +316,15 @@ __device__ __forceinline__ void solve_direct(const SolveArgs& a, Shared<T>& sh,
   const double nb2 = op.sumd(nbp);
   const double nr02 = a.warm ? op.sumd(nrp) : nb2;
   __syncthreads();  // the T buffers overlap the float64 view
-  // rhat = L^{-1} r0
+  // rhat = L^{-1} r0, r0 scaled by a power of two to norm in [1, 2) (exact;
+  // keeps float32 iterations clear of underflow and overflow)
+  const double sc = bt_unit_scale(nr02), unscale = 1.0 / sc;
   {
     T bt[S];
 #pragma unroll
-    for (int s = 0; s < S; ++s) bt[s] = (T)r0[s];
+    for (int s = 0; s < S; ++s) bt[s] = (T)(r0[s] * sc);
     const T* bs = op.stage(bt);
+    ++op.ntr;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       r[s] = in.act[s] ? apply_lower<T>(in.Li, bs, in.n, in.k[s], in.i[s])
@@ -337,7 +354,7 @@ __device__ __forceinline__ void solve_direct(const SolveArgs& a, Shared<T>& sh,
   // t = L r is only needed for BT_PC_NONE at the start (r = rhat, L r = r0)
   if (a.pc == BT_PC_NONE) {
 #pragma unroll
-    for (int s = 0; s < S; ++s) t[s] = in.act[s] ? (T)r0[s] : T(0);
+    for (int s = 0; s < S; ++s) t[s] = in.act[s] ? (T)(r0[s] * sc) : T(0);
   }
   op.precond(a, r, nullptr, t, z);
   double rho = op.dot(r, z);
@@ -365,11 +382,12 @@ __device__ __forceinline__ void solve_direct(const SolveArgs& a, Shared<T>& sh,
     }
     // ||r|| = ||L rhat||
     const T* rs = op.stage(r);
+    ++op.ntr;
 #pragma unroll
     for (int s = 0; s < S; ++s)
       t[s] = in.act[s] ? apply_lower<T>(in.L, rs, in.n, in.k[s], in.i[s])
                        : T(0);
-    nr2 = op.dot(t, t);
+    nr2 = op.dot(t, t) * (unscale * unscale);
     if (nr2 <= tol2) {
       status = BT_OK;
       break;
@@ -395,14 +413,17 @@ __device__ __forceinline__ void solve_direct(const SolveArgs& a, Shared<T>& sh,
   double xo[S];
   {
     const T* xs = op.stage(xh);
+    ++op.ntr;
 #pragma unroll
     for (int s = 0; s < S; ++s)
       xo[s] = in.act[s]
                   ? x0[s] + (double)apply_lowerT<T>(in.Li, xs, in.n, in.k[s],
-                                                    in.i[s])
+                                                    in.i[s]) *
+                                unscale
                   : 0.0;
   }
   const double* xd = op.stage_d(xo);
+  ++op.nrs;
   double rp = 0.0;
 #pragma unroll
   for (int s = 0; s < S; ++s)
@@ -412,7 +433,8 @@ __device__ __forceinline__ void solve_direct(const SolveArgs& a, Shared<T>& sh,
       rp += rv * rv;
     }
   const double rt2 = op.sumd(rp);
-  write_info(info, status, it, 1, -1, sqrt(nr2 / nb2), sqrt(rt2 / nb2));
+  write_info(info, status, it, 1, -1, sqrt(nr2 / nb2), sqrt(rt2 / nb2),
+             op.gemv_exec(), (int64_t)it * bt_gemv_g(a.pc, a.a, a.m));
 }
 
 // ------------------------------------------------------------------------
@@ -448,6 +470,7 @@ __device__ __forceinline__ void solve_ir(const SolveArgs& a, Shared<T>& sh,
   const double itol2 = a.inner_tol * a.inner_tol;
   int status = BT_NOT_CONVERGED, total = 0, outer = 0;
   double nr2 = nb2;
+  double unscale = 1.0;  // 1 / the scale of the current inner solve
   T r[S], d[S], p[S], q[S], z[S], t[S];
 #pragma unroll
   for (int s = 0; s < S; ++s) t[s] = T(0);
@@ -455,6 +478,7 @@ __device__ __forceinline__ void solve_ir(const SolveArgs& a, Shared<T>& sh,
   for (;;) {
     if (outer > 0 || a.warm) {
       const double* xd = op.stage_d(x64);
+      ++op.nrs;
       double rp = 0.0;
 #pragma unroll
       for (int s = 0; s < S; ++s)
@@ -476,12 +500,16 @@ __device__ __forceinline__ void solve_ir(const SolveArgs& a, Shared<T>& sh,
     if (outer >= a.max_outer || total >= a.maxit) break;
     ++outer;
 
-    // inner system: Ahat dhat = L^{-1} r64
+    // inner system: Ahat dhat = L^{-1} r64, the residual scaled by a power
+    // of two to norm in [1, 2) before it is rounded to the inner precision
+    const double sc = bt_unit_scale(nr2);
+    unscale = 1.0 / sc;
     {
       T rt[S];
 #pragma unroll
-      for (int s = 0; s < S; ++s) rt[s] = (T)r64[s];
+      for (int s = 0; s < S; ++s) rt[s] = (T)(r64[s] * sc);
       const T* rs = op.stage(rt);
+      ++op.ntr;
 #pragma unroll
       for (int s = 0; s < S; ++s) {
         r[s] = in.act[s] ? apply_lower<T>(in.Li, rs, in.n, in.k[s], in.i[s])
@@ -491,7 +519,7 @@ __device__ __forceinline__ void solve_ir(const SolveArgs& a, Shared<T>& sh,
     }
     if (a.pc == BT_PC_NONE) {
 #pragma unroll
-      for (int s = 0; s < S; ++s) t[s] = (T)r64[s];
+      for (int s = 0; s < S; ++s) t[s] = (T)(r64[s] * sc);
     }
     const double n0 = op.dot(r, r);
     const double itarget = itol2 * n0;
@@ -519,6 +547,7 @@ __device__ __forceinline__ void solve_ir(const SolveArgs& a, Shared<T>& sh,
       const T* rs = nullptr;
       if (a.pc == BT_PC_NONE) {
         rs = op.stage(r);
+        ++op.ntr;
 #pragma unroll
         for (int s = 0; s < S; ++s)
           t[s] = in.act[s] ? apply_lower<T>(in.L, rs, in.n, in.k[s], in.i[s])
@@ -536,19 +565,22 @@ __device__ __forceinline__ void solve_ir(const SolveArgs& a, Shared<T>& sh,
       status = BT_EBREAKDOWN;
       break;
     }
-    // x64 += L^{-T} dhat
+    // x64 += L^{-T} dhat (undoing the scale)
     const T* ds = op.stage(d);
+    ++op.ntr;
 #pragma unroll
     for (int s = 0; s < S; ++s)
       if (in.act[s])
-        x64[s] += (double)apply_lowerT<T>(in.Li, ds, in.n, in.k[s], in.i[s]);
+        x64[s] += (double)apply_lowerT<T>(in.Li, ds, in.n, in.k[s], in.i[s]) *
+                  unscale;
   }
 
 #pragma unroll
   for (int s = 0; s < S; ++s)
     if (in.act[s]) x[in.pidx(s)] = x64[s];
   write_info(info, status, total, outer, -1, sqrt(nr2 / nb2),
-             sqrt(nr2 / nb2));
+             sqrt(nr2 / nb2), op.gemv_exec(),
+             (int64_t)total * bt_gemv_g(a.pc, a.a, a.m));
 }
 
 // ------------------------------------------------------------------------

@@ -110,6 +110,9 @@ struct Ctx {
   int k, N;          // row within the system, system length (0: idle lane)
   bool row_ok;       // a real block row (not padding, not idle)
   int sf, sd, seen;
+  // what the system executed: halves of applications of C, triangular
+  // transforms, float64 residuals (uniform over the system's lanes)
+  int nh, ntr, nrs;
   float Fr[EPT][NB]; // own rows of F_k, columns in lane order
 
   __device__ Ctx(Smem<NB, EPT>& s) : sm(s) {}
@@ -138,6 +141,7 @@ struct Ctx {
 
   template <int BUF>
   __device__ __forceinline__ void prep(const float (&v)[EPT]) {
+    ++nh;
     float S[EPT];
     if constexpr (G::TPR == 8) {
       // Partner q xor 7 (mirror inside the 8-lane half row), then xor 2, then
@@ -185,6 +189,7 @@ struct Ctx {
 
   template <int BUF>
   __device__ __forceinline__ void finish(float (&y)[EPT]) {
+    ++nh;
     const int rp = k < N - 1 ? lrow + 1 : lrow;
     const float* vr = &sm.V[BUF][rp * G::ROW];
     float acc[EPT];
@@ -440,6 +445,10 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
     const double tol2 = a.tol * a.tol * nb2;
     int outer = 0, total = 0;
     double nr2 = nb2;
+    double unscale = 1.0;  // 1 / the scale of the current inner solve
+    c.nh = 0;
+    c.ntr = 0;
+    c.nrs = 0;
     if (a.warm) {  // initial guess x0 (held in x on entry) of running systems
       if (!done && c.row_ok) {
 #pragma unroll
@@ -450,9 +459,11 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
     }
 
     for (;;) {
-      // float64 residual of the record for the current iterate
+      // float64 residual of the record for the current iterate, scaled by
+      // a power of two to norm in [1, 2) before the float32 inner solve
       float r64f[EPT];
       {
+        double r64v[EPT];
         double rp = 0.0;
         const double* xk = sm.xs + c.lrow * NB;
 #pragma unroll 1
@@ -485,10 +496,17 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
             r64 = a.b[g * NB + i] - acc;
           }
           rp += r64 * r64;
-          r64f[e] = (float)r64;
+          r64v[e] = r64;
         }
         const double s = c.sumd(rp);  // its barrier also orders xs reads
-        if (!done && (outer > 0 || a.warm)) nr2 = s;
+        if (!done && (outer > 0 || a.warm)) {
+          nr2 = s;
+          ++c.nrs;
+        }
+        const double sc = bt_unit_scale(nr2);
+        unscale = 1.0 / sc;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) r64f[e] = (float)(r64v[e] * sc);
       }
       if (!done) {
         if (nr2 <= tol2) {
@@ -509,6 +527,7 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
         c.put_flag(!done);
         __syncthreads();
         if (!c.any_after_barrier()) break;  // every system of the bin is done
+        if (!done) ++c.ntr;
         const float* rk = &sm.V[0][c.lrow * G::ROW];
 #pragma unroll 1
         for (int e = 0; e < EPT; ++e) {
@@ -615,9 +634,10 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
                   acc = __fmaf_rn(
                       lc[PK ? jj * (jj + 1) / 2 : jj * NB],
                       dk[spos(jj)], acc);
-              sm.xs[c.lrow * NB + i] += (double)acc;
+              sm.xs[c.lrow * NB + i] += (double)acc * unscale;
             }
           }
+          ++c.ntr;
           ++outer;
           if (inner == 0) {
             status = BT_EBREAKDOWN;
@@ -642,6 +662,8 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
       const double rr = nb2 > 0.0 ? sqrt(nr2 / nb2) : 0.0;
       inf->relres = status == BT_ENOTSPD ? NAN : rr;
       inf->relres_true = status == BT_ENOTSPD ? NAN : rr;
+      inf->gemv_exec = bt_gemv_rows(c.N, c.nh, c.ntr, c.nrs);
+      inf->gemv_paper = (int64_t)total * bt_gemv_g(a.pc, a.a, a.m);
     }
     __syncthreads();
   }

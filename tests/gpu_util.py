@@ -55,6 +55,38 @@ def rel(a, b):
                  max(np.linalg.norm(np.asarray(b)), 1e-300))
 
 
+def rowmax_rel(a, b, n=None):
+    """Largest error of one block row: ||a_k - b_k|| over the larger of
+    ||b_k|| and the root-mean-square block-row norm of b. A wrong block row
+    (a short tail, one instance of a batch) shows here even when the global
+    relative norm hides it."""
+    b = np.asarray(b, dtype=np.float64)
+    n = n or b.shape[-1]
+    a = np.asarray(a, dtype=np.float64).reshape(-1, n)
+    b = b.reshape(-1, n)
+    e = np.linalg.norm(a - b, axis=1)
+    nb = np.linalg.norm(b, axis=1)
+    rms = max(float(np.sqrt(np.mean(nb ** 2))), 1e-300)
+    return float(np.max(e / np.maximum(nb, rms)))
+
+
+def assert_close(a, b, tol, what=""):
+    """Global relative error and largest block-row error both within tol."""
+    g, r = rel(a, b), rowmax_rel(a, b)
+    assert g <= tol and r <= tol, (what, "global", g, "row max", r, "tol", tol)
+
+
+def true_relres(D, O, b, x):
+    """||b - A x|| / ||b|| in float64 with the oracle's product."""
+    r = np.asarray(b) - orc.spmv(D, O, np.asarray(x).reshape(np.shape(b)))
+    return float(np.linalg.norm(r) / max(np.linalg.norm(b), 1e-300))
+
+
+# float64 solves stop on the recursive residual at tol; the true residual of
+# the returned x may drift above it by rounding: 1 % is allowed
+F64_TRUE_RES = 1.01e-10
+
+
 def workload(name, instances=None):
     """Synthetic inputs of a standard workload (optionally a subset of the
     instances of a batch, drawn with the same per-instance seeds)."""

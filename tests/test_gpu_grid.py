@@ -14,7 +14,8 @@ import pytest
 import lqrgen
 import oracle as orc
 import paper_2503_15269_amd as bt
-from gpu_util import iteration_match, oracle_kind, rel, to_dev, workload
+from gpu_util import (F64_TRUE_RES, assert_close, iteration_match, oracle_kind,
+                      rel, to_dev, true_relres, workload)
 
 pytestmark = pytest.mark.gpu
 
@@ -69,11 +70,13 @@ def test_grid_f64_matches_oracle(N, n, name):
     slack = max(2, 3 * ri["iters"] // 100) if P.pc == "none" else 0
     assert iteration_match(int(info[0]["iters"]), ri, slack=slack), (info, ri)
     if info[0]["iters"] == ri["iters"]:
-        assert rel(x, xr) <= 1e-10, rel(x, xr)
+        assert_close(x, xr, 1e-10, "against the oracle's PCG iterate")
     else:  # both converged iterates agree to the conditioning bound
-        assert rel(x, orc.btchol_solve(d["D"], d["O"], d["b"])) <= 1e-6
+        assert_close(x, orc.btchol_solve(d["D"], d["O"], d["b"]), 1e-6,
+                     "against the direct solve")
     assert info[0]["relres"] <= 1e-10
-    assert info[0]["relres_true"] <= 1e-9
+    assert info[0]["relres_true"] <= F64_TRUE_RES
+    assert true_relres(d["D"], d["O"], d["b"], x) <= F64_TRUE_RES
 
 
 @pytest.mark.parametrize("name", ["polycoeff_m2", "jacobi_m2"])
@@ -100,8 +103,9 @@ def test_grid_f32_refinement(record):
     assert info[0]["status"] == bt.OK, info
     assert info[0]["relres_true"] <= 1e-10
     assert info[0]["outer"] >= 2
+    assert true_relres(D, O, d["b"], x) <= F64_TRUE_RES
     xd = orc.btchol_solve(D, O, d["b"])
-    assert rel(x, xd) <= 1e-5, rel(x, xd)
+    assert_close(x, xd, 1e-5, "against the direct solve")
 
 
 def test_grid_above_single_workgroup_capacity():
@@ -111,9 +115,10 @@ def test_grid_above_single_workgroup_capacity():
     P = bt.Params.polycoeff(2)
     x, info, h = grid_solve(d["D"], d["O"], d["b"], P)
     assert info[0]["status"] == bt.OK, info
-    assert info[0]["relres_true"] <= 1e-9
+    assert info[0]["relres_true"] <= F64_TRUE_RES
+    assert true_relres(d["D"], d["O"], d["b"], x) <= F64_TRUE_RES
     xd = orc.btchol_solve(d["D"], d["O"], d["b"])
-    assert rel(x, xd) <= 1e-8
+    assert_close(x, xd, 1e-8, "against the direct solve")
     with pytest.raises(bt.BtError):
         h.solve(to_dev(d["b"].reshape(-1), torch.float64), 1e-10)
 
@@ -131,7 +136,9 @@ def test_grid_n48_blocks_read_from_memory(prec):
     P = bt.Params.polycoeff(2, prec=prec)
     x, info, _ = grid_solve(D, O, d["b"], P, record=record)
     assert info[0]["status"] == bt.OK, info
-    assert info[0]["relres_true"] <= (1e-10 if prec == "f32_ir" else 1e-9)
+    assert info[0]["relres_true"] <= (1e-10 if prec == "f32_ir"
+                                      else F64_TRUE_RES)
+    assert true_relres(D, O, d["b"], x) <= F64_TRUE_RES
     xd = orc.btchol_solve(D, O, d["b"])
     assert rel(x, xd) <= 1e-6, rel(x, xd)
     if prec == "f64":

@@ -7,7 +7,7 @@ import pytest
 import lqrgen
 import oracle as orc
 import paper_2503_15269_amd as bt
-from gpu_util import to_dev
+from gpu_util import rowmax_rel, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -44,6 +44,8 @@ def check(D, O, B, X, info, tol=1e-10, err_bound=2e-5, cols=None):
         assert np.linalg.norm(r) <= 1.01 * tol * np.linalg.norm(B[:, :, c]), c
         err = np.linalg.norm(X[:, :, c] - Xd[:, :, c]) / np.linalg.norm(Xd[:, :, c])
         assert err <= err_bound, (c, err)
+        row = rowmax_rel(X[:, :, c], Xd[:, :, c])
+        assert row <= err_bound, (c, "row max", row)
 
 
 @pytest.mark.parametrize("m", [1, 2])
@@ -83,3 +85,21 @@ def test_mrhs_argument_checks():
     h2 = bt.Handle(Dt, Ot, None, bt.Params.polycoeff(2, prec="bf16x2_ir"))
     with pytest.raises(bt.BtError):
         h2.solve_mrhs(B[:, :, :32].contiguous())   # nrhs not a multiple of 64
+
+
+@pytest.mark.parametrize("scale", [1e-14, 1e18])
+def test_mrhs_scaled_columns(scale):
+    """Columns far from unit scale: the float32 inner solves see each
+    column's residual scaled to unit norm, so tiny and huge right-hand sides
+    converge like unit ones."""
+    import torch
+    d = lqrgen.lqr_instance(40, 48, 16, 31, 0, s=0.05, nrhs=64)
+    D = d["D"].astype(np.float32).astype(np.float64)
+    O = d["O"].astype(np.float32).astype(np.float64)
+    B = d["b"].copy()
+    B[:, :, ::2] *= scale   # every other column scaled
+    h = bt.Handle(to_dev(D, torch.float32), to_dev(O, torch.float32), None,
+                  bt.Params.polycoeff(2, prec="bf16x2_ir", inner_tol=1e-4))
+    X, info = h.solve_mrhs(to_dev(B, torch.float64), 1e-10)
+    torch.cuda.synchronize()
+    check(D, O, B, X.cpu().numpy(), bt.infos_to_numpy(info))

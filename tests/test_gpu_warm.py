@@ -12,7 +12,8 @@ import pytest
 import lqrgen
 import oracle as orc
 import paper_2503_15269_amd as bt
-from gpu_util import iteration_match, oracle_kind, rel, to_dev
+from gpu_util import (F64_TRUE_RES, assert_close, iteration_match, oracle_kind,
+                      rel, to_dev, true_relres)
 
 pytestmark = pytest.mark.gpu
 
@@ -73,8 +74,9 @@ def test_f64_from_x0_matches_oracle(N, n, name, path):
             (which, info)
         assert iteration_match(int(info[0]["iters"]), ri), (which, info, ri)
         if info[0]["iters"] == ri["iters"]:
-            assert rel(x, xr) <= 1e-10, (which, rel(x, xr))
-        assert info[0]["relres_true"] <= 1e-9
+            assert_close(x, xr, 1e-10, which)
+        assert info[0]["relres_true"] <= F64_TRUE_RES
+        assert true_relres(d["D"], d["O"], d["b"], x) <= F64_TRUE_RES
     # a cold start needs more iterations than the near one
     _, ri0 = orc.pcg(d["D"], d["O"], d["b"], tol=1e-10, **oracle_kind(P))
     _, rin = orc.pcg(d["D"], d["O"], d["b"], tol=1e-10,
@@ -95,7 +97,8 @@ def test_f64_batch_from_x0_matches_oracle():
         assert info[i]["status"] == bt.OK
         assert iteration_match(int(info[i]["iters"]), ri), (i, info[i], ri)
         if info[i]["iters"] == ri["iters"]:
-            assert rel(x[rows], xr) <= 1e-10
+            assert_close(x[rows], xr, 1e-10, i)
+        assert true_relres(D, O, b, x[rows]) <= F64_TRUE_RES
 
 
 @pytest.mark.parametrize("path", ["fast", "generic", "grid"])
