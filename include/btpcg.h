@@ -268,6 +268,25 @@ int bt_solve_grid(const bt_handle* h, const double* b, double* x, double tol,
                   int maxit, bt_info* info, void* scratch,
                   size_t scratch_bytes, void* stream);
 
+/* bt_solve_grid for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same solve, kernels and results as bt_solve_grid, but the scratch is
+ * a static device array the library holds, BT_GRID_NOALLOC_MAX_BYTES per GPU
+ * (allocated with the library's code object on each GPU it runs on, kept
+ * until the process ends), instead of a workspace argument. The call
+ * allocates no device memory. A system whose grid scratch
+ * (bt_grid_workspace_bytes) exceeds the maximum is refused with BT_ENOSPACE
+ * before any work is enqueued (float64: about 130 000 unknowns N n, float32
+ * and refinement: about 230 000). Every call on one GPU shares that GPU's
+ * array: calls that overlap on one GPU (two host threads, or two streams
+ * in flight) race. The current device must be the one the stream belongs
+ * to. Like bt_solve_grid it synchronises with the stream and is not
+ * capturable. Errors: as bt_solve_grid, plus BT_ENOSPACE for a system above
+ * the maximum. */
+#define BT_GRID_NOALLOC_MAX_BYTES ((size_t)8 << 20)
+int bt_solve_grid_noalloc(const bt_handle* h, const double* b, double* x,
+                          double tol, int maxit, bt_info* info, void* stream);
+
 /* Kernel configurations for the solve (workgroup size x vector elements per
  * thread), for the autotuner. bt_kernel_config_count() entries; entry i has
  * threads nt[i], elements per thread s[i] and iteration precision prec[i].

@@ -79,6 +79,7 @@ def load_library(path: str = LIB_PATH):
         "bt_solve_mrhs": (I, [P, I, P, P, Dd, I, P, P, Sz, P]),
         "bt_grid_workspace_bytes": (Sz, [P]),
         "bt_solve_grid": (I, [P, P, P, Dd, I, P, P, Sz, P]),
+        "bt_solve_grid_noalloc": (I, [P, P, P, Dd, I, P, P]),
         "bt_kernel_config_count": (I, []),
         "bt_kernel_config": (I, [I, ctypes.POINTER(I), ctypes.POINTER(I),
                                  ctypes.POINTER(I)]),
@@ -102,6 +103,7 @@ def exported_symbols():
             "bt_mrhs_workspace_bytes", "bt_solve_mrhs",
             "bt_direct_workspace_bytes", "bt_solve_direct",
             "bt_grid_workspace_bytes", "bt_solve_grid",
+            "bt_solve_grid_noalloc",
             "bt_kernel_config_count", "bt_kernel_config",
             "bt_set_kernel_config", "bt_get_kernel_config", "bt_destroy"]
 
@@ -405,6 +407,25 @@ class Handle:
                                  int(maxit), _ptr(info), _ptr(scratch),
                                  scratch.numel(), _stream(torch, stream)),
                "bt_solve_grid")
+        return x, info
+
+    def solve_grid_noalloc(self, b, tol=1e-10, maxit=None, x=None,
+                           info=None, stream=None):
+        """bt_solve_grid with the library's own static scratch instead of a
+        workspace (bt_solve_grid_noalloc): no device allocation in the
+        library. ``x`` and ``info`` may be passed in so that the call
+        allocates nothing on the torch side either. Returns (x, info)."""
+        torch = _torch()
+        b = self._vec(b, "b")
+        x = self._start(x, b)
+        if info is None:
+            info = torch.empty(INFO_DTYPE.itemsize, dtype=torch.uint8,
+                               device=self.device)
+        if maxit is None:
+            maxit = self.default_maxit()
+        _check(load_library().bt_solve_grid_noalloc(
+            self._h, _ptr(b), _ptr(x), float(tol), int(maxit), _ptr(info),
+            _stream(torch, stream)), "bt_solve_grid_noalloc")
         return x, info
 
     def precondition(self, r, z=None, stream=None):

@@ -514,6 +514,18 @@ int bt_solve_grid(const bt_handle* h, const double* b, double* x, double tol,
   return bt_grid_solve(h, b, x, tol, maxit, info, scratch, s);
 }
 
+int bt_solve_grid_noalloc(const bt_handle* h, const double* b, double* x,
+                          double tol, int maxit, bt_info* info, void* stream) {
+  if (!h || h->B != 1) return BT_EINVAL;
+  const size_t need = bt_grid_scratch_bytes(h);
+  if (need == 0) return BT_EINVAL;
+  if (need > BT_GRID_NOALLOC_MAX_BYTES) return BT_ENOSPACE;
+  void* ws = nullptr;
+  if (bt_grid_static_scratch(&ws) != hipSuccess || !ws) return BT_EHIP;
+  return bt_solve_grid(h, b, x, tol, maxit, info, ws,
+                       BT_GRID_NOALLOC_MAX_BYTES, stream);
+}
+
 int bt_kernel_config_count(void) { return num_configs(); }
 
 int bt_kernel_config(int i, int* nt, int* s, int* prec) {

@@ -14,4 +14,8 @@ size_t bt_grid_scratch_bytes(const bt_handle* h);
 // PCG for the single system of ``h`` with every step a kernel over all block
 // rows; host-driven (synchronises with the stream every few iterations).
 int bt_grid_solve(const bt_handle* h, const double* b, double* x, double tol,
-                  int maxit, bt_info* info, void* scratch, hipStream_t s);
+                  int maxit, bt_info* info, void* ws, hipStream_t s);
+
+// Device address of the library's own grid scratch array on the current
+// device (BT_GRID_NOALLOC_MAX_BYTES), looked up once per device.
+hipError_t bt_grid_static_scratch(void** out);

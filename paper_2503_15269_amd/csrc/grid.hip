@@ -31,7 +31,7 @@
 
 #include <algorithm>
 #include <cmath>
-#include <vector>
+#include <mutex>
 
 #include "grid.h"
 #include "internal.h"
@@ -50,6 +50,9 @@ enum { P_RHO0 = 0, P_RHO1 = 1, P_SIG = 2, P_NR2 = 3, P_NB2 = 4, P_RES = 5,
 struct Ctl {
   int status;  // BT_NOT_CONVERGED while the (inner) iteration runs
   int it;      // PCG steps of this (inner) solve
+  // sums of the partial slots P_NB2, P_RES, P_NR2 (k_g_sums), read by the
+  // host after the last kernel of a solve or refinement step
+  double nb2, res, nr2;
 };
 
 template <typename T>
@@ -557,6 +560,19 @@ __global__ void __launch_bounds__(NT) k_g_res(GArgs<T> a) {
   put_partial(a, P_NB2, b2, red);
 }
 
+// Sums of the partial slots the host needs (fixed order, one workgroup).
+template <typename T>
+__global__ void __launch_bounds__(NT) k_g_sums(GArgs<T> a) {
+  extern __shared__ double red[];
+  double S[3];
+  slot_sums<3>(a.part, {P_NB2, P_RES, P_NR2}, a.nwg, red, S);
+  if (threadIdx.x == 0) {
+    a.ctl->nb2 = S[0];
+    a.ctl->res = S[1];
+    a.ctl->nr2 = S[2];
+  }
+}
+
 template <typename T>
 struct Plan {
   GArgs<T> a;
@@ -603,7 +619,7 @@ hipError_t set_lds(size_t lds) {
   if (lds <= 65536) return hipSuccess;
   const void* fns[] = {(const void*)k_g_init<T>, (const void*)k_g_q<T>,
                        (const void*)k_g_u<T>, (const void*)k_g_x<T>,
-                       (const void*)k_g_res<T>};
+                       (const void*)k_g_res<T>, (const void*)k_g_sums<T>};
   for (const void* f : fns) {
     const hipError_t e = hipFuncSetAttribute(
         f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -614,7 +630,7 @@ hipError_t set_lds(size_t lds) {
 
 template <typename T>
 int run(const bt_handle* h, const double* b, double* x, double tol, int maxit,
-        bt_info* info, void* scratch, hipStream_t s) {
+        bt_info* info, void* ws, hipStream_t s) {
   const int64_t R = h->R;
   const int n = h->n;
   Plan<T> pl{};
@@ -641,7 +657,7 @@ int run(const bt_handle* h, const double* b, double* x, double tol, int maxit,
   a.b = b;
   a.x = x;
   const size_t v = (size_t)R * n;
-  T* f = (T*)scratch;
+  T* f = (T*)ws;
   a.pb[0] = f;
   a.pb[1] = f + v;
   a.rbuf[0] = f + 2 * v;
@@ -650,9 +666,9 @@ int run(const bt_handle* h, const double* b, double* x, double tol, int maxit,
   a.z = f + 5 * v;
   a.xh = f + 6 * v;
   const Scratch<T> sl(R, n);
-  a.r64 = (double*)((unsigned char*)scratch + sl.r64);
-  a.part = (double*)((unsigned char*)scratch + sl.part);
-  a.ctl = (Ctl*)((unsigned char*)scratch + sl.ctl);
+  a.r64 = (double*)((unsigned char*)ws + sl.r64);
+  a.part = (double*)((unsigned char*)ws + sl.part);
+  a.ctl = (Ctl*)((unsigned char*)ws + sl.ctl);
   pl.grid = a.nwg;
   pl.lds = NT * sizeof(double) +
            5 * (size_t)wlen(a.rb, a.depth, n) * sizeof(T);
@@ -660,21 +676,17 @@ int run(const bt_handle* h, const double* b, double* x, double tol, int maxit,
   if (fb <= FSTAGE_MAX) pl.lds += fb;
   if (set_lds<T>(pl.lds) != hipSuccess) return BT_EHIP;
 
-  std::vector<double> hp((size_t)P_SLOTS * a.nwg);
   Ctl ctl{};
+  // parts: first sum the partial slots on the device (k_g_sums)
   auto sync_state = [&](bool parts) -> bool {
+    if (parts && launch(k_g_sums<T>, pl, s) != hipSuccess) return false;
     if (hipMemcpyAsync(&ctl, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s) !=
         hipSuccess)
-      return false;
-    if (parts && hipMemcpyAsync(hp.data(), a.part, hp.size() * sizeof(double),
-                                hipMemcpyDeviceToHost, s) != hipSuccess)
       return false;
     return hipStreamSynchronize(s) == hipSuccess;
   };
   auto host_slot = [&](int slot) {
-    double t = 0.0;
-    for (int i = 0; i < a.nwg; ++i) t += hp[(size_t)slot * a.nwg + i];
-    return t;
+    return slot == P_NB2 ? ctl.nb2 : slot == P_RES ? ctl.res : ctl.nr2;
   };
   // inner loop: steps until the control block is settled or ``cap`` steps.
   // The first check comes after as many steps as the last inner solve on
@@ -855,8 +867,42 @@ size_t bt_grid_scratch_bytes(const bt_handle* h) {
 }
 
 int bt_grid_solve(const bt_handle* h, const double* b, double* x, double tol,
-                  int maxit, bt_info* info, void* scratch, hipStream_t s) {
+                  int maxit, bt_info* info, void* ws, hipStream_t s) {
   if (h->p.prec == BT_F64)
-    return btg::run<double>(h, b, x, tol, maxit, info, scratch, s);
-  return btg::run<float>(h, b, x, tol, maxit, info, scratch, s);
+    return btg::run<double>(h, b, x, tol, maxit, info, ws, s);
+  return btg::run<float>(h, b, x, tol, maxit, info, ws, s);
+}
+
+// ---------------------------------------------------------------------------
+// Scratch held by the library for bt_solve_grid_noalloc (callers that cannot
+// allocate device memory). One array per GPU the library runs on, kept until
+// the process ends. On the host the array's name is only a stand-in, never
+// a device address: host code uses the address that hipGetSymbolAddress
+// returns for the current device, taken once per device and kept below.
+// Every call on a GPU shares that GPU's array (calls that overlap on one GPU
+// race); the grid kernels initialise everything they read before reading it
+// (control block in k_g_init, partial slots before their sums, p and the
+// correction at step 0), so nothing has to start at zero.
+static __device__ __align__(256) unsigned char scratch[BT_GRID_NOALLOC_MAX_BYTES];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_addr[64];  // per device ordinal
+}  // namespace
+
+hipError_t bt_grid_static_scratch(void** out) {
+  *out = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return hipSuccess;
 }

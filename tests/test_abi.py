@@ -154,6 +154,8 @@ def test_setup_rejects_before_touching_memory(lib):
     assert lib.bt_solve_grid(None, bogus, bogus, 1e-10, 10, bogus, bogus,
                              1 << 20, None) == bt.EINVAL
     assert lib.bt_grid_workspace_bytes(None) == 0
+    assert lib.bt_solve_grid_noalloc(None, bogus, bogus, 1e-10, 10, bogus,
+                                     None) == bt.EINVAL
 
 
 def test_kernel_configs_listed(lib):
