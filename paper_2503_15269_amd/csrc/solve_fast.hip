@@ -86,6 +86,31 @@ __device__ __forceinline__ double uni(double v) {
                               (long long)(unsigned int)lo);
 }
 
+// One block row of NB entries from a 16-byte aligned address (16-byte
+// loads).
+template <int NB, typename T>
+__device__ __forceinline__ void load_row(const T* src, T (&v)[NB]) {
+  if constexpr (sizeof(T) == 4) {
+    static_assert(NB % 4 == 0, "whole 16-byte chunks");
+#pragma unroll
+    for (int c = 0; c < NB / 4; ++c) {
+      const float4 t = reinterpret_cast<const float4*>(src)[c];
+      v[4 * c] = t.x;
+      v[4 * c + 1] = t.y;
+      v[4 * c + 2] = t.z;
+      v[4 * c + 3] = t.w;
+    }
+  } else {
+    static_assert(NB % 2 == 0, "whole 16-byte chunks");
+#pragma unroll
+    for (int c = 0; c < NB / 2; ++c) {
+      const double2 t = reinterpret_cast<const double2*>(src)[c];
+      v[2 * c] = t.x;
+      v[2 * c + 1] = t.y;
+    }
+  }
+}
+
 template <int NB, int EPT>
 struct Smem {
   using G = Geo<NB, EPT>;
@@ -127,6 +152,106 @@ struct Ctx {
 
   __device__ __forceinline__ int col(int x) const {  // lane-order column
     return EPT * ((x / EPT) ^ q) + x % EPT;
+  }
+
+  // Sum partial column sums P (lane column order, one per column of the
+  // row's block) over the TPR lanes of the row; lane q receives the sums of
+  // its own columns EPT q .. EPT q + EPT - 1. Every lane must take part.
+  template <typename T>
+  __device__ __forceinline__ void rscatter(const T (&P)[NB], T (&S)[EPT]) const {
+    static_assert(G::TPR <= 4, "1, 2 or 4 lanes per block row");
+    if constexpr (G::TPR == 4) {
+      T K[2 * EPT];
+#pragma unroll
+      for (int y = 0; y < 2 * EPT; ++y)
+        K[y] = P[y] + btk::dpp<btk::DPP_QUAD_2301>(P[2 * EPT + y]);
+#pragma unroll
+      for (int z = 0; z < EPT; ++z)
+        S[z] = K[z] + btk::dpp<btk::DPP_QUAD_1032>(K[EPT + z]);
+    } else if constexpr (G::TPR == 2) {
+#pragma unroll
+      for (int z = 0; z < EPT; ++z)
+        S[z] = P[z] + btk::dpp<btk::DPP_QUAD_1032>(P[EPT + z]);
+    } else {
+#pragma unroll
+      for (int z = 0; z < EPT; ++z) S[z] = P[z];
+    }
+  }
+
+  // Natural column order -> lane column order (chunk cc of EPT entries
+  // takes natural chunk cc xor q), one bit of q at a time with selects; the
+  // map is its own inverse.
+  template <typename T>
+  __device__ __forceinline__ void to_lane_order(T (&v)[NB]) const {
+    if constexpr (G::TPR >= 2) {
+      const bool b0 = (q & 1) != 0;
+#pragma unroll
+      for (int cc = 0; cc < G::TPR; cc += 2)
+#pragma unroll
+        for (int z = 0; z < EPT; ++z) {
+          const T u = v[EPT * cc + z], w = v[EPT * (cc + 1) + z];
+          v[EPT * cc + z] = b0 ? w : u;
+          v[EPT * (cc + 1) + z] = b0 ? u : w;
+        }
+    }
+    if constexpr (G::TPR >= 4) {
+      const bool b1 = (q & 2) != 0;
+#pragma unroll
+      for (int cc = 0; cc < G::TPR; cc += 4)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int z = 0; z < EPT; ++z) {
+            const T u = v[EPT * (cc + h) + z], w = v[EPT * (cc + h + 2) + z];
+            v[EPT * (cc + h) + z] = b1 ? w : u;
+            v[EPT * (cc + h + 2) + z] = b1 ? u : w;
+          }
+    }
+    static_assert(G::TPR <= 4, "1, 2 or 4 lanes per block row");
+  }
+
+  // Own rows EPT q .. EPT q + EPT - 1 of F_k into registers, lane column
+  // order (zero for the last row of a system, which has no F_k): 16-byte
+  // loads of the contiguous rows, then the chunk permutation.
+  __device__ __forceinline__ void load_F(const float* F, int64_t g) {
+    const bool has_next = row_ok && k < N - 1;
+    const float keep = has_next ? 1.f : 0.f;
+    const float* fk = F + (size_t)(has_next ? g : 0) * NB * NB +
+                      (size_t)q * EPT * NB;  // always valid
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      load_row(fk + e * NB, Fr[e]);
+#pragma unroll
+      for (int x = 0; x < NB; ++x) Fr[e][x] *= keep;
+      to_lane_order(Fr[e]);
+    }
+  }
+
+  // Own rows i = EPT q + e of L_k^{-1} (natural column order, zero above the
+  // diagonal), from the full blocks or the packed lower triangles. A packed
+  // row is read as NB consecutive entries from its start (past its end they
+  // belong to the next rows or the padding of the same block) and masked.
+  template <bool PK>
+  __device__ __forceinline__ void load_li_rows(const float* Li, int64_t g,
+                                               float (&Lv)[EPT][NB]) const {
+    constexpr size_t LP = li_packed_len(NB);
+    if constexpr (PK) {
+      const int i0 = q * EPT;
+      const float* base = Li + (size_t)g * LP + (size_t)(i0 * (i0 + 1) / 2);
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        const float* row = base + e * i0 + e * (e + 1) / 2;
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          const float v = row[j];
+          Lv[e][j] = j <= i0 + e ? v : 0.f;
+        }
+      }
+    } else {
+      const float* base = Li + (size_t)g * NB * NB + (size_t)q * EPT * NB;
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) load_row(base + e * NB, Lv[e]);
+    }
   }
 
   // ---- one application of C in two halves around a barrier -------------
@@ -402,23 +527,6 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
     const int64_t g = sys ? a.off[inst] + c.k : 0;  // global block row
     const int64_t ob = g - inst;                     // its upper block
 
-    // ---- own rows of F_k into registers, lane column order ----------------
-    {
-      const bool has_next = c.row_ok && c.k < c.N - 1;
-      const float keep = has_next ? 1.f : 0.f;
-      const float* fk = F + (size_t)(has_next ? g : 0) * nn;  // always valid
-#pragma unroll
-      for (int e = 0; e < EPT; ++e) {
-        const float* row = fk + (size_t)(c.q * EPT + e) * NB;
-#pragma unroll
-        for (int cc = 0; cc < G::TPR; ++cc) {
-          const int src = EPT * (cc ^ c.q);
-#pragma unroll
-          for (int z = 0; z < EPT; ++z) c.Fr[e][EPT * cc + z] = keep * row[src + z];
-        }
-      }
-    }
-
     // ---- per-system state ----------------------------------------------
     const int fail = sys ? a.fail[inst] : BT_NO_FAIL;
     const int e0 = c.q * EPT;
@@ -458,48 +566,124 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
       __syncthreads();  // neighbour rows of xs are read by the residual
     }
 
+    // Refinement loop. F_k lives in registers only during an inner solve;
+    // the residual and the two transforms in between use those registers to
+    // issue all of a lane's loads at once (wide, row-contiguous), and the
+    // transposed products O_k^T x_k and L_k^{-T} d are formed as partial
+    // column sums over the lane's own rows, summed across the row's lanes
+    // with DPP (the hand-off that F_k^T uses).
+    float d[EPT];   // correction of the last inner solve (scaled coordinates)
+    bool ran = false;  // an inner solve ran since the last correction
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) d[e] = 0.f;
+    const Rec* Dg = (const Rec*)a.D + (size_t)g * nn + (size_t)e0 * NB;
+    const bool has_next = c.row_ok && c.k < c.N - 1;
     for (;;) {
-      // float64 residual of the record for the current iterate, scaled by
-      // a power of two to norm in [1, 2) before the float32 inner solve
+      // ---- x64 += L^{-T} d (undoing the scale) ------------------------
+      {
+        float P[NB];  // column sums over the lane's rows, natural order
+#pragma unroll
+        for (int x = 0; x < NB; ++x) P[x] = 0.f;
+        if (ran && c.row_ok) {
+          float Lv[EPT][NB];
+          c.template load_li_rows<PK>(Li, g, Lv);
+#pragma unroll
+          for (int e = 0; e < EPT; ++e)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) P[j] = __fmaf_rn(Lv[e][j], d[e], P[j]);
+        }
+        c.to_lane_order(P);
+        float S[EPT];
+        c.rscatter(P, S);
+        if (ran) {
+          if (c.row_ok) {
+#pragma unroll
+            for (int e = 0; e < EPT; ++e)
+              sm.xs[c.lrow * NB + e0 + e] += (double)S[e] * unscale;
+          }
+          ++c.ntr;
+          ++outer;
+          ran = false;
+        }
+        __syncthreads();  // xs complete before the residual reads it
+      }
+
+      // ---- float64 residual of the record, scaled by a power of two to
+      // norm in [1, 2) before the float32 inner solve ----------------------
       float r64f[EPT];
       {
-        double r64v[EPT];
-        double rp = 0.0;
+        const bool need = !done && (outer > 0 || a.warm);  // wave-uniform
         const double* xk = sm.xs + c.lrow * NB;
-#pragma unroll 1
+        double acc[EPT];
+        double P[NB];  // column sums of O_k^T x_k over own rows, natural
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) acc[e] = 0.0;
+#pragma unroll
+        for (int x = 0; x < NB; ++x) P[x] = 0.0;
+        if (need && c.row_ok) {
+          // rows e0 .. e0 + EPT - 1 of D_k and O_k, 16-byte loads, in
+          // batches of RB rows issued before their sums
+          constexpr int RB = sizeof(Rec) == 4 ? 3 : 1;
+          static_assert(EPT % RB == 0, "whole batches");
+          const double* xn = sm.xs + (c.lrow + 1) * NB;
+#pragma unroll
+          for (int e1 = 0; e1 < EPT; e1 += RB) {
+            Rec Dv[RB][NB], Ov[RB][NB];
+#pragma unroll
+            for (int e = 0; e < RB; ++e) load_row(Dg + (e1 + e) * NB, Dv[e]);
+            if (has_next) {
+              const Rec* Og = (const Rec*)a.O + (size_t)ob * nn + (size_t)e0 * NB;
+#pragma unroll
+              for (int e = 0; e < RB; ++e) load_row(Og + (e1 + e) * NB, Ov[e]);
+            }
+#pragma unroll
+            for (int e = 0; e < RB; ++e)
+#pragma unroll
+              for (int j = 0; j < NB; ++j)
+                acc[e1 + e] += (double)Dv[e][j] * xk[j];
+            if (has_next) {
+#pragma unroll
+              for (int e = 0; e < RB; ++e) {
+                const double xo = xk[e0 + e1 + e];
+#pragma unroll
+                for (int j = 0; j < NB; ++j) {
+                  const double o = (double)Ov[e][j];
+                  acc[e1 + e] += o * xn[j];
+                  P[j] += o * xo;
+                }
+              }
+            }
+          }
+        }
+        // O_k^T x_k to the lanes of row k + 1 (float64 through the T area)
+        double* Td = reinterpret_cast<double*>(&sm.T[0][0]);
+        {
+          c.to_lane_order(P);
+          double S[EPT];
+          c.rscatter(P, S);
+#pragma unroll
+          for (int e = 0; e < EPT; ++e) Td[c.lrow * NB + e0 + e] = S[e];
+        }
+        __syncthreads();
+        double rp = 0.0;
+        double r64v[EPT];
+#pragma unroll
         for (int e = 0; e < EPT; ++e) {
           double r64 = 0.0;
           if (c.row_ok && !done) {
-            const int i = e0 + e;
-            double acc = 0.0;
-            if (outer > 0 || a.warm) {
-              const size_t db = (size_t)g * nn + (size_t)i * NB;
-#pragma unroll
-              for (int jj = 0; jj < NB; ++jj)
-                acc += (double)((const Rec*)a.D)[db + jj] * xk[jj];
-              if (c.k < c.N - 1) {
-                const size_t o = (size_t)ob * nn + (size_t)i * NB;
-#pragma unroll
-                for (int jj = 0; jj < NB; ++jj)
-                  acc += (double)((const Rec*)a.O)[o + jj] * xk[NB + jj];
-              }
-              if (c.k > 0) {
-                // column i of O_{k-1}: all loads issued before the sums
-                const Rec* oc = (const Rec*)a.O + (size_t)(ob - 1) * nn + i;
-                Rec col[NB];
-#pragma unroll
-                for (int jj = 0; jj < NB; ++jj) col[jj] = oc[(size_t)jj * NB];
-#pragma unroll
-                for (int jj = 0; jj < NB; ++jj) acc += (double)col[jj] * xk[jj - NB];
-              }
+            const double bv = a.b[g * NB + e0 + e];
+            if (need) {
+              const double up = c.k > 0 ? Td[(c.lrow - 1) * NB + e0 + e] : 0.0;
+              r64 = bv - (acc[e] + up);
+            } else {
+              r64 = bv;  // x = 0
             }
-            r64 = a.b[g * NB + i] - acc;
           }
           rp += r64 * r64;
           r64v[e] = r64;
         }
-        const double s = c.sumd(rp);  // its barrier also orders xs reads
-        if (!done && (outer > 0 || a.warm)) {
+        const double s = c.sumd(rp);
+        if (need) {
           nr2 = s;
           ++c.nrs;
         }
@@ -520,8 +704,8 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
         }
       }
 
-      // inner system  Ahat d = L^{-1} r64  for the systems still running
-      float r[EPT], d[EPT], p[EPT], z[EPT], qv[EPT];
+      // ---- inner system  Ahat d = L^{-1} r64  for the systems still running
+      float r[EPT], p[EPT], z[EPT], qv[EPT];
       {
         c.put(&sm.V[0][c.lrow * G::ROW], r64f);
         c.put_flag(!done);
@@ -529,23 +713,25 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
         if (!c.any_after_barrier()) break;  // every system of the bin is done
         if (!done) ++c.ntr;
         const float* rk = &sm.V[0][c.lrow * G::ROW];
-#pragma unroll 1
-        for (int e = 0; e < EPT; ++e) {
-          const int i = e0 + e;
-          float acc = 0.f;
-          if (c.row_ok && !done) {
-            // row i of L_k^{-1}: full blocks, or packed lower triangles
-            const float* lr =
-                Li + (PK ? (size_t)g * LP + (size_t)(i * (i + 1) / 2)
-                         : (size_t)g * nn + (size_t)i * NB);
+        float Lv[EPT][NB];
+        if (c.row_ok && !done) {
+          c.template load_li_rows<PK>(Li, g, Lv);
+        } else {
 #pragma unroll
-            for (int jj = 0; jj < NB; ++jj)
-              if (jj <= i) acc = __fmaf_rn(lr[jj], rk[spos(jj)], acc);
-          }
+          for (int e = 0; e < EPT; ++e)
+#pragma unroll
+            for (int j = 0; j < NB; ++j) Lv[e][j] = 0.f;
+        }
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          float acc = 0.f;
+#pragma unroll
+          for (int j = 0; j < NB; ++j) acc = __fmaf_rn(Lv[e][j], rk[spos(j)], acc);
           r[e] = acc;
           d[e] = 0.f;
         }
       }
+      c.load_F(F, g);  // F_k for this inner solve
       // z = M^{-1} r for the inner right-hand side
       {
         float cr[EPT];
@@ -617,34 +803,14 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
         c.template C<1>(r, cr, act);
         c.template precond_rest<M>(a, r, cr, z, act);
       }
-      // x64 += L^{-T} d
-      {
-        const float* dk = c.template stage_row<0>(d);
-        if (!done) {
-#pragma unroll 1
-          for (int e = 0; e < EPT; ++e) {
-            const int i = e0 + e;
-            if (c.row_ok) {
-              // column i of L_k^{-1}
-              const float* lc = Li + (PK ? (size_t)g * LP : (size_t)g * nn) + i;
-              float acc = 0.f;
-#pragma unroll
-              for (int jj = 0; jj < NB; ++jj)
-                if (jj >= i)
-                  acc = __fmaf_rn(
-                      lc[PK ? jj * (jj + 1) / 2 : jj * NB],
-                      dk[spos(jj)], acc);
-              sm.xs[c.lrow * NB + i] += (double)acc * unscale;
-            }
-          }
-          ++c.ntr;
+      if (!done) {
+        ran = true;  // the correction is applied at the top of the loop
+        if (inner == 0) {
+          status = BT_EBREAKDOWN;
+          done = true;
+          ran = false;
           ++outer;
-          if (inner == 0) {
-            status = BT_EBREAKDOWN;
-            done = true;
-          }
         }
-        __syncthreads();  // xs complete before the next residual
       }
     }
 
