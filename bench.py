@@ -39,8 +39,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--cpu-seconds", type=float, default=6.0,
-                    help="budget of the oracle CPU-baseline sample")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0,
+                    help="wall-clock budget of the oracle CPU-baseline sample "
+                         "on all cores (the one-core sample takes half)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-tune", action="store_true",
@@ -410,12 +411,14 @@ def _multirhs_n48(bt, torch, dev, tol, one):
 
 def cpu_baseline(data, budget_s, cores):
     """The FP64 oracle (closed-form setup + textbook PCG, same preconditioner
-    and tolerance) on a prefix of the batch, instances spread over ``cores``
-    threads (the C oracle releases the GIL), for about ``budget_s`` seconds."""
+    and tolerance), compiled -O3 -march=native on this host, on a prefix of
+    the batch: once with instances spread over ``cores`` threads (the C
+    oracle releases the GIL) for about ``budget_s`` seconds, once on one
+    core for about half that. Returns (all-core figure, one-core figure)."""
     import concurrent.futures as cf
+    import tempfile
 
     import oracle
-    oracle.build(force=False)
     offs = data["offsets"]
     slices = list(oracle.batch_slices(offs))
 
@@ -425,27 +428,39 @@ def cpu_baseline(data, budget_s, cores):
                              m=2, alpha=oracle.polycoeff(2), tol=1e-10)
         return info["iters"]
 
-    # calibrate on a few instances, then size the sample to the budget; when
-    # the whole batch takes less than the budget it is solved several times
-    t0 = time.perf_counter()
-    for it in slices[:8]:
-        one(it)
-    per = (time.perf_counter() - t0) / 8
-    want = int(max(cores, budget_s * cores / max(per, 1e-6)))
-    passes = max(1, min(20, want // len(slices)))
-    sample = slices[:min(len(slices), want)] * passes
-    count = len(sample)
-    t0 = time.perf_counter()
-    with cf.ThreadPoolExecutor(max_workers=cores) as ex:
-        list(ex.map(one, sample))
-    dt = time.perf_counter() - t0
-    rows = int(sum(r.stop - r.start for _, r, _ in sample))
-    what = (f"the whole batch {passes} times" if passes > 1 else
-            f"first {count} of {len(slices)} instances")
-    return {"value": count / dt, "unit": "solves/s", "cores": cores,
-            "kind": "oracle",
-            "sample": f"{what} ({count} solves, {rows} block rows), FP64 "
-                      f"closed-form setup + PCG to 1e-10, {dt:.1f} s wall"}
+    def run(threads, budget):
+        # calibrate on a few instances, then size the sample to the budget;
+        # when the whole batch takes less than the budget it is solved
+        # several times
+        t0 = time.perf_counter()
+        for it in slices[:8]:
+            one(it)
+        per = (time.perf_counter() - t0) / 8
+        want = int(max(threads, budget * threads / max(per, 1e-6)))
+        passes = max(1, min(20, want // len(slices)))
+        sample = slices[:min(len(slices), want)] * passes
+        t0 = time.perf_counter()
+        if threads > 1:
+            with cf.ThreadPoolExecutor(max_workers=threads) as ex:
+                list(ex.map(one, sample))
+        else:
+            for it in sample:
+                one(it)
+        dt = time.perf_counter() - t0
+        rows = int(sum(r.stop - r.start for _, r, _ in sample))
+        what = (f"the whole batch {passes} times" if passes > 1 else
+                f"first {len(sample)} of {len(slices)} instances")
+        return {"value": len(sample) / dt, "unit": "solves/s",
+                "cores": threads, "kind": "oracle",
+                "sample": f"{what} ({len(sample)} solves, {rows} block rows), "
+                          f"FP64 closed-form setup + PCG to 1e-10, oracle "
+                          f"built -O3 -march=native, {dt:.1f} s wall"}
+
+    with tempfile.TemporaryDirectory(prefix="oracle_native_") as tmp:
+        with oracle.use_library(oracle.build_native(tmp)):
+            allc = run(cores, budget_s)
+            onec = run(1, budget_s / 2)
+    return allc, onec
 
 
 def main():
@@ -640,8 +655,9 @@ def main():
                              "inner_iters_mean": float(iters.mean()),
                              "converged": True}
 
-    cores = min(16, len(os.sched_getaffinity(0)))
-    cpu = None if args.no_cpu else cpu_baseline(data, args.cpu_seconds, cores)
+    cores = len(os.sched_getaffinity(0))  # every core this process may use
+    cpu, cpu1 = ((None, None) if args.no_cpu
+                 else cpu_baseline(data, args.cpu_seconds, cores))
 
     out = {
         "metric": METRIC,
@@ -700,6 +716,7 @@ def main():
             "direct_block_cholesky_ms": direct_ms,
             "direct_vs_pcg_rel_diff": direct_diff,
             "workloads": secondary,
+            "cpu_baseline_one_core": cpu1,
         },
     }
     print(json.dumps(out), flush=True)

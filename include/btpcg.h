@@ -58,6 +58,9 @@ extern "C" {
 #define BT_ENONFINITE (-4)  /* a non-finite value appeared */
 #define BT_EHIP (-5)        /* HIP runtime error */
 #define BT_ENOSPACE (-6)    /* workspace too small */
+#define BT_ETIMEOUT (-7)    /* bt_solve_grid: a grid barrier waited longer
+                               than its limit (bt_set_grid_wait) and the
+                               solve gave up; x is not a solution */
 
 /* Arithmetic of the iteration. */
 #define BT_F64 0     /* float64 throughout */
@@ -247,26 +250,34 @@ int bt_solve_direct(const bt_handle* h, const double* b, double* x,
 
 /* One system spread over the whole GPU (the preconditioned conjugate
  * gradient iteration of bt_solve with the preconditioner of eq.
- * Mminv-polynomial-coefficients evaluated as in Section IV-B; the
- * parallel layout follows the n_blk workgroups over block rows of Section
- * IV-C): every
- * step of the iteration is a kernel over all block rows, so a single long
- * horizon is not confined to one workgroup, and systems above the
- * single-workgroup capacity of bt_solve (N n > 8192) can be solved. Same
+ * Mminv-polynomial-coefficients evaluated as in Section IV-B; the parallel
+ * layout follows the n_blk workgroups over block rows of Section IV-C): the
+ * block rows are cut into windows spread over all CUs, so a single long
+ * horizon is not confined to one workgroup and systems above the
+ * single-workgroup capacity of bt_solve (N n > 8192) can be solved. One
+ * persistent (cooperative) launch runs the whole solve, the refinement loop
+ * included, with grid-wide barriers between the steps and every decision
+ * taken on the device; the call is asynchronous on the stream. Same
  * parameters, stopping tests and results as bt_solve for a handle of one
  * system (B = 1): BT_F64 / BT_F32 iterate in that precision, BT_F32_IR (and
  * BT_BF16X2_IR) run float32 PCG inside float64 refinement on the record.
- * b, x: device [N][n] float64; info: device, 1 entry. scratch: device,
- * >= bt_grid_workspace_bytes(h) (seven vectors of the iteration precision,
- * one float64 vector and per-workgroup partial sums). Host-driven: the call
- * synchronises with the stream every few iterations and returns when the
- * solve is complete (not capturable in a graph). Errors: BT_EINVAL (B != 1,
- * NULL pointers, tol < 0, maxit < 0), BT_ENOSPACE, BT_EHIP; a D_k that is
- * not positive definite gives info.status BT_ENOTSPD with fail_index. */
+ * b, x: device [N][n] float64; info: device, 1 entry (status BT_ETIMEOUT if
+ * a barrier gave up, see bt_set_grid_wait). scratch: device,
+ * >= bt_grid_workspace_bytes(h) (nine vectors of the iteration precision,
+ * one float64 vector, per-window partial sums and the barrier state).
+ * Errors: BT_EINVAL (B != 1, NULL pointers, tol < 0, maxit < 0),
+ * BT_ENOSPACE, BT_EHIP; a D_k that is not positive definite gives
+ * info.status BT_ENOTSPD with fail_index. */
 size_t bt_grid_workspace_bytes(const bt_handle* h);
 int bt_solve_grid(const bt_handle* h, const double* b, double* x, double tol,
                   int maxit, bt_info* info, void* scratch,
                   size_t scratch_bytes, void* stream);
+
+/* Longest wait, in seconds, of one grid barrier of bt_solve_grid on this
+ * handle before the solve gives up with BT_ETIMEOUT (default 2 s; a barrier
+ * normally waits microseconds). Every workgroup then returns, so the kernel
+ * always ends. Errors: BT_EINVAL (NULL handle, seconds < 0 or not finite). */
+int bt_set_grid_wait(bt_handle* h, double seconds);
 
 /* bt_solve_grid for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid allocation):
@@ -276,13 +287,12 @@ int bt_solve_grid(const bt_handle* h, const double* b, double* x, double tol,
  * until the process ends), instead of a workspace argument. The call
  * allocates no device memory. A system whose grid scratch
  * (bt_grid_workspace_bytes) exceeds the maximum is refused with BT_ENOSPACE
- * before any work is enqueued (float64: about 130 000 unknowns N n, float32
- * and refinement: about 230 000). Every call on one GPU shares that GPU's
+ * before any work is enqueued (float64: about 100 000 unknowns N n, float32
+ * and refinement: about 190 000). Every call on one GPU shares that GPU's
  * array: calls that overlap on one GPU (two host threads, or two streams
  * in flight) race. The current device must be the one the stream belongs
- * to. Like bt_solve_grid it synchronises with the stream and is not
- * capturable. Errors: as bt_solve_grid, plus BT_ENOSPACE for a system above
- * the maximum. */
+ * to. Like bt_solve_grid it is asynchronous on the stream. Errors: as
+ * bt_solve_grid, plus BT_ENOSPACE for a system above the maximum. */
 #define BT_GRID_NOALLOC_MAX_BYTES ((size_t)8 << 20)
 int bt_solve_grid_noalloc(const bt_handle* h, const double* b, double* x,
                           double tol, int maxit, bt_info* info, void* stream);

@@ -36,6 +36,15 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+def build_native(dest_dir: str) -> str:
+    """Compile oracle.c with -O3 -march=native into ``dest_dir`` (for timing
+    the oracle on the host it runs on; the in-tree build stays portable)."""
+    out = os.path.join(dest_dir, "liboracle_native.so")
+    subprocess.check_call(["gcc", "-O3", "-march=native", "-std=c99", "-fPIC",
+                           "-shared", "-o", out, _SRC, "-lm"])
+    return out
+
+
 _lib = None
 
 

@@ -21,6 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libbtpcg.so")
 
 OK, NOT_CONVERGED, EINVAL, ENOTSPD, EBREAKDOWN, ENONFINITE, EHIP, ENOSPACE = \
     0, 1, -1, -2, -3, -4, -5, -6
+ETIMEOUT = -7
 F64, F32, F32_IR, BF16X2_IR = 0, 1, 2, 3
 DT_F64, DT_F32 = 0, 1
 PC_POLY, PC_NONE = 0, 1
@@ -80,6 +81,7 @@ def load_library(path: str = LIB_PATH):
         "bt_grid_workspace_bytes": (Sz, [P]),
         "bt_solve_grid": (I, [P, P, P, Dd, I, P, P, Sz, P]),
         "bt_solve_grid_noalloc": (I, [P, P, P, Dd, I, P, P]),
+        "bt_set_grid_wait": (I, [P, Dd]),
         "bt_kernel_config_count": (I, []),
         "bt_kernel_config": (I, [I, ctypes.POINTER(I), ctypes.POINTER(I),
                                  ctypes.POINTER(I)]),
@@ -103,7 +105,7 @@ def exported_symbols():
             "bt_mrhs_workspace_bytes", "bt_solve_mrhs",
             "bt_direct_workspace_bytes", "bt_solve_direct",
             "bt_grid_workspace_bytes", "bt_solve_grid",
-            "bt_solve_grid_noalloc",
+            "bt_solve_grid_noalloc", "bt_set_grid_wait",
             "bt_kernel_config_count", "bt_kernel_config",
             "bt_set_kernel_config", "bt_get_kernel_config", "bt_destroy"]
 
@@ -290,6 +292,12 @@ class Handle:
     def kernel_config(self) -> int:
         return load_library().bt_get_kernel_config(self._h)
 
+    def set_grid_wait(self, seconds: float):
+        """Longest wait of one grid barrier of solve_grid before the solve
+        gives up with status ETIMEOUT (default 2 s)."""
+        _check(load_library().bt_set_grid_wait(self._h, float(seconds)),
+               "bt_set_grid_wait")
+
     def refactor(self, stream=None):
         torch = _torch()
         _check(load_library().bt_refactor(self._h, _stream(torch, stream)),
@@ -387,8 +395,8 @@ class Handle:
 
     def solve_grid(self, b, tol=1e-10, maxit=None, x=None, info=None,
                    scratch=None, stream=None):
-        """Solve the handle's single system with every PCG step a kernel over
-        all block rows (bt_solve_grid). Returns (x, info)."""
+        """Solve the handle's single system spread over the whole GPU, one
+        persistent launch (bt_solve_grid). Returns (x, info)."""
         torch = _torch()
         b = self._vec(b, "b")
         lib = load_library()

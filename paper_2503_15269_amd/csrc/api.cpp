@@ -15,84 +15,16 @@
 
 namespace {
 
-constexpr size_t kAlign = 256;
-
-size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
-
-bool params_ok(const bt_params* p) {
-  if (!p) return false;
-  if (!(std::isfinite(p->a) && std::isfinite(p->b))) return false;
-  // admissible set C_g: 2a + b = 1, a >= 0, b >= -1
-  if (std::fabs(2.0 * p->a + p->b - 1.0) > 1e-12) return false;
-  if (p->a < 0.0 || p->b < -1.0 - 1e-12) return false;
-  if (p->m < 1 || p->m > BT_MAX_M) return false;
-  if (p->pc != BT_PC_POLY && p->pc != BT_PC_NONE) return false;
-  if (p->prec != BT_F64 && p->prec != BT_F32 && p->prec != BT_F32_IR &&
-      p->prec != BT_BF16X2_IR)
-    return false;
-  for (int i = 1; i < p->m; ++i)
-    if (!std::isfinite(p->alpha[i])) return false;
-  if (p->warm_start != 0 && p->warm_start != 1) return false;
-  if (p->prec == BT_F32_IR || p->prec == BT_BF16X2_IR) {
-    if (p->max_outer < 1) return false;
-    if (!(p->inner_tol > 0.0 && p->inner_tol < 1.0)) return false;
-  }
-  return true;
-}
-
-size_t elem_bytes(const bt_params* p) {
-  return p->prec == BT_F64 ? sizeof(double) : sizeof(float);
-}
+using btv::align_up;
+using btv::check_offsets;
+using btv::elem_bytes;
+using btv::fast_capable;
+using btv::Layout;
+using btv::layout;
+using btv::params_ok;
 
 int kernel_prec(const bt_params* p) {
   return p->prec == BT_F64 ? BT_F64 : BT_F32;
-}
-
-// Validate offsets; returns total rows R (or -1) and the largest horizon.
-int64_t check_offsets(int B, const int64_t* off, int* maxN) {
-  if (B < 1 || !off || off[0] != 0) return -1;
-  int64_t mx = 0;
-  for (int i = 0; i < B; ++i) {
-    int64_t Ni = off[i + 1] - off[i];
-    if (Ni < 1 || Ni > (int64_t)1 << 30) return -1;
-    mx = std::max(mx, Ni);
-  }
-  *maxN = (int)mx;
-  return off[B];
-}
-
-struct Layout {
-  size_t off, order, rowinst, ctr, fail, bins, items, F, L, Li, Lp, Fhi, Flo,
-      total;
-};
-
-// The register-resident kernel can serve the handle (block size and
-// precision; whether its systems fit its bins is decided at setup).
-bool fast_capable(int n, const bt_params* p) {
-  return (n == 12 || n == 24) && p->prec == BT_F32_IR;
-}
-
-Layout layout(int B, int64_t R, int n, size_t es, bool split, bool packed) {
-  Layout l{};
-  size_t at = 0;
-  l.off = at; at += align_up(sizeof(int64_t) * (B + 1));
-  l.order = at; at += align_up(sizeof(int32_t) * B);
-  l.rowinst = at; at += align_up(sizeof(int32_t) * (size_t)R);
-  l.ctr = at; at += align_up(sizeof(int32_t) * 64);
-  l.fail = at; at += align_up(sizeof(int32_t) * B);
-  l.bins = at; at += BT_FAST_VARIANTS * align_up(sizeof(int32_t) * 2 * B);
-  l.items = at; at += BT_FAST_VARIANTS * align_up(sizeof(int32_t) * B);
-  const size_t blk = align_up(es * (size_t)R * n * n);
-  l.F = at; at += blk;
-  l.L = at; at += blk;
-  l.Li = at; at += blk;
-  l.Lp = at; at += packed ? align_up(es * (size_t)R * li_packed_len(n)) : 0;
-  // bfloat16 splits of F and of the transposed blocks
-  const size_t hblk = split ? align_up(2 * 2 * (size_t)R * n * n) : 0;
-  l.Fhi = at; at += hblk;
-  l.Flo = at; at += hblk;
-  l.total = at;
-  return l;
 }
 
 // Configuration indices of the register-resident bin kernel variants (after
@@ -247,6 +179,7 @@ const char* bt_strerror(int code) {
     case BT_ENONFINITE: return "non-finite value";
     case BT_EHIP: return "HIP runtime error";
     case BT_ENOSPACE: return "workspace too small";
+    case BT_ETIMEOUT: return "a grid barrier gave up waiting (workgroups not all resident)";
     default: return "unknown status";
   }
 }
@@ -493,24 +426,6 @@ int bt_solve_grid(const bt_handle* h, const double* b, double* x, double tol,
     const int rc = launch_setup(h, s, true);
     if (rc != BT_OK) return rc;
   }
-  int fail = BT_NO_FAIL;
-  if (hipMemcpyAsync(&fail, h->fail, sizeof(int), hipMemcpyDeviceToHost, s) !=
-          hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
-    return BT_EHIP;
-  if (fail != BT_NO_FAIL) {  // a D_k is not positive definite
-    bt_info hi{};
-    hi.status = BT_ENOTSPD;
-    hi.fail_index = fail;
-    hi.relres = NAN;
-    hi.relres_true = NAN;
-    if (hipMemsetAsync(x, 0, sizeof(double) * h->R * h->n, s) != hipSuccess ||
-        hipMemcpyAsync(info, &hi, sizeof(hi), hipMemcpyHostToDevice, s) !=
-            hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
-      return BT_EHIP;
-    return BT_OK;
-  }
   return bt_grid_solve(h, b, x, tol, maxit, info, scratch, s);
 }
 
@@ -524,6 +439,12 @@ int bt_solve_grid_noalloc(const bt_handle* h, const double* b, double* x,
   if (bt_grid_static_scratch(&ws) != hipSuccess || !ws) return BT_EHIP;
   return bt_solve_grid(h, b, x, tol, maxit, info, ws,
                        BT_GRID_NOALLOC_MAX_BYTES, stream);
+}
+
+int bt_set_grid_wait(bt_handle* h, double seconds) {
+  if (!h || !(seconds >= 0.0) || !std::isfinite(seconds)) return BT_EINVAL;
+  h->grid_wait_s = seconds;
+  return BT_OK;
 }
 
 int bt_kernel_config_count(void) { return num_configs(); }

@@ -11,8 +11,8 @@ struct bt_handle;
 // Scratch bytes of bt_grid_solve for a handle of one system.
 size_t bt_grid_scratch_bytes(const bt_handle* h);
 
-// PCG for the single system of ``h`` with every step a kernel over all block
-// rows; host-driven (synchronises with the stream every few iterations).
+// PCG for the single system of ``h`` spread over the whole GPU in one
+// persistent launch (asynchronous on the stream).
 int bt_grid_solve(const bt_handle* h, const double* b, double* x, double tol,
                   int maxit, bt_info* info, void* ws, hipStream_t s);
 

@@ -1,35 +1,53 @@
-// Grid-wide PCG for one large system.
+// Grid-wide PCG for one large system, in one persistent launch.
 //
-// The register-resident and persistent kernels give each system one
-// workgroup, which leaves a single long horizon (hundreds of block rows) on
-// one CU with the whole iteration latency-bound there. Here every step of
-// the iteration is a kernel over all block rows instead, and the kernel
-// boundaries are the grid-wide barriers the PCG recurrences need:
-//   k_g_init   r = L^{-1} s (s = b, or the float64 residual under
-//              refinement), z = M^{-1} r, rho and ||s||^2 partials
-//   k_g_q      p = z + beta p, q = Ahat p = p - C p, sigma partials
-//   k_g_u      x += alpha p, r -= alpha q, ||L r||^2 partials,
-//              z = M^{-1} r, rho partials
-//   k_g_x      x = L^{-T} xhat (or x += L^{-T} d under refinement)
-//   k_g_res    float64 residual b - A x of the record, ||.||^2 partials
-// Same scaled coordinates as the other solve kernels: Ahat = I - C,
+// The register-resident and queue kernels give each system one workgroup,
+// which leaves a single long horizon (hundreds of block rows) on one CU with
+// the whole iteration latency-bound there. Here the block rows of the one
+// system are cut into windows of rb consecutive rows spread over the whole
+// GPU, and one launch runs the complete solve: the phases below, separated
+// by grid-wide barriers, with every decision (alpha, beta, stopping, the
+// refinement loop) taken on the device.
+//   init   r = L^{-1} f (f = b, or the float64 residual), u = M^{-1} r,
+//          w = Ahat u, partials of r'u, w'u and ||f||^2
+//   step   alpha, beta from the sums; p = u + beta p, s = w + beta s,
+//          x += alpha p, r -= alpha s, u = M^{-1} r, w = Ahat u, partials
+//          of r'u, w'u (and ||L r||^2 for the stopping test)
+//   x      x = L^{-T} xhat (or x += L^{-T} d under refinement)
+//   res    float64 residual b - A x of the record, ||.||^2 partials
+// The step is the conjugate gradient iteration in the arrangement of
+// Chronopoulos and Gear (1989): s = A p is carried by its own recurrence and
+// sigma = p'A p = w'u - beta r'u / alpha_prev, so both dot products of an
+// iteration come from one reduction and a step costs one grid barrier
+// instead of two. In exact arithmetic its iterates are those of textbook
+// PCG (the same alpha, beta, r, x); in floating point they differ by
+// rounding. Same scaled
+// coordinates as the other solve kernels: Ahat = I - C,
 // (C v)_k = -(F_{k-1}^T v_{k-1} + F_k v_{k+1}), and the preconditioner of
 // eq. Mminv-polynomial-coefficients evaluated as y_0 = (I + aC) r,
 // y_i = ((1-a)C + aC^2) y_{i-1}, z = sum alpha_i y_i (Section IV-B).
 //
-// A workgroup owns rb consecutive block rows. M^{-1} needs neighbours to a
-// depth D (1 + 2(m-1) at a = 1): the workgroup loads r (or forms r - alpha q)
-// on its rows plus D on each side into LDS and applies C there on windows
-// that shrink by one row per application, so M^{-1} r of its own rows needs
-// no further grid-wide exchange. Scalars never leave the device: each
-// workgroup writes one partial per reduction, and every workgroup of the
-// next kernel sums all partials in the same fixed order, so all of them
-// take the same decisions (alpha, beta, stopping) without a broadcast.
-// Workgroup 0 records the outcome in a small control block that the host
-// reads every few iterations; kernels that find it settled return at once.
+// M^{-1} needs neighbours to a depth D (1 + 2(m-1) at a = 1) and w = Ahat u
+// one more: the workgroup forms r - alpha s on its window's rows plus D + 1
+// on each side in LDS and applies C there on windows that shrink by one row
+// per application, so u and w of its own rows need no further exchange.
+// Scalars never leave the device: each window writes one partial per
+// reduction, and every workgroup sums all partials in the same fixed order,
+// so all of them take the same decisions without a broadcast.
+//
+// Grid barrier: an arrival counter in the scratch, reset before the solve;
+// barrier j is passed once it reaches (j + 1) times the workgroups. The data
+// windows exchange is written and read with agent-coherent accesses, and
+// every thread waits for its stores to complete before its workgroup
+// arrives, so no cache has to be written back or invalidated. The wait is bounded by a wall-clock limit: a
+// workgroup that gives up raises an abort flag, every other workgroup sees it
+// at its next wait and returns, and the solve reports BT_ETIMEOUT. The grid
+// never exceeds the workgroups that fit on the device at once, and each
+// workgroup loops over several windows when there are more windows than
+// that.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <mutex>
 
@@ -41,49 +59,74 @@ namespace btg {
 
 using btk::AccOf;
 
-constexpr int NT = 256;    // threads per workgroup
-constexpr int CHUNK = 8;   // iterations enqueued between host checks
-// partial-sum slots, nwg doubles each
-enum { P_RHO0 = 0, P_RHO1 = 1, P_SIG = 2, P_NR2 = 3, P_NB2 = 4, P_RES = 5,
-       P_RHOF = 6, P_SLOTS = 7 };
+constexpr int NT = 256;  // threads per workgroup
+// partial-sum slots, nwin doubles each: gamma = r'u, delta = w'u and
+// ||L r||^2 by step parity, ||src||^2, the float64 residual, gamma of the
+// first step
+enum { P_G = 0, P_D = 2, P_N = 4, P_NB2 = 6, P_RES = 7, P_GF = 8,
+       P_SLOTS = 9 };
 
-struct Ctl {
-  int status;  // BT_NOT_CONVERGED while the (inner) iteration runs
-  int it;      // PCG steps of this (inner) solve
-  // sums of the partial slots P_NB2, P_RES, P_NR2 (k_g_sums), read by the
-  // host after the last kernel of a solve or refinement step
-  double nb2, res, nr2;
+// Barrier state in the scratch (reset by k_g_reset before every solve).
+struct Bar {
+  unsigned count;  // arrivals so far in this solve: barrier j is passed
+                   // when it reaches (j + 1) * (workgroups)
+  int abort;       // a workgroup gave up waiting
+  int pad[2];
 };
 
 template <typename T>
 struct GArgs {
-  int R, n, rb, depth, nwg, pc, m, ir, dtype;
+  int R, n, rb, depth, nwin, pc, m, dtype;
+  int refine, warm, from_res, max_outer, maxit;
   double a, tol, itol;
-  // k_g_init reads src * sscale (a power of two: the right-hand side of the
-  // inner solve at norm in [1, 2)); k_g_x adds L^{-T} d * xscale = 1/sscale
-  double sscale, xscale;
   double alpha[BT_MAX_M];
+  long long spin_limit;  // wall-clock ticks (100 MHz) a barrier waits at most
   const T* F;
   const T* L;
   const T* Li;
   const void* D;  // record
   const void* O;
-  const double* src;  // k_g_init: b or the float64 residual
+  const int32_t* fail;  // first failing block row of the factorisation
   const double* b;
   double* x;          // float64 iterate / solution
-  double* r64;        // float64 residual (refinement)
-  T* pb[2];
-  T* rbuf[2];
-  T* q;
-  T* z;
+  double* r64;        // float64 residual
+  T* rbuf[2];         // residual r, by step parity
+  T* sbuf[2];         // s = A p, by step parity
+  T* wbuf[2];         // w = A u, by step parity
+  T* u;               // u = M^{-1} r
+  T* p;               // search direction
   T* xh;              // scaled iterate (direct) or correction d (refinement)
-  double* part;       // [P_SLOTS][nwg]
-  Ctl* ctl;
+  double* part;       // [P_SLOTS][nwin]
+  Bar* bar;
+  bt_info* info;
+};
+
+// Per-solve state that every workgroup holds identically.
+struct St {
+  const double* src;   // right-hand side of the next init phase
+  double sscale;       // init reads src * sscale (a power of two)
+  double xscale;       // x phase adds L^{-T} d * xscale
+  double tol_in;       // stopping tolerance of the inner iteration
+  int ir;              // inner solve of a refinement step
 };
 
 __device__ __forceinline__ double rec(const void* P, size_t i, int dtype) {
   return dtype == BT_DT_F64 ? ((const double*)P)[i]
                             : (double)((const float*)P)[i];
+}
+
+// Data that one window writes and others read (vector rows next to a
+// window's own, partial sums, x for the residual) goes through agent-scope
+// relaxed atomic loads and stores: coherent across the XCDs' separate L2
+// caches without writing back or invalidating whole caches, so read-only
+// operands (F, L, D, O) stay cached across the barriers.
+template <typename V>
+__device__ __forceinline__ V ld_sh(const V* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename V>
+__device__ __forceinline__ void st_sh(V* p, V v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Sums over the workgroup of K values per thread, every thread gets them:
@@ -114,39 +157,76 @@ __device__ __forceinline__ double wg_sum(double v, double* red) {
   return t[0];
 }
 
-// Sums of K partial slots over all workgroups (fixed order).
+// Sums of K partial slots over all windows (fixed order).
 template <int K>
 __device__ __forceinline__ void slot_sums(const double* part,
-                                          const int (&slot)[K], int nwg,
+                                          const int (&slot)[K], int nwin,
                                           double* red, double (&out)[K]) {
 #pragma unroll
   for (int k = 0; k < K; ++k) out[k] = 0.0;
-  for (int i = threadIdx.x; i < nwg; i += NT) {
+  for (int i = threadIdx.x; i < nwin; i += NT) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) out[k] += part[slot[k] * nwg + i];
+    for (int k = 0; k < K; ++k) out[k] += ld_sh(part + slot[k] * nwin + i);
   }
   wg_sums<K>(out, red);
 }
 
-// Settle the solve (workgroup 0 writes; the others took the same decision).
-__device__ __forceinline__ void settle(Ctl* ctl, int status) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->status = status;
-}
+// Grid-wide barrier with a bounded wait; false once the solve is aborted.
+// Every thread first waits until its shared stores have completed (they are
+// agent-coherent), then one thread per workgroup adds its arrival to the
+// counter (no reply needed) and waits until the counter reaches this
+// barrier's target: no workgroup has to reset or release anything.
+struct Sync {
+  Bar* bar;
+  unsigned nwg;
+  unsigned target;  // arrivals that complete the next barrier (thread 0)
+  long long limit;
+  __device__ bool operator()(int* flag) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int ok = 1;
+      target += nwg;
+      __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+      const long long t0 = (long long)wall_clock64();
+      while ((int)(__hip_atomic_load(&bar->count, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT) -
+                   target) < 0) {
+        if (__hip_atomic_load(&bar->abort, __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+            (long long)wall_clock64() - t0 > limit) {
+          __hip_atomic_store(&bar->abort, 1, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      if (__hip_atomic_load(&bar->abort, __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_AGENT) != 0)
+        ok = 0;
+      *flag = ok;
+    }
+    __syncthreads();
+    return *flag != 0;
+  }
+};
 
 // Window geometry: own rows [k0, k1), window [w0, w1) with depth d.
 struct Win {
   int k0, k1, w0, w1;
 };
-__device__ __forceinline__ Win window(int R, int rb, int d) {
+__device__ __forceinline__ Win window(int R, int rb, int d, int wi) {
   Win w;
-  w.k0 = blockIdx.x * rb;
+  w.k0 = wi * rb;
   w.k1 = min(R, w.k0 + rb);
   w.w0 = max(0, w.k0 - d);
   w.w1 = min(R, w.k1 + d);
   return w;
 }
 
-// The blocks F_b, b in [fb0, fb0 + cnt), of a workgroup: staged in LDS when
+// The blocks F_b, b in [fb0, fb0 + cnt), of a window: staged in LDS when
 // they fit (then C reads them from there), else read from memory.
 template <typename T>
 struct FBlocks {
@@ -272,43 +352,12 @@ __device__ __forceinline__ T lowerT(const T* M, const T* v, int n, int k,
   return acc;
 }
 
-// Partial of one reduction over the own rows into its slot.
+// Partial of one reduction over the window's own rows into its slot.
 template <typename T>
 __device__ __forceinline__ void put_partial(const GArgs<T>& a, int slot,
-                                            double v, double* red) {
+                                            int wi, double v, double* red) {
   const double s = wg_sum(v, red);
-  if (threadIdx.x == 0) a.part[slot * a.nwg + blockIdx.x] = s;
-}
-
-// The preconditioner on the own rows from r known on the window; for
-// BT_PC_NONE (M = I on the original system) z = L^T L r, a row-local map.
-// Returns the rho partial r'z (the accumulator of the precision).
-template <typename T>
-__device__ double precond_own(const GArgs<T>& a, const FBlocks<T>& F,
-                              const Win& W, T* r, T* y, T* w1, T* w2, T* z) {
-  const int n = a.n, w0 = W.w0;
-  if (a.pc == BT_PC_NONE) {
-    for (int e = threadIdx.x; e < (W.k1 - W.k0) * n; e += NT) {
-      const int k = W.k0 + e / n, i = e % n;
-      y[(k - w0) * n + i] = lower(a.L, r + (k - w0) * n, n, k, i);
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < (W.k1 - W.k0) * n; e += NT) {
-      const int k = W.k0 + e / n, i = e % n;
-      z[(k - w0) * n + i] = lowerT(a.L, y + (k - w0) * n, n, k, i);
-    }
-    __syncthreads();
-  } else {
-    precond(a, F, W, r, y, w1, w2, z);
-  }
-  typename AccOf<T>::type acc;
-  acc.zero();
-  for (int e = threadIdx.x; e < (W.k1 - W.k0) * n; e += NT) {
-    const int o = (W.k0 - w0) * n + e;
-    acc.add_prod(r[o], z[o]);
-    a.z[(size_t)W.k0 * n + e] = z[o];
-  }
-  return acc.value();
+  if (threadIdx.x == 0) st_sh(a.part + slot * a.nwin + wi, s);
 }
 
 template <typename T>
@@ -317,13 +366,13 @@ __device__ __forceinline__ T* lds_vec(double* red, int slot, int len) {
 }
 
 // Entries of one window vector in LDS: rb rows and the halo on both sides
-// (at least one row: k_g_q forms p on the neighbour rows).
+// (at least one row: the q phase forms p on the neighbour rows).
 __host__ __device__ __forceinline__ int wlen(int rb, int depth, int n) {
   return (rb + 2 * (depth > 1 ? depth : 1)) * n;
 }
 
-// Bytes of staged blocks: the window's (rb + 2 depth - 1) or, in k_g_q,
-// rb + 1 blocks.
+// Bytes of staged blocks: the window's (rb + 2 depth - 1) or, in the q
+// phase, rb + 1 blocks.
 template <typename T>
 __host__ __device__ __forceinline__ size_t fstage_bytes(int rb, int depth,
                                                         int n) {
@@ -334,203 +383,256 @@ __host__ __device__ __forceinline__ size_t fstage_bytes(int rb, int depth,
 // do not fit
 template <typename T>
 __device__ __forceinline__ T* lds_F(const GArgs<T>& a, double* red) {
-  const int lmax = wlen(a.rb, a.depth, a.n);
-  return fstage_bytes<T>(a.rb, a.depth, a.n) <= FSTAGE_MAX
+  const int lmax = wlen(a.rb, a.depth + 1, a.n);
+  return fstage_bytes<T>(a.rb, a.depth + 1, a.n) <= FSTAGE_MAX
              ? lds_vec<T>(red, 5, lmax)
              : nullptr;
 }
 
-// r = L^{-1} s on the window (s = a.src, float64, cast to T first),
-// z = M^{-1} r, partials rho (both rho slots of step 0), ||s||^2.
+// ---------------------------------------------------------------------------
+// Phases on one window. Each ends with a barrier of the workgroup, so the
+// next window may reuse the LDS.
+// ---------------------------------------------------------------------------
+
+// u = M^{-1} r on own rows +- 1 and w = Ahat u = u - C u on own rows, from
+// r in LDS on the window (depth D + 1); u and w to memory, partials of r'u
+// and w'u (and ||L r||^2 when ``nrm``) into the slots of parity ``par``.
 template <typename T>
-__global__ void __launch_bounds__(NT) k_g_init(GArgs<T> a) {
-  extern __shared__ double red[];
-  const Win W = window(a.R, a.rb, a.depth);
+__device__ void u_and_w(const GArgs<T>& a, const FBlocks<T>& F, const Win& W,
+                        int par, bool nrm, int wi, T* r, T* y, T* w1, T* w2,
+                        T* z, double* red) {
+  const int n = a.n, w0 = W.w0;
+  if (a.pc == BT_PC_NONE) {  // u = L^T L r, row-local, on own rows +- 1
+    const int lo = max(W.k0 - 1, 0), hi = min(W.k1 + 1, a.R);
+    for (int e = threadIdx.x; e < (hi - lo) * n; e += NT) {
+      const int k = lo + e / n, i = e % n;
+      y[(k - w0) * n + i] = lower(a.L, r + (k - w0) * n, n, k, i);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < (hi - lo) * n; e += NT) {
+      const int k = lo + e / n, i = e % n;
+      z[(k - w0) * n + i] = lowerT(a.L, y + (k - w0) * n, n, k, i);
+    }
+    __syncthreads();
+  } else {
+    precond(a, F, W, r, y, w1, w2, z);
+  }
+  applyC(a, F, z, w1, w0, W.k0, W.k1);  // C u on own rows
+  __syncthreads();
+  typename AccOf<T>::type g, d, t2;
+  g.zero();
+  d.zero();
+  t2.zero();
+  for (int e = threadIdx.x; e < (W.k1 - W.k0) * n; e += NT) {
+    const int o = (W.k0 - w0) * n + e;
+    const size_t gi = (size_t)W.k0 * n + e;
+    const T wv = z[o] - w1[o];
+    a.u[gi] = z[o];
+    st_sh(a.wbuf[par] + gi, wv);
+    g.add_prod(r[o], z[o]);
+    d.add_prod(wv, z[o]);
+    if (nrm) {  // ||r|| = ||L rhat|| of the original system
+      const int k = W.k0 + e / n, i = e % n;
+      const T tv = lower(a.L, r + (k - w0) * n, n, k, i);
+      t2.add_prod(tv, tv);
+    }
+  }
+  double v[3] = {g.value(), d.value(), t2.value()};
+  wg_sums<3>(v, red);
+  if (threadIdx.x == 0) {
+    st_sh(a.part + (P_G + par) * a.nwin + wi, v[0]);
+    st_sh(a.part + (P_D + par) * a.nwin + wi, v[1]);
+    if (nrm) st_sh(a.part + (P_N + par) * a.nwin + wi, v[2]);
+  }
+}
+
+// Start of an inner solve: r = L^{-1} (src * sscale) on the window, xhat = 0,
+// u, w and their partials (parity 0), ||src * sscale||^2.
+template <typename T>
+__device__ void ph_init(const GArgs<T>& a, const St& st, int wi,
+                        double* red) {
+  const Win W = window(a.R, a.rb, a.depth + 1, wi);
   const int n = a.n, len = (W.w1 - W.w0) * n;
-  const int lmax = wlen(a.rb, a.depth, n);
+  const int lmax = wlen(a.rb, a.depth + 1, n);
   T* r = lds_vec<T>(red, 0, lmax);
   T* y = lds_vec<T>(red, 1, lmax);
   T* w1 = lds_vec<T>(red, 2, lmax);
   T* w2 = lds_vec<T>(red, 3, lmax);
   T* z = lds_vec<T>(red, 4, lmax);
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    a.ctl->status = BT_NOT_CONVERGED;
-    a.ctl->it = 0;
-  }
   const FBlocks<T> F = stage_F(a, W.w0, W.w1 - 1, lds_F(a, red));
   for (int e = threadIdx.x; e < len; e += NT)
-    y[e] = (T)(a.src[(size_t)W.w0 * n + e] * a.sscale);
+    y[e] = (T)(ld_sh(st.src + (size_t)W.w0 * n + e) * st.sscale);
   __syncthreads();
   double nb = 0.0;
   for (int e = threadIdx.x; e < len; e += NT) {
     const int k = W.w0 + e / n, i = e % n;
     r[e] = lower(a.Li, y + (k - W.w0) * n, n, k, i);
     if (k >= W.k0 && k < W.k1) {
-      const double s = a.src[(size_t)W.w0 * n + e] * a.sscale;
+      const double s = ld_sh(st.src + (size_t)W.w0 * n + e) * st.sscale;
       nb += s * s;
-      a.rbuf[0][(size_t)k * n + i] = r[e];
+      st_sh(a.rbuf[0] + (size_t)k * n + i, r[e]);
       a.xh[(size_t)k * n + i] = T(0);
     }
   }
   __syncthreads();
-  put_partial(a, P_NB2, nb, red);
-  const double rho = precond_own(a, F, W, r, y, w1, w2, z);
-  const double s = wg_sum(rho, red);
-  if (threadIdx.x == 0) {
-    a.part[P_RHO0 * a.nwg + blockIdx.x] = s;
-    a.part[P_RHOF * a.nwg + blockIdx.x] = s;
-  }
+  put_partial(a, P_NB2, wi, nb, red);
+  u_and_w(a, F, W, 0, false, wi, r, y, w1, w2, z, red);
+  if (threadIdx.x == 0)
+    st_sh(a.part + P_GF * a.nwin + wi, ld_sh(a.part + P_G * a.nwin + wi));
+  __syncthreads();
 }
 
-// Step i: the stopping test on the state after step i - 1, beta,
-// p = z + beta p (own rows and both neighbour rows), q = p - C p, sigma.
-// Everything the step reads is requested before the decisions.
+// Decision at the start of step i from the sums of the previous phase: the
+// stopping test on r_i (textbook order: ||r|| first, then r'u, then
+// p'Ap), beta and alpha. ``gprev`` and ``aprev`` hold gamma and alpha of
+// step i - 1 and are updated. Returns BT_NOT_CONVERGED to go on.
+constexpr int kCapped = 100;  // dec_step: the step cap is reached
+
 template <typename T>
-__global__ void __launch_bounds__(NT) k_g_q(GArgs<T> a, int i) {
-  extern __shared__ double red[];
-  const int st = a.ctl->status;
-  const Win W = window(a.R, a.rb, 1);
-  const int n = a.n, len = (W.w1 - W.w0) * n;
-  const int lmax = wlen(a.rb, a.depth, n);
-  T* p = lds_vec<T>(red, 0, lmax);
-  T* zb = lds_vec<T>(red, 1, lmax);
-  T* cp = lds_vec<T>(red, 2, lmax);
-  const T* pin = a.pb[(i + 1) & 1];
-  T* pout = a.pb[i & 1];
-  for (int e = threadIdx.x; e < len; e += NT) {
-    const size_t g = (size_t)W.w0 * n + e;
-    zb[e] = a.z[g];
-    p[e] = i == 0 ? T(0) : pin[g];
-  }
-  const FBlocks<T> F = stage_F(a, W.k0 - 1, W.k1, lds_F(a, red));
+__device__ int dec_step(const GArgs<T>& a, const St& st, int i, bool capped,
+                        double* red, double* gprev, double* aprev, T* al,
+                        T* be) {
+  const int par = i & 1;
   double S[5];
-  slot_sums<5>(a.part, {i & 1, (i + 1) & 1, P_NB2, P_NR2, P_RHOF}, a.nwg,
-               red, S);
-  if (st != BT_NOT_CONVERGED) return;
-  const double rho = S[0], rprev = S[1], nb2 = S[2], nr2 = S[3], rho0 = S[4];
-  if (!a.ir) {
+  slot_sums<5>(a.part, {P_G + par, P_D + par, P_N + par, P_NB2, P_GF},
+               a.nwin, red, S);
+  const double gam = S[0], del = S[1], nr2 = S[2], nb2 = S[3], g0 = S[4];
+  if (!st.ir) {
     if (i == 0) {
-      if (!(nb2 < INFINITY)) { settle(a.ctl, BT_ENONFINITE); return; }
-      if (nb2 == 0.0) { settle(a.ctl, BT_OK); return; }
+      if (!(nb2 < INFINITY)) return BT_ENONFINITE;
+      if (nb2 == 0.0) return BT_OK;
     } else {
-      if (nr2 <= a.tol * a.tol * nb2) { settle(a.ctl, BT_OK); return; }
-      if (!(nr2 < INFINITY)) { settle(a.ctl, BT_ENONFINITE); return; }
+      if (nr2 <= st.tol_in * st.tol_in * nb2) return BT_OK;
+      if (!(nr2 < INFINITY)) return BT_ENONFINITE;
     }
-    if (!(rho > 0.0)) {
-      settle(a.ctl, rho == rho ? BT_EBREAKDOWN : BT_ENONFINITE);
-      return;
-    }
-  } else {  // inner solve of a refinement step: stop when r'z fell enough
-    if (!(rho > 0.0)) { settle(a.ctl, BT_OK); return; }
-    if (i > 0 && rho <= a.itol * a.itol * rho0) {
-      settle(a.ctl, BT_OK);
-      return;
-    }
+    if (!(gam > 0.0)) return gam == gam ? BT_EBREAKDOWN : BT_ENONFINITE;
+  } else {  // inner solve of a refinement step: stop when r'u fell enough
+    if (!(gam > 0.0)) return BT_OK;
+    if (i > 0 && gam <= a.itol * a.itol * g0) return BT_OK;
   }
-  const T be = i == 0 ? T(0) : (T)(rho / rprev);
-  for (int e = threadIdx.x; e < len; e += NT)
-    p[e] = i == 0 ? zb[e] : zb[e] + be * p[e];
-  __syncthreads();
-  applyC(a, F, p, cp, W.w0, W.k0, W.k1);
-  __syncthreads();
-  typename AccOf<T>::type acc;
-  acc.zero();
-  for (int e = threadIdx.x; e < (W.k1 - W.k0) * n; e += NT) {
-    const int o = (W.k0 - W.w0) * n + e;
-    const size_t g = (size_t)W.k0 * n + e;
-    const T qv = p[o] - cp[o];
-    pout[g] = p[o];
-    a.q[g] = qv;
-    acc.add_prod(p[o], qv);
-  }
-  put_partial(a, P_SIG, acc.value(), red);
+  if (capped) return kCapped;
+  const double beta = i == 0 ? 0.0 : gam / *gprev;
+  const double sigma = i == 0 ? del : del - beta * gam / *aprev;  // p'A p
+  if (!(sigma > 0.0))
+    return st.ir ? BT_OK : (sigma == sigma ? BT_EBREAKDOWN : BT_ENONFINITE);
+  const double alpha = gam / sigma;
+  *gprev = gam;
+  *aprev = alpha;
+  *al = (T)alpha;
+  *be = (T)beta;
+  return BT_NOT_CONVERGED;
 }
 
-// Step i: alpha = rho / sigma, x += alpha p, r -= alpha q (own rows and the
-// preconditioner's halo), ||L r||^2, z = M^{-1} r, rho.
+// The vector data a step reads on one window, fetched before the step's
+// decision so that its loads overlap the partial sums' (windows of at most
+// PF NT entries; larger ones load in ph_step).
+constexpr int PF = 2;
 template <typename T>
-__global__ void __launch_bounds__(NT) k_g_u(GArgs<T> a, int i) {
-  extern __shared__ double red[];
-  if (a.ctl->status != BT_NOT_CONVERGED) return;
-  const Win W = window(a.R, a.rb, a.depth);
+struct Pre {
+  T r[PF], w[PF], s[PF], u[PF], p[PF];
+};
+
+template <typename T>
+__device__ __forceinline__ bool prefetchable(const GArgs<T>& a) {
+  return wlen(a.rb, a.depth + 1, a.n) <= PF * NT;
+}
+
+template <typename T>
+__device__ void ph_step_fetch(const GArgs<T>& a, int i, int wi, Pre<T>& f) {
+  const Win W = window(a.R, a.rb, a.depth + 1, wi);
   const int n = a.n, len = (W.w1 - W.w0) * n;
-  const int lmax = wlen(a.rb, a.depth, n);
+  const int cur = i & 1, nxt = cur ^ 1;
+#pragma unroll
+  for (int t = 0; t < PF; ++t) {
+    const int e = threadIdx.x + t * NT;
+    if (e < len) {
+      const int k = W.w0 + e / n;
+      const size_t g = (size_t)W.w0 * n + e;
+      f.r[t] = ld_sh(a.rbuf[cur] + g);
+      f.w[t] = ld_sh(a.wbuf[cur] + g);
+      f.s[t] = i == 0 ? T(0) : ld_sh(a.sbuf[nxt] + g);
+      if (k >= W.k0 && k < W.k1) {
+        f.u[t] = a.u[g];
+        f.p[t] = i == 0 ? T(0) : a.p[g];
+      }
+    }
+  }
+}
+
+// Step i: p = u + beta p, xhat += alpha p (own rows); s = w + beta s and
+// r -= alpha s on the window (depth D + 1); u, w of the new r and the
+// partials of step i + 1. ``f``: the window's data fetched ahead, or null.
+template <typename T>
+__device__ void ph_step(const GArgs<T>& a, const St& st, int i, T al, T be,
+                        int wi, const Pre<T>* f, double* red) {
+  const Win W = window(a.R, a.rb, a.depth + 1, wi);
+  const int n = a.n, len = (W.w1 - W.w0) * n;
+  const int lmax = wlen(a.rb, a.depth + 1, n);
+  const int cur = i & 1, nxt = cur ^ 1;
   T* r = lds_vec<T>(red, 0, lmax);
   T* y = lds_vec<T>(red, 1, lmax);
   T* w1 = lds_vec<T>(red, 2, lmax);
   T* w2 = lds_vec<T>(red, 3, lmax);
   T* z = lds_vec<T>(red, 4, lmax);
-  const int st = a.ctl->status;
-  const T* rin = a.rbuf[i & 1];
-  T* rout = a.rbuf[(i + 1) & 1];
-  const T* p = a.pb[i & 1];
-  for (int e = threadIdx.x; e < len; e += NT) {
-    const size_t g = (size_t)W.w0 * n + e;
-    r[e] = rin[g];
-    y[e] = a.q[g];
-  }
-  const FBlocks<T> F = stage_F(a, W.w0, W.w1 - 1, lds_F(a, red));
-  double S[2];
-  slot_sums<2>(a.part, {P_SIG, i & 1}, a.nwg, red, S);
-  if (st != BT_NOT_CONVERGED) return;
-  const double sigma = S[0], rho = S[1];
-  if (!(sigma > 0.0)) {
-    settle(a.ctl, a.ir ? BT_OK : (sigma == sigma ? BT_EBREAKDOWN
-                                                 : BT_ENONFINITE));
-    return;
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) a.ctl->it = i + 1;
-  const T al = (T)(rho / sigma);
-  for (int e = threadIdx.x; e < len; e += NT) {
+  auto one = [&](int e, T rv, T wv, T sv0, T uv, T pv0) {
     const int k = W.w0 + e / n;
     const size_t g = (size_t)W.w0 * n + e;
-    r[e] = r[e] - al * y[e];
+    const T sv = i == 0 ? wv : wv + be * sv0;
+    r[e] = rv - al * sv;
     if (k >= W.k0 && k < W.k1) {
-      a.xh[g] += al * p[g];
-      rout[g] = r[e];
+      const T pv = i == 0 ? uv : uv + be * pv0;
+      a.p[g] = pv;
+      a.xh[g] += al * pv;
+      st_sh(a.sbuf[cur] + g, sv);
+      st_sh(a.rbuf[nxt] + g, r[e]);
+    }
+  };
+  if (f) {
+#pragma unroll
+    for (int t = 0; t < PF; ++t) {
+      const int e = threadIdx.x + t * NT;
+      if (e < len) one(e, f->r[t], f->w[t], f->s[t], f->u[t], f->p[t]);
+    }
+  } else {
+    for (int e = threadIdx.x; e < len; e += NT) {
+      const int k = W.w0 + e / n;
+      const size_t g = (size_t)W.w0 * n + e;
+      const bool own = k >= W.k0 && k < W.k1;
+      one(e, ld_sh(a.rbuf[cur] + g), ld_sh(a.wbuf[cur] + g),
+          i == 0 ? T(0) : ld_sh(a.sbuf[nxt] + g), own ? a.u[g] : T(0),
+          own && i > 0 ? a.p[g] : T(0));
     }
   }
+  const FBlocks<T> F = stage_F(a, W.w0, W.w1 - 1, lds_F(a, red));
   __syncthreads();
-  if (!a.ir) {  // ||r|| = ||L rhat|| of the original system
-    double t2 = 0.0;
-    typename AccOf<T>::type acc;
-    acc.zero();
-    for (int e = threadIdx.x; e < (W.k1 - W.k0) * n; e += NT) {
-      const int k = W.k0 + e / n, ii = e % n;
-      const T t = lower(a.L, r + (k - W.w0) * n, n, k, ii);
-      acc.add_prod(t, t);
-    }
-    t2 = acc.value();
-    put_partial(a, P_NR2, t2, red);
-  }
-  const double rz = precond_own(a, F, W, r, y, w1, w2, z);
-  put_partial(a, (i + 1) & 1, rz, red);
+  u_and_w(a, F, W, nxt, !st.ir, wi, r, y, w1, w2, z, red);
+  __syncthreads();
 }
 
-// x = L^{-T} xhat (add = 0) or x += L^{-T} d (add = 1), own rows.
+// x = L^{-T} xhat * xscale (add = 0) or x += L^{-T} d * xscale, own rows.
 template <typename T>
-__global__ void __launch_bounds__(NT) k_g_x(GArgs<T> a, int add) {
-  extern __shared__ double red[];
-  const Win W = window(a.R, a.rb, 0);
+__device__ void ph_x(const GArgs<T>& a, const St& st, int add, int wi,
+                     double* red) {
+  const Win W = window(a.R, a.rb, 0, wi);
   const int n = a.n;
-  T* v = lds_vec<T>(red, 0, wlen(a.rb, a.depth, n));
+  T* v = lds_vec<T>(red, 0, wlen(a.rb, a.depth + 1, n));
   for (int e = threadIdx.x; e < (W.k1 - W.k0) * n; e += NT)
     v[e] = a.xh[(size_t)W.k0 * n + e];
   __syncthreads();
   for (int e = threadIdx.x; e < (W.k1 - W.k0) * n; e += NT) {
     const int k = W.k0 + e / n, i = e % n;
     const double u =
-        (double)lowerT(a.Li, v + (k - W.k0) * n, n, k, i) * a.xscale;
+        (double)lowerT(a.Li, v + (k - W.k0) * n, n, k, i) * st.xscale;
     const size_t g = (size_t)W.k0 * n + e;
-    a.x[g] = add ? a.x[g] + u : u;
+    st_sh(a.x + g, add ? ld_sh(a.x + g) + u : u);
   }
+  __syncthreads();
 }
 
-// r64 = b - A x in float64 from the record, own rows, and ||r64||^2.
+// r64 = b - A x in float64 from the record, own rows, ||r64||^2 and ||b||^2.
 template <typename T>
-__global__ void __launch_bounds__(NT) k_g_res(GArgs<T> a) {
-  extern __shared__ double red[];
-  const Win W = window(a.R, a.rb, 0);
+__device__ void ph_res(const GArgs<T>& a, int wi, double* red) {
+  const Win W = window(a.R, a.rb, 0, wi);
   const int n = a.n;
   const size_t nn = (size_t)n * n;
   double s2 = 0.0, b2 = 0.0;
@@ -539,46 +641,225 @@ __global__ void __launch_bounds__(NT) k_g_res(GArgs<T> a) {
     const double* xk = a.x + (size_t)k * n;
     double acc = 0.0;
     const size_t db = (size_t)k * nn + (size_t)i * n;
-    for (int j = 0; j < n; ++j) acc += rec(a.D, db + j, a.dtype) * xk[j];
+    for (int j = 0; j < n; ++j) acc += rec(a.D, db + j, a.dtype) * ld_sh(xk + j);
     if (k > 0) {
       const size_t ob = (size_t)(k - 1) * nn + i;
       for (int j = 0; j < n; ++j)
-        acc += rec(a.O, ob + (size_t)j * n, a.dtype) * xk[j - n];
+        acc += rec(a.O, ob + (size_t)j * n, a.dtype) * ld_sh(xk + j - n);
     }
     if (k < a.R - 1) {
       const size_t ob = (size_t)k * nn + (size_t)i * n;
       for (int j = 0; j < n; ++j)
-        acc += rec(a.O, ob + j, a.dtype) * xk[n + j];
+        acc += rec(a.O, ob + j, a.dtype) * ld_sh(xk + n + j);
     }
     const size_t g = (size_t)k * n + i;
     const double rv = a.b[g] - acc;
-    if (a.r64) a.r64[g] = rv;
+    st_sh(a.r64 + g, rv);
     s2 += rv * rv;
     b2 += a.b[g] * a.b[g];
   }
-  put_partial(a, P_RES, s2, red);
-  put_partial(a, P_NB2, b2, red);
+  put_partial(a, P_RES, wi, s2, red);
+  put_partial(a, P_NB2, wi, b2, red);
+  __syncthreads();
 }
 
-// Sums of the partial slots the host needs (fixed order, one workgroup).
+// x = 0 on the window's own rows.
 template <typename T>
-__global__ void __launch_bounds__(NT) k_g_sums(GArgs<T> a) {
+__device__ void ph_zero_x(const GArgs<T>& a, int wi) {
+  const Win W = window(a.R, a.rb, 0, wi);
+  for (int e = threadIdx.x; e < (W.k1 - W.k0) * a.n; e += NT)
+    st_sh(a.x + (size_t)W.k0 * a.n + e, 0.0);
+}
+
+__global__ void k_g_reset(Bar* bar) {
+  bar->count = 0u;
+  bar->abort = 0;
+}
+
+// The whole solve. Every workgroup runs the same control flow and takes
+// the same decisions; workgroup 0 writes the outcome.
+template <typename T>
+__global__ void __launch_bounds__(NT) k_g_solve(GArgs<T> a) {
   extern __shared__ double red[];
-  double S[3];
-  slot_sums<3>(a.part, {P_NB2, P_RES, P_NR2}, a.nwg, red, S);
-  if (threadIdx.x == 0) {
-    a.ctl->nb2 = S[0];
-    a.ctl->res = S[1];
-    a.ctl->nr2 = S[2];
+  __shared__ int s_flag;
+  Sync sync{a.bar, gridDim.x, 0u, a.spin_limit};
+  const int wg = blockIdx.x, nwg = gridDim.x;
+  auto each = [&](auto&& f) {
+    for (int wi = wg; wi < a.nwin; wi += nwg) f(wi);
+  };
+  // executed block products: halves of applications of C, triangular
+  // transforms, float64 residuals (halo rows a window recomputes are not
+  // counted)
+  long long g_half = 0, g_tri = 0, g_res = 0;
+  const bool none = a.pc == BT_PC_NONE;
+  const int apc = none ? 0
+                       : (a.a != 0.0 ? 1 : 0) + (a.m - 1) * (a.a != 0.0 ? 2 : 1);
+  int status = BT_NOT_CONVERGED, total = 0, outer = 0;
+  double nb2 = 0.0, nr2 = 0.0, nrt2 = 0.0;
+  bool aborted = false;
+  auto barrier = [&]() {
+    if (!aborted && !sync(&s_flag)) aborted = true;
+    return !aborted;
+  };
+  auto sums2 = [&](int s0, int s1, double* v0, double* v1) {
+    double S[2];
+    slot_sums<2>(a.part, {s0, s1}, a.nwin, red, S);
+    *v0 = S[0];
+    *v1 = S[1];
+  };
+  St st{a.b, 1.0, 1.0, a.tol, 0};
+  // one inner PCG solve from the right-hand side in st; returns the steps
+  // taken, or -1 when aborted
+  auto pcg = [&](int cap, int* settled) -> int {
+    each([&](int wi) { ph_init(a, st, wi, red); });
+    if (!barrier()) return -1;
+    int steps = 0;
+    double gprev = 0.0, aprev = 0.0;
+    // a workgroup with one window fetches its data before the decision
+    const bool pre = prefetchable(a) && a.nwin <= nwg;
+    for (int i = 0;; ++i) {
+      Pre<T> f;
+      if (pre && wg < a.nwin) ph_step_fetch(a, i, wg, f);
+      T al, be;
+      const int d = dec_step(a, st, i, i >= cap, red, &gprev, &aprev, &al, &be);
+      if (d != BT_NOT_CONVERGED) {
+        *settled = d == kCapped ? BT_NOT_CONVERGED : d;
+        break;
+      }
+      steps = i + 1;
+      each([&](int wi) { ph_step(a, st, i, al, be, wi, pre ? &f : nullptr, red); });
+      if (!barrier()) return -1;
+    }
+    // per step (and at the start): u = M^{-1} r and w = A u
+    g_half += 2 * ((long long)(apc + 1) * (steps + 1));
+    g_tri += 2 + (none ? 2 * (long long)(steps + 1) : 0) + (st.ir ? 0 : steps);
+    return steps;
+  };
+
+  if (a.fail[0] != BT_NO_FAIL) {  // a D_k is not positive definite
+    each([&](int wi) { ph_zero_x(a, wi); });
+    status = BT_ENOTSPD;
+  } else if (!a.refine) {
+    int add = 0;
+    outer = 1;
+    if (a.from_res) {
+      // from the initial guess x0 (held in x; 0 when not warm): plain PCG
+      // on the correction A d = r0 = b - A x0, the test ||r|| <= tol ||b||
+      // carried over to the correction's right-hand side
+      if (!a.warm) {
+        each([&](int wi) { ph_zero_x(a, wi); });
+        barrier();
+      }
+      if (!aborted) each([&](int wi) { ph_res(a, wi, red); });
+      barrier();
+      ++g_res;
+      double nr02 = 0.0;
+      if (!aborted) sums2(P_NB2, P_RES, &nb2, &nr02);
+      nr2 = nrt2 = nr02;
+      if (aborted) {
+      } else if (!(nb2 < INFINITY) || !(nr02 < INFINITY)) {
+        status = BT_ENONFINITE;
+      } else if (nb2 == 0.0) {  // b = 0: x = 0
+        each([&](int wi) { ph_zero_x(a, wi); });
+        status = BT_OK;
+        nr2 = nrt2 = 0.0;
+      } else if (nr02 <= a.tol * a.tol * nb2) {
+        status = BT_OK;
+      } else {
+        st.src = a.r64;
+        st.tol_in = a.tol * sqrt(nb2 / nr02);
+        st.sscale = bt_unit_scale(nr02);
+        st.xscale = 1.0 / st.sscale;
+        add = 1;
+      }
+    }
+    if (status == BT_NOT_CONVERGED && !aborted) {
+      int settled = BT_NOT_CONVERGED;
+      const int steps = pcg(a.maxit, &settled);
+      if (steps >= 0) {
+        total = steps;
+        status = settled;
+        double nr2s = 0.0, unused = 0.0;
+        sums2(P_N + (steps & 1), P_NB2, &nr2s, &unused);
+        each([&](int wi) { ph_x(a, st, add, wi, red); });
+        if (barrier()) {
+          each([&](int wi) { ph_res(a, wi, red); });
+          if (barrier()) {
+            ++g_res;
+            double b2 = 0.0;
+            sums2(P_NB2, P_RES, &b2, &nrt2);
+            const double nr02 = nr2;
+            nb2 = b2;
+            nr2 = total > 0 ? nr2s * st.xscale * st.xscale
+                            : (a.from_res ? nr02 : b2);
+            // the test after the last permitted step (the q phase runs it
+            // at the start of the next step, which the cap did not reach)
+            if (status == BT_NOT_CONVERGED && total > 0 &&
+                nr2 <= a.tol * a.tol * nb2)
+              status = BT_OK;
+          }
+        }
+      }
+    }
+  } else {
+    // float inner PCG inside float64 refinement on the record
+    st.ir = 1;
+    st.src = a.r64;
+    if (!a.warm) {
+      each([&](int wi) { ph_zero_x(a, wi); });
+      barrier();
+    }
+    while (!aborted) {
+      each([&](int wi) { ph_res(a, wi, red); });
+      if (!barrier()) break;
+      if (outer > 0 || a.warm) ++g_res;  // the first pass from 0 reads b only
+      double b2 = 0.0;
+      sums2(P_NB2, P_RES, &b2, &nr2);
+      if (outer == 0) nb2 = b2;
+      nrt2 = nr2;
+      if (a.warm && outer == 0 && nb2 == 0.0) {  // b = 0: x = 0
+        each([&](int wi) { ph_zero_x(a, wi); });
+        nr2 = nrt2 = 0.0;
+        status = BT_OK;
+        break;
+      }
+      if (nr2 <= a.tol * a.tol * nb2) { status = BT_OK; break; }
+      if (!(nr2 < INFINITY)) { status = BT_ENONFINITE; break; }
+      if (outer >= a.max_outer || total >= a.maxit) break;
+      st.sscale = bt_unit_scale(nr2);
+      st.xscale = 1.0 / st.sscale;
+      int settled = BT_NOT_CONVERGED;
+      const int steps = pcg(a.maxit - total, &settled);
+      if (steps < 0) break;
+      total += steps;
+      each([&](int wi) { ph_x(a, st, 1, wi, red); });
+      if (!barrier()) break;
+      ++outer;
+      if (steps == 0) {
+        status = BT_EBREAKDOWN;
+        each([&](int wi) { ph_res(a, wi, red); });
+        if (!barrier()) break;
+        ++g_res;
+        sums2(P_RES, P_NB2, &nr2, &b2);
+        nrt2 = nr2;
+        break;
+      }
+    }
+  }
+  if (aborted) status = BT_ETIMEOUT;
+  if (wg == 0 && threadIdx.x == 0) {
+    const bool spd = status != BT_ENOTSPD;
+    bt_info* inf = a.info;
+    inf->status = status;
+    inf->iters = total;
+    inf->outer = spd ? outer : 0;
+    inf->fail_index = spd ? -1 : a.fail[0];
+    inf->relres = !spd ? NAN : nb2 > 0.0 ? sqrt(nr2 / nb2) : 0.0;
+    inf->relres_true = !spd ? NAN : nb2 > 0.0 ? sqrt(nrt2 / nb2) : 0.0;
+    inf->gemv_exec = spd ? bt_gemv_rows(a.R, g_half, g_tri, g_res) : 0;
+    inf->gemv_paper = (int64_t)total * bt_gemv_g(a.pc, a.a, a.m);
   }
 }
-
-template <typename T>
-struct Plan {
-  GArgs<T> a;
-  size_t lds;
-  int grid;
-};
 
 inline int depth_of(const bt_params& p) {
   if (p.pc == BT_PC_NONE) return 0;
@@ -586,276 +867,114 @@ inline int depth_of(const bt_params& p) {
   return d1 + (p.m - 1) * dh;
 }
 
-inline int rows_per_wg(int64_t R) {
+inline int rows_per_win(int64_t R) {
   return (int)std::max<int64_t>(4, std::min<int64_t>(16, R / 64));
 }
 
-// Scratch layout: seven T vectors (p twice, r twice, q, z, xhat), the
-// float64 residual, the partial sums, the control block.
+// Scratch layout: nine T vectors (r, s and w twice, u, p, xhat), the
+// float64 residual, the partial sums, the barrier.
+constexpr int NVEC = 9;
 template <typename T>
 struct Scratch {
-  size_t r64, part, ctl, total;
+  size_t r64, part, bar, total;
   Scratch(int64_t R, int n) {
-    const int nwg = (int)((R + rows_per_wg(R) - 1) / rows_per_wg(R));
+    const int rb = rows_per_win(R);
+    const int nwin = (int)((R + rb - 1) / rb);
     const size_t v = (size_t)R * n;
-    r64 = (7 * v * sizeof(T) + 255) / 256 * 256;
+    r64 = (NVEC * v * sizeof(T) + 255) / 256 * 256;
     part = r64 + v * sizeof(double);
-    ctl = part + (size_t)P_SLOTS * nwg * sizeof(double);
-    total = ctl + sizeof(Ctl);
+    bar = (part + (size_t)P_SLOTS * nwin * sizeof(double) + 255) / 256 * 256;
+    total = bar + sizeof(Bar);
   }
 };
 
-template <typename T, typename K, typename... Args>
-hipError_t launch(K kernel, const Plan<T>& pl, hipStream_t s, Args... args) {
-  hipLaunchKernelGGL(kernel, dim3(pl.grid), dim3(NT), pl.lds, s, pl.a,
-                     args...);
-  return hipGetLastError();
-}
-
+// Workgroups of k_g_solve that fit on the device at once with ``lds`` bytes
+// of LDS each (the grid never exceeds it: the barrier needs them all).
 template <typename T>
-hipError_t set_lds(size_t lds) {
-  // the size depends on the system, so the limit is set on every call that
-  // needs more than the default (a few runtime calls per solve)
-  if (lds <= 65536) return hipSuccess;
-  const void* fns[] = {(const void*)k_g_init<T>, (const void*)k_g_q<T>,
-                       (const void*)k_g_u<T>, (const void*)k_g_x<T>,
-                       (const void*)k_g_res<T>, (const void*)k_g_sums<T>};
-  for (const void* f : fns) {
-    const hipError_t e = hipFuncSetAttribute(
-        f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
+int coresident(size_t lds) {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                            dev) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per, (const void*)k_g_solve<T>, NT, lds) != hipSuccess)
+    return 0;
+  return cus * per;
 }
 
 template <typename T>
 int run(const bt_handle* h, const double* b, double* x, double tol, int maxit,
-        bt_info* info, void* ws, hipStream_t s) {
+        bt_info* info, void* ws, long long spin_limit, hipStream_t s) {
   const int64_t R = h->R;
   const int n = h->n;
-  Plan<T> pl{};
-  GArgs<T>& a = pl.a;
+  GArgs<T> a{};
   a.R = (int)R;
   a.n = n;
-  a.rb = rows_per_wg(R);
-  a.nwg = (int)((R + a.rb - 1) / a.rb);
+  a.rb = rows_per_win(R);
+  a.nwin = (int)((R + a.rb - 1) / a.rb);
   a.depth = depth_of(h->p);
   a.pc = h->p.pc;
   a.m = h->p.m;
   a.a = h->p.a;
   for (int i = 0; i < BT_MAX_M; ++i) a.alpha[i] = i == 0 ? 1.0 : h->p.alpha[i];
-  a.ir = 0;
   a.dtype = h->dtype;
   a.tol = tol;
   a.itol = h->p.inner_tol;
-  a.sscale = a.xscale = 1.0;
+  a.refine = h->p.prec == BT_F32_IR || h->p.prec == BT_BF16X2_IR;
+  a.warm = h->p.warm_start != 0;
+  // float32 without refinement also starts from the residual of x0 = 0,
+  // which gives ||b|| before the iteration, so that its right-hand side can
+  // be scaled (float64 needs no scaling and saves the pass)
+  a.from_res = !a.refine && (a.warm || sizeof(T) == sizeof(float));
+  a.max_outer = h->p.max_outer;
+  a.maxit = maxit;
+  a.spin_limit = spin_limit;
   a.F = (const T*)h->F;
   a.L = (const T*)h->L;
   a.Li = (const T*)h->Li;
   a.D = h->D;
   a.O = h->O;
+  a.fail = h->fail;
   a.b = b;
   a.x = x;
+  a.info = info;
   const size_t v = (size_t)R * n;
   T* f = (T*)ws;
-  a.pb[0] = f;
-  a.pb[1] = f + v;
-  a.rbuf[0] = f + 2 * v;
-  a.rbuf[1] = f + 3 * v;
-  a.q = f + 4 * v;
-  a.z = f + 5 * v;
-  a.xh = f + 6 * v;
+  a.rbuf[0] = f;
+  a.rbuf[1] = f + v;
+  a.sbuf[0] = f + 2 * v;
+  a.sbuf[1] = f + 3 * v;
+  a.wbuf[0] = f + 4 * v;
+  a.wbuf[1] = f + 5 * v;
+  a.u = f + 6 * v;
+  a.p = f + 7 * v;
+  a.xh = f + 8 * v;
   const Scratch<T> sl(R, n);
   a.r64 = (double*)((unsigned char*)ws + sl.r64);
   a.part = (double*)((unsigned char*)ws + sl.part);
-  a.ctl = (Ctl*)((unsigned char*)ws + sl.ctl);
-  pl.grid = a.nwg;
-  pl.lds = NT * sizeof(double) +
-           5 * (size_t)wlen(a.rb, a.depth, n) * sizeof(T);
-  const size_t fb = fstage_bytes<T>(a.rb, a.depth, n);
-  if (fb <= FSTAGE_MAX) pl.lds += fb;
-  if (set_lds<T>(pl.lds) != hipSuccess) return BT_EHIP;
-
-  Ctl ctl{};
-  // parts: first sum the partial slots on the device (k_g_sums)
-  auto sync_state = [&](bool parts) -> bool {
-    if (parts && launch(k_g_sums<T>, pl, s) != hipSuccess) return false;
-    if (hipMemcpyAsync(&ctl, a.ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s) !=
-        hipSuccess)
-      return false;
-    return hipStreamSynchronize(s) == hipSuccess;
-  };
-  auto host_slot = [&](int slot) {
-    return slot == P_NB2 ? ctl.nb2 : slot == P_RES ? ctl.res : ctl.nr2;
-  };
-  // inner loop: steps until the control block is settled or ``cap`` steps.
-  // The first check comes after as many steps as the last inner solve on
-  // this handle took (steps launched after the settling return at once),
-  // later ones every CHUNK steps.
-  auto iterate = [&](int cap, int* steps) -> bool {
-    int i = 0;
-    int chunk = std::max(CHUNK, h->grid_hint);
-    for (;;) {
-      const int stop = std::min(cap, i + chunk);
-      chunk = CHUNK;
-      for (; i < stop; ++i) {
-        if (launch(k_g_q<T>, pl, s, i) != hipSuccess ||
-            launch(k_g_u<T>, pl, s, i) != hipSuccess)
-          return false;
-      }
-      if (!sync_state(false)) return false;
-      if (ctl.status != BT_NOT_CONVERGED || i >= cap) break;
-    }
-    *steps = ctl.it;
-    h->grid_hint = ctl.it;
-    return true;
-  };
-
-  int status = BT_NOT_CONVERGED, total = 0, outer = 0;
-  double nb2 = 0.0, nr2 = 0.0, nrt2 = 0.0;
-  const bool refine = h->p.prec == BT_F32_IR || h->p.prec == BT_BF16X2_IR;
-  // executed block products: halves of applications of C, triangular
-  // transforms, float64 residuals (halo rows recomputed by a workgroup are
-  // not counted)
-  int64_t g_half = 0, g_tri = 0, g_res = 0;
-  const bool none = a.pc == BT_PC_NONE;
-  const int apc = none ? 0
-                       : (a.a != 0.0 ? 1 : 0) + (a.m - 1) * (a.a != 0.0 ? 2 : 1);
-  // one inner solve of ``steps`` steps: k_g_init (L^{-1} s, z = M^{-1} r),
-  // per step q = Ahat p and z = M^{-1} r (and ||L r|| without refinement),
-  // then k_g_x (L^{-T})
-  auto count_inner = [&](int steps) {
-    g_half += 2 * ((int64_t)apc * (steps + 1) + steps);
-    g_tri += 2 + (none ? 2 * (int64_t)(steps + 1) : 0) + (a.ir ? 0 : steps);
-  };
-  const bool warm = h->p.warm_start != 0;
-  // float32 without refinement also starts from the residual of x0 = 0,
-  // which gives ||b|| before the iteration, so that its right-hand side can
-  // be scaled (float64 needs no scaling and saves the pass)
-  const bool from_res = warm || sizeof(T) == sizeof(float);
-  if (!refine && from_res) {
-    // from the initial guess x0 (held in x): plain PCG on the correction,
-    // A d = r0 = b - A x0, with the test ||r|| <= tol ||b|| carried over to
-    // the correction's right-hand side
-    if (!warm && hipMemsetAsync(x, 0, v * sizeof(double), s) != hipSuccess)
-      return BT_EHIP;
-    if (launch(k_g_res<T>, pl, s) != hipSuccess || !sync_state(true))
-      return BT_EHIP;
-    ++g_res;
-    nb2 = host_slot(P_NB2);
-    const double nr02 = host_slot(P_RES);
-    nr2 = nrt2 = nr02;
-    outer = 1;
-    if (!(nb2 < INFINITY) || !(nr02 < INFINITY)) {
-      status = BT_ENONFINITE;
-    } else if (nb2 == 0.0) {  // b = 0: x = 0
-      if (hipMemsetAsync(x, 0, v * sizeof(double), s) != hipSuccess)
-        return BT_EHIP;
-      status = BT_OK;
-      nr2 = nrt2 = 0.0;
-    } else if (nr02 <= tol * tol * nb2) {
-      status = BT_OK;
-    } else {
-      a.src = a.r64;
-      a.tol = tol * std::sqrt(nb2 / nr02);
-      a.sscale = bt_unit_scale(nr02);
-      a.xscale = 1.0 / a.sscale;
-      if (launch(k_g_init<T>, pl, s) != hipSuccess) return BT_EHIP;
-      int steps = 0;
-      if (!iterate(maxit, &steps)) return BT_EHIP;
-      status = ctl.status;
-      total = steps;
-      count_inner(steps);
-      double* r64 = a.r64;
-      a.r64 = nullptr;
-      if (launch(k_g_x<T>, pl, s, 1) != hipSuccess ||
-          launch(k_g_res<T>, pl, s) != hipSuccess || !sync_state(true))
-        return BT_EHIP;
-      ++g_res;
-      a.r64 = r64;
-      nr2 = total > 0 ? host_slot(P_NR2) * a.xscale * a.xscale : nr02;
-      nrt2 = host_slot(P_RES);
-      if (status == BT_NOT_CONVERGED && total > 0 && nr2 <= tol * tol * nb2)
-        status = BT_OK;
-    }
-  } else if (!refine) {
-    // plain PCG in the precision of the factors
-    a.src = b;
-    if (launch(k_g_init<T>, pl, s) != hipSuccess) return BT_EHIP;
-    int steps = 0;
-    if (!iterate(maxit, &steps)) return BT_EHIP;
-    status = ctl.status;
-    total = steps;
-    count_inner(steps);
-    outer = 1;
-    a.r64 = nullptr;
-    if (launch(k_g_x<T>, pl, s, 0) != hipSuccess ||
-        launch(k_g_res<T>, pl, s) != hipSuccess || !sync_state(true))
-      return BT_EHIP;
-    ++g_res;
-    nb2 = host_slot(P_NB2);
-    nr2 = total > 0 ? host_slot(P_NR2) : nb2;
-    nrt2 = host_slot(P_RES);
-    // the test after the last permitted step (the kernels run it at the
-    // start of the next step, which is not launched)
-    if (status == BT_NOT_CONVERGED && total > 0 && nr2 <= tol * tol * nb2)
-      status = BT_OK;
-  } else {
-    // float inner PCG inside float64 refinement on the record
-    a.ir = 1;
-    if (!warm && hipMemsetAsync(x, 0, v * sizeof(double), s) != hipSuccess)
-      return BT_EHIP;
-    for (;;) {
-      if (launch(k_g_res<T>, pl, s) != hipSuccess || !sync_state(true))
-        return BT_EHIP;
-      if (outer > 0 || warm) ++g_res;  // the first pass from 0 reads b only
-      nr2 = host_slot(P_RES);
-      if (outer == 0) nb2 = host_slot(P_NB2);
-      nrt2 = nr2;
-      if (warm && outer == 0 && nb2 == 0.0) {  // b = 0: x = 0
-        if (hipMemsetAsync(x, 0, v * sizeof(double), s) != hipSuccess)
-          return BT_EHIP;
-        nr2 = nrt2 = 0.0;
-        status = BT_OK;
-        break;
-      }
-      if (nr2 <= tol * tol * nb2) { status = BT_OK; break; }
-      if (!(nr2 < INFINITY)) { status = BT_ENONFINITE; break; }
-      if (outer >= h->p.max_outer || total >= maxit) break;
-      a.src = a.r64;
-      a.sscale = bt_unit_scale(nr2);
-      a.xscale = 1.0 / a.sscale;
-      if (launch(k_g_init<T>, pl, s) != hipSuccess) return BT_EHIP;
-      int steps = 0;
-      if (!iterate(maxit - total, &steps)) return BT_EHIP;
-      total += steps;
-      count_inner(steps);
-      if (launch(k_g_x<T>, pl, s, 1) != hipSuccess) return BT_EHIP;
-      ++outer;
-      if (steps == 0) {
-        status = BT_EBREAKDOWN;
-        if (launch(k_g_res<T>, pl, s) != hipSuccess || !sync_state(true))
-          return BT_EHIP;
-        ++g_res;
-        nrt2 = nr2 = host_slot(P_RES);
-        break;
-      }
-    }
-  }
-  bt_info hi{};
-  hi.status = status;
-  hi.iters = total;
-  hi.outer = outer;
-  hi.fail_index = -1;
-  hi.relres = nb2 > 0.0 ? std::sqrt(nr2 / nb2) : 0.0;
-  hi.relres_true = nb2 > 0.0 ? std::sqrt(nrt2 / nb2) : 0.0;
-  hi.gemv_exec = bt_gemv_rows(a.R, g_half, g_tri, g_res);
-  hi.gemv_paper = (int64_t)total * bt_gemv_g(a.pc, a.a, a.m);
-  if (hipMemcpyAsync(info, &hi, sizeof(hi), hipMemcpyHostToDevice, s) !=
-          hipSuccess ||
-      hipStreamSynchronize(s) != hipSuccess)
+  a.bar = (Bar*)((unsigned char*)ws + sl.bar);
+  size_t lds = NT * sizeof(double) +
+               5 * (size_t)wlen(a.rb, a.depth + 1, n) * sizeof(T);
+  const size_t fb = fstage_bytes<T>(a.rb, a.depth + 1, n);
+  if (fb <= FSTAGE_MAX) lds += fb;
+  static std::atomic<uint64_t> attr{0};
+  if (lds > 65536 &&
+      lds_limit((const void*)k_g_solve<T>, 160 * 1024, attr) != hipSuccess)
     return BT_EHIP;
-  return BT_OK;
+  const int res = coresident<T>(lds);
+  if (res < 1) return BT_EHIP;
+  const int grid = std::min(a.nwin, res);
+  hipLaunchKernelGGL(k_g_reset, dim3(1), dim3(1), 0, s, a.bar);
+  if (hipGetLastError() != hipSuccess) return BT_EHIP;
+  // a cooperative launch: all workgroups resident at once (the barrier
+  // needs them; its bounded wait turns a violation into BT_ETIMEOUT)
+  void* args[] = {&a};
+  return hipLaunchCooperativeKernel((const void*)k_g_solve<T>, dim3(grid),
+                                    dim3(NT), args, (unsigned)lds, s) ==
+                 hipSuccess
+             ? BT_OK
+             : BT_EHIP;
 }
 
 }  // namespace btg
@@ -868,9 +987,18 @@ size_t bt_grid_scratch_bytes(const bt_handle* h) {
 
 int bt_grid_solve(const bt_handle* h, const double* b, double* x, double tol,
                   int maxit, bt_info* info, void* ws, hipStream_t s) {
+  // the barrier's wait limit in ticks of the device's wall clock
+  int dev = 0, khz = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) !=
+          hipSuccess ||
+      khz <= 0)
+    khz = 100000;  // 100 MHz
+  const double ticks = h->grid_wait_s * 1e3 * khz;
+  const long long lim = ticks < 9e18 ? (long long)ticks : (long long)9e18;
   if (h->p.prec == BT_F64)
-    return btg::run<double>(h, b, x, tol, maxit, info, ws, s);
-  return btg::run<float>(h, b, x, tol, maxit, info, ws, s);
+    return btg::run<double>(h, b, x, tol, maxit, info, ws, lim, s);
+  return btg::run<float>(h, b, x, tol, maxit, info, ws, lim, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -880,8 +1008,8 @@ int bt_grid_solve(const bt_handle* h, const double* b, double* x, double tol,
 // a device address: host code uses the address that hipGetSymbolAddress
 // returns for the current device, taken once per device and kept below.
 // Every call on a GPU shares that GPU's array (calls that overlap on one GPU
-// race); the grid kernels initialise everything they read before reading it
-// (control block in k_g_init, partial slots before their sums, p and the
+// race); the solve initialises everything it reads before reading it (the
+// barrier state in k_g_reset, partial slots before their sums, p and the
 // correction at step 0), so nothing has to start at zero.
 static __device__ __align__(256) unsigned char scratch[BT_GRID_NOALLOC_MAX_BYTES];
 

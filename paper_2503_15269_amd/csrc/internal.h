@@ -9,16 +9,11 @@
 #include <vector>
 
 #include "btpcg.h"
+#include "validate.h"
 
 #define BT_NO_FAIL 0x7fffffff
-// Variants of the register-resident bin kernel (3, 6, 12 entries per lane).
-#define BT_FAST_VARIANTS 3
 
 // Host-side handle. Device pointers point into the caller's workspace.
-// Entries of a packed lower triangle of an n x n block, rows one after the
-// other (row i holds entries (i, 0..i)), padded to whole 16-byte chunks of
-// float32 (n = 12: 78 entries, 80 stored).
-constexpr int li_packed_len(int n) { return (n * (n + 1) / 2 + 3) / 4 * 4; }
 
 struct bt_handle {
   int B = 0, n = 0, dtype = 0, maxN = 0;
@@ -48,9 +43,9 @@ struct bt_handle {
   // L is current (the register-resident kernel does not read it; for the
   // other kernels it is computed on first use)
   mutable bool full_valid = false;
-  // grid-wide solve: PCG steps of the last inner solve on this handle, the
-  // number of steps launched before the first check of the next one
-  mutable int grid_hint = 0;
+  // grid-wide solve: longest wait at one of its grid barriers before the
+  // solve gives up (BT_ETIMEOUT), in seconds
+  double grid_wait_s = 2.0;
   std::vector<int64_t> off_host;
 };
 

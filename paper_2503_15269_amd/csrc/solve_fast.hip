@@ -116,6 +116,7 @@ struct Smem {
   using G = Geo<NB, EPT>;
   float V[2][G::RPB * G::ROW];  // staged vector rows
   float T[2][G::RPB * G::ROW];  // transposed sums for row k+1
+  float Z[G::ROW];              // zeros: the "previous row" of a first row
   double xs[G::RPB * NB];       // float64 iterate of the bin
   AccF redF[SL][MAXW];
   double redD[SL][MAXW];
@@ -319,15 +320,14 @@ struct Ctx {
     const float* vr = &sm.V[BUF][rp * G::ROW];
     float acc[EPT];
     {
-      const float* tr = &sm.T[BUF][(k > 0 ? lrow - 1 : lrow) * G::ROW];
-      const float keep = k > 0 ? 1.f : 0.f;
+      const float* tr = k > 0 ? &sm.T[BUF][(lrow - 1) * G::ROW] : sm.Z;
 #pragma unroll
       for (int h = 0; h < G::SUB; ++h) {
         const float4 u =
             *reinterpret_cast<const float4*>(tr + 4 * (G::SUB * q + h));
-        acc[3 * h] = keep * u.x;
-        acc[3 * h + 1] = keep * u.y;
-        acc[3 * h + 2] = keep * u.z;
+        acc[3 * h] = u.x;
+        acc[3 * h + 1] = u.y;
+        acc[3 * h + 2] = u.z;
       }
     }
 #pragma unroll
@@ -466,6 +466,7 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
   c.sf = 0;
   c.sd = 0;
   if (t == 0) sm.active = 0;
+  if (t < G::ROW) sm.Z[t] = 0.f;
   __syncthreads();
   c.seen = 0;
   const size_t nn = (size_t)NB * NB;
@@ -778,7 +779,9 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
 #pragma unroll
         for (int e = 0; e < EPT; ++e) u[e] = z[e] - u[e];
         if (act) {
-          const float be = first ? 0.f : (float)(rho1 / rho);
+          // the step sizes only scale float32 vectors: a float32 quotient
+          // (reciprocal and product) is accurate enough
+          const float be = first ? 0.f : __fdividef((float)rho1, (float)rho);
 #pragma unroll
           for (int e = 0; e < EPT; ++e) {
             p[e] = __fmaf_rn(be, p[e], z[e]);
@@ -790,7 +793,7 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
         const double sigma = c.dot(p, qv, act);
         if (act && !(sigma > 0.0)) act = false;
         if (act) {
-          const float al = (float)(rho / sigma);
+          const float al = __fdividef((float)rho, (float)sigma);
 #pragma unroll
           for (int e = 0; e < EPT; ++e) {
             d[e] = __fmaf_rn(al, p[e], d[e]);

@@ -201,10 +201,10 @@ def test_grid_argument_checks():
 
 
 @pytest.mark.parametrize("prec", ["f64", "f32_ir"])
-def test_grid_repeated_solves_and_cap_below_the_hint(prec):
-    """A handle launches as many steps as its last solve took before the
-    first check: repeated solves give the same result bit for bit, and an
-    iteration cap below that count still stops the iteration exactly."""
+def test_grid_repeated_solves_and_iteration_cap(prec):
+    """Repeated solves on one handle give the same result bit for bit (the
+    barrier state and every partial are reset or rewritten per solve), and
+    an iteration cap stops the iteration exactly."""
     import torch
     d = lqrgen.lqr_instance(300, 12, 4, 17, 3)
     P = bt.Params.polycoeff(2, prec=prec)
@@ -228,3 +228,45 @@ def test_grid_repeated_solves_and_cap_below_the_hint(prec):
         xr, ri = orc.pcg(d["D"], d["O"], d["b"], tol=1e-30, maxit=3,
                          **oracle_kind(P))
         assert rel(x.cpu().numpy().reshape(xr.shape), xr) <= 1e-10
+
+
+@pytest.mark.parametrize("N,n", [(300, 12), (40000, 6), (2000, 48)])
+def test_grid_more_windows_than_resident_workgroups(N, n):
+    """Systems with more row windows than one pass of the grid holds: each
+    workgroup loops over several windows; float64 counts equal the oracle's
+    where the oracle finishes quickly, otherwise the true residual and the
+    error against the direct solve."""
+    d = lqrgen.lqr_instance(N, n, max(1, n // 3), 29, N, s=0.05)
+    P = bt.Params.polycoeff(2)
+    x, info, _ = grid_solve(d["D"], d["O"], d["b"], P)
+    assert info[0]["status"] == bt.OK, info
+    assert true_relres(d["D"], d["O"], d["b"], x) <= F64_TRUE_RES
+    assert_close(x, orc.btchol_solve(d["D"], d["O"], d["b"]), 1e-7,
+                 "against the direct solve")
+    if N * n <= 4000:
+        xr, ri = orc.pcg(d["D"], d["O"], d["b"], tol=1e-10, **oracle_kind(P))
+        assert iteration_match(int(info[0]["iters"]), ri), (info, ri)
+
+
+def test_grid_barrier_gives_up_and_the_handle_recovers():
+    """A barrier wait limit of zero makes a grid barrier give up: every
+    workgroup returns, the solve reports ETIMEOUT, and the next solve with
+    the default limit on the same handle is correct."""
+    import torch
+    d = lqrgen.lqr_instance(512, 12, 4, 31, 0)
+    P = bt.Params.polycoeff(2)
+    h = bt.Handle(to_dev(d["D"], torch.float64), to_dev(d["O"], torch.float64),
+                  None, P)
+    b = to_dev(d["b"].reshape(-1), torch.float64)
+    h.set_grid_wait(0.0)
+    x, info = h.solve_grid(b)
+    torch.cuda.synchronize()
+    assert bt.infos_to_numpy(info)[0]["status"] == bt.ETIMEOUT
+    h.set_grid_wait(2.0)
+    x, info = h.solve_grid(b)
+    torch.cuda.synchronize()
+    inf = bt.infos_to_numpy(info)[0]
+    xr, ri = orc.pcg(d["D"], d["O"], d["b"], tol=1e-10, **oracle_kind(P))
+    assert inf["status"] == bt.OK and iteration_match(int(inf["iters"]), ri)
+    if inf["iters"] == ri["iters"]:
+        assert_close(x.cpu().numpy().reshape(-1, 12), xr, 1e-10, "after")
