@@ -374,7 +374,8 @@ class Handle:
 
     def solve_direct(self, b, x=None, info=None, scratch=None, stream=None):
         """x = A^{-1} b for every system by block Cholesky (float64, no
-        preconditioner, no iteration); n <= 16. Returns (x, info)."""
+        preconditioner, no iteration); n in 1..16, 24, 32, 48, 64. Returns
+        (x, info)."""
         torch = _torch()
         b = self._vec(b, "b")
         lib = load_library()
