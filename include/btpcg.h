@@ -237,14 +237,18 @@ int bt_solve_mrhs(const bt_handle* h, int nrhs, const double* b, double* x,
  * instance of the handle, in float64 from the system of record:
  * S_0 = D_0, S_k = D_k - M_k M_k^T, L_k = chol(S_k), M_k = O_{k-1}^T
  * L_{k-1}^{-T}; forward and backward substitution. Independent of the
- * preconditioner parameters; n in 1..16, 24, 32, 48 or 64. One wavefront
- * per instance, lane i holding row i of the current blocks, the Cholesky
- * pivots and the substitutions carried between lanes in registers.
+ * preconditioner parameters; n in 1..16, 24, 32, 48 or 64. For n <= 16
+ * four instances share a wavefront, one per row of 16 lanes, lane c holding
+ * column c of the current blocks, with values moved between columns by DPP
+ * broadcasts fused into the float64 FMAs; above 16, one wavefront per
+ * instance, lane i holding row i, with readlane broadcasts. No square roots
+ * are taken for n <= 16 (unscaled Schur complements, pivots 1 / d).
  * b, x: device [R][n] float64. info:
  * device, B entries (status BT_OK or BT_ENOTSPD with fail_index = the block
  * row whose Schur complement is not positive definite; iters = 0; relres
  * fields NaN, not computed). scratch: device, >= bt_direct_workspace_bytes
- * (the factors L_k and M_k, 2 R n^2 float64). Asynchronous on the stream.
+ * (the factors of every block row, (2 n^2 + n) R float64). Asynchronous
+ * on the stream.
  * Errors: BT_EINVAL (another n, NULL pointers), BT_ENOSPACE, BT_EHIP. */
 size_t bt_direct_workspace_bytes(const bt_handle* h);
 int bt_solve_direct(const bt_handle* h, const double* b, double* x,

@@ -19,6 +19,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "internal.h"
 
@@ -34,6 +35,7 @@ struct DirectArgs {
   double* x;
   double* Lbuf;  // [R][n][n] rows of L_k
   double* Mbuf;  // [R][n][n] rows of M_k (unused for a system's first row)
+  double* Rbuf;  // [R][n] 1 / d_c, the pivots of S_k (n <= 16)
   bt_info* info;
 };
 
@@ -229,8 +231,348 @@ __global__ void __launch_bounds__(64) k_direct(DirectArgs a) {
   }
 }
 
+// ------------------------------------------------------------------------
+// n <= 16: four systems per wavefront, one per row of 16 lanes, lane c of a
+// row holding column c of that system's current blocks. A value from
+// another column j is taken with the DPP broadcast row_newbcast:j (lane j
+// of each row of 16 to the whole row), which the float64 FMA applies to its
+// first operand in the same instruction: every step of the sequential
+// horizon is register to register, with no readlane, LDS or memory on the
+// chain, and each instruction serves four systems.
+//
+// Column c keeps the lower-triangle entries S[r][c] (r >= c) and, above the
+// diagonal, the mirrored entries S[c][r], read from the lower triangle of
+// D_k. The factorisation runs on unscaled Schur complements (pivots d_j,
+// multipliers S[c][j] / d_j), so no square root is ever taken:
+//   L[r][c] = Sc[r][c] / sqrt(d_c),  y_c = vh_c / sqrt(d_c)
+// with Sc[r][c] the entries of column c at its own pivot and vh the
+// right-hand side there; the solves below use Sc, vh and 1 / d_c directly.
+// The solve for the next row's M^T = L_k^{-1} O_k and the update of its
+// right-hand side run inside the pivot loop of row k (pivot j finishes
+// column j of L_k, which is all step j of that solve needs), filling the
+// latency of the pivot chain.
+
+// row_newbcast is a 64-bit DPP form of the VOP1/VOP2 encodings; the
+// compiler does not form it, and it leaves the wait states of inline asm to
+// the author: each block starts with the two the DPP read of a VGPR written
+// by the previous VALU instruction requires.
+template <int L>
+__device__ __forceinline__ double nb(double v) {  // lane L of the row
+  double r;
+  asm("s_nop 1\n\tv_mov_b64_dpp %0, %1 row_newbcast:%2 row_mask:0xf "
+      "bank_mask:0xf"
+      : "=v"(r)
+      : "v"(v), "n"(L));
+  return r;
+}
+template <int L>
+__device__ __forceinline__ double fnb(double acc, double a, double b) {
+  // acc - a[lane L of the row] * b
+  asm("s_nop 1\n\tv_fmac_f64_dpp %0, %1, -%2 row_newbcast:%3 row_mask:0xf "
+      "bank_mask:0xf"
+      : "+v"(acc)
+      : "v"(a), "v"(b), "n"(L));
+  return acc;
+}
+// Four independent updates behind one pair of wait states (no instruction
+// of the block writes a register another one broadcasts).
+// acc_i -= acc_i[lane L] * b
+template <int L>
+__device__ __forceinline__ void self4(double& c0, double& c1, double& c2,
+                                      double& c3, double b) {
+  asm("s_nop 1\n\t"
+      "v_fmac_f64_dpp %0, %0, -%4 row_newbcast:%5 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %1, %1, -%4 row_newbcast:%5 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %2, %2, -%4 row_newbcast:%5 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %3, %3, -%4 row_newbcast:%5 row_mask:0xf bank_mask:0xf"
+      : "+v"(c0), "+v"(c1), "+v"(c2), "+v"(c3)
+      : "v"(b), "n"(L));
+}
+template <int L>
+__device__ __forceinline__ double self1(double c, double b) {
+  asm("s_nop 1\n\tv_fmac_f64_dpp %0, %0, -%1 row_newbcast:%2 row_mask:0xf "
+      "bank_mask:0xf"
+      : "+v"(c)
+      : "v"(b), "n"(L));
+  return c;
+}
+// acc_i -= a_i[lane L] * b
+template <int L>
+__device__ __forceinline__ void fnb4(double& c0, double& c1, double& c2,
+                                     double& c3, double a0, double a1,
+                                     double a2, double a3, double b) {
+  asm("s_nop 1\n\t"
+      "v_fmac_f64_dpp %0, %4, -%8 row_newbcast:%9 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %1, %5, -%8 row_newbcast:%9 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %2, %6, -%8 row_newbcast:%9 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %3, %7, -%8 row_newbcast:%9 row_mask:0xf bank_mask:0xf"
+      : "+v"(c0), "+v"(c1), "+v"(c2), "+v"(c3)
+      : "v"(a0), "v"(a1), "v"(a2), "v"(a3), "v"(b), "n"(L));
+}
+// acc_i -= a[lane L_i] * b
+template <int L0, int L1, int L2, int L3>
+__device__ __forceinline__ void gram4(double& c0, double& c1, double& c2,
+                                      double& c3, double a, double b) {
+  asm("s_nop 1\n\t"
+      "v_fmac_f64_dpp %0, %4, -%5 row_newbcast:%6 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %1, %4, -%5 row_newbcast:%7 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %2, %4, -%5 row_newbcast:%8 row_mask:0xf bank_mask:0xf\n\t"
+      "v_fmac_f64_dpp %3, %4, -%5 row_newbcast:%9 row_mask:0xf bank_mask:0xf"
+      : "+v"(c0), "+v"(c1), "+v"(c2), "+v"(c3)
+      : "v"(a), "v"(b), "n"(L0), "n"(L1), "n"(L2), "n"(L3));
+}
+
+// After code that may have written EXEC with a vector instruction (the
+// predicated stores), the five wait states a DPP instruction needs.
+__device__ __forceinline__ void dpp_exec_fence() {
+  asm volatile("s_nop 4" ::: "memory");
+}
+
+template <int B, int E, typename F>
+__device__ __forceinline__ void sfor(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    sfor<B + 1, E>(f);
+  }
+}
+
+// 1 / d: the hardware estimate and two Newton steps y <- y + y (1 - d y).
+__device__ __forceinline__ double rcp_nr(double d) {
+  double y = __builtin_amdgcn_rcp(d);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) y = fma(y, fma(-d, y, 1.0), y);
+  return y;
+}
+
+// Waves per workgroup. Each wave is bound by its own instruction issue (a
+// lone wave issues a float64 FMA about every 7.5 cycles, a DPP FMA behind
+// its wait states about every 9 to 15), and waves sharing a CU slow each
+// other down even on different SIMDs: one-wave workgroups, spread over as
+// many CUs as the batch allows, measured fastest.
+constexpr int kDirectWaves = 1;
+
+template <int NB, typename Rec>
+__global__ void __launch_bounds__(64 * kDirectWaves) k_direct4(DirectArgs a) {
+  constexpr int NN = NB * NB;
+  const int lane = threadIdx.x & 63;
+  const int q = lane >> 4, c = lane & 15;
+  const int cc = c < NB ? c : NB - 1;  // lanes past the block mirror NB - 1
+  const int slot = (blockIdx.x * kDirectWaves + (threadIdx.x >> 6)) * 4 + q;
+  const bool live = slot < a.B;
+  const int sys = a.order[live ? slot : a.B - 1];
+  const int64_t r0 = a.off[sys];
+  const int Ns = (int)(a.off[sys + 1] - r0);
+  const int N = live ? Ns : 0;
+  const int Nw = max(max(__builtin_amdgcn_readlane(N, 0),
+                         __builtin_amdgcn_readlane(N, 16)),
+                     max(__builtin_amdgcn_readlane(N, 32),
+                         __builtin_amdgcn_readlane(N, 48)));
+  const int ob0 = (int)(r0 - sys);
+  const bool wr = live && c < NB;
+  int fail = -1;
+
+  // Rows past the system's end repeat its last row (computed, never stored).
+  // Lower-triangle entries of D_k for column cc: row cc left of the
+  // diagonal, column cc from it down.
+  auto load_d = [&](int k, double* Dr) {
+    const int64_t g = r0 + min(k, Ns - 1);
+#pragma unroll
+    for (int r = 0; r < NB; ++r) {
+      const int e = r < cc ? cc * NB + r : r * NB + cc;
+      Dr[r] = ld<Rec>(a.D, (size_t)g * NN + e);
+    }
+  };
+  // column cc of O_k (between rows k and k + 1), b_{k+1}[cc]
+  auto load_o = [&](int k, double* Oc, double& bv) {
+    const int kc = min(k, Ns - 2);
+    if (kc >= 0) {
+      const size_t ob = (size_t)(ob0 + kc) * NN;
+#pragma unroll
+      for (int r = 0; r < NB; ++r) Oc[r] = ld<Rec>(a.O, ob + (size_t)r * NB + cc);
+      bv = a.b[(r0 + kc + 1) * NB + cc];
+    } else {
+#pragma unroll
+      for (int r = 0; r < NB; ++r) Oc[r] = 0.0;
+      bv = 0.0;
+    }
+  };
+
+  double S[NB], Dn[NB], On[NB], Za[NB], Zh[NB];
+  double v = a.b[r0 * NB + cc], bn;
+  load_d(0, S);
+  load_d(1, Dn);
+  load_o(0, On, bn);
+
+  // ------------------------------------------------------------ forward
+  for (int k = 0; k < Nw; ++k) {
+    const int64_t g = r0 + k;
+    const bool act = k < N, nxt = k + 1 < N;
+    // Za: O_k column c, becoming L_k^{-1} O_k (times sqrt d) in the loop;
+    // vn: b_{k+1} - M_{k+1} y_k
+#pragma unroll
+    for (int r = 0; r < NB; ++r) Za[r] = On[r];
+    double vn = bn;
+    load_o(k + 1, On, bn);
+
+    // Pivot j: every column c > j takes S[r][j] S[c][j] / d_j off its rows
+    // r > j (S[r][j] from lane j, S[c][j] its own mirrored entry), and v
+    // takes v_j S[c][j] / d_j. Columns stop changing at their own pivot.
+    double ido = 1.0;
+    bool spd = true;
+    sfor<0, NB>([&](auto J) {
+      constexpr int j = decltype(J)::value;
+      const double d = nb<j>(S[j]);
+      spd = spd && d > 0.0 && d < INFINITY;
+      const double id = rcp_nr(d);
+      ido = c == j ? id : ido;
+      const double m = c > j ? S[j] * id : 0.0;
+      sfor<0, (NB - 1 - j) / 4>([&](auto G) {
+        constexpr int r = j + 1 + 4 * decltype(G)::value;
+        self4<j>(S[r], S[r + 1], S[r + 2], S[r + 3], m);
+      });
+      sfor<j + 1 + 4 * ((NB - 1 - j) / 4), NB>([&](auto R) {
+        constexpr int r = decltype(R)::value;
+        S[r] = self1<j>(S[r], m);
+      });
+      // next row, step j: with Zh_j = Za_j / d_j (Za_j final: all earlier
+      // columns of L_k taken off), L[r][j] z_j = Sc[r][j] Zh_j and
+      // M[c][j] y_j = Zh_j[c] vh_j
+      Zh[j] = Za[j] * id;
+      sfor<0, (NB - 1 - j) / 4>([&](auto G) {
+        constexpr int r = j + 1 + 4 * decltype(G)::value;
+        fnb4<j>(Za[r], Za[r + 1], Za[r + 2], Za[r + 3], S[r], S[r + 1],
+                S[r + 2], S[r + 3], Zh[j]);
+      });
+      sfor<j + 1 + 4 * ((NB - 1 - j) / 4), NB>([&](auto R) {
+        constexpr int r = decltype(R)::value;
+        Za[r] = fnb<j>(Za[r], S[r], Zh[j]);
+      });
+      vn = fnb<j>(vn, v, Zh[j]);
+      v = self1<j>(v, m);
+    });
+    fail = (!spd && act && fail < 0) ? k : fail;
+    if (wr && act) {
+      // the column at its pivot below the diagonal, 1 / d_c, vh_c
+#pragma unroll
+      for (int r = 0; r < NB; ++r)
+        a.Lbuf[(size_t)g * NN + (size_t)c * NB + r] = r > c ? S[r] : 0.0;
+      a.Rbuf[g * NB + c] = ido;
+      a.x[g * NB + c] = v;  // vh, replaced by x_k on the way back
+    }
+    if (wr && nxt) {
+      // Za of row k + 1: M_{k+1}^T = Za / sqrt(d) row by row
+#pragma unroll
+      for (int r = 0; r < NB; ++r)
+        a.Mbuf[(size_t)(g + 1) * NN + (size_t)c * NB + r] = Za[r];
+    }
+    dpp_exec_fence();
+    // S_{k+1} = D_{k+1} - M M^T, (M M^T)[r][c] = sum_p Zh_p[r] Za_p[c]
+#pragma unroll
+    for (int r = 0; r < NB; ++r) S[r] = Dn[r];
+    load_d(k + 2, Dn);
+#pragma unroll
+    for (int p = 0; p < NB; ++p) {
+      sfor<0, NB / 4>([&](auto G) {
+        constexpr int r = 4 * decltype(G)::value;
+        gram4<r, r + 1, r + 2, r + 3>(S[r], S[r + 1], S[r + 2], S[r + 3],
+                                      Zh[p], Za[p]);
+      });
+      sfor<4 * (NB / 4), NB>([&](auto R) {
+        constexpr int r = decltype(R)::value;
+        S[r] = fnb<r>(S[r], Zh[p], Za[p]);
+      });
+    }
+    v = vn;
+  }
+
+  // ----------------------------------------------------------- backward
+  // sqrt(d_c) u_c = vh_c - sum_p Za_{k+1}[p][c] x_{k+1,p} (row c of the
+  // stored Za, at p n + c), then x_c = (that - sum_{r>c} Sc[r][c] x_r) / d_c.
+  auto load_b = [&](int k, double* L_, double* Zr, double& id, double& u) {
+    const int kc = min(k, Ns - 1);
+    const int64_t g = r0 + kc;
+#pragma unroll
+    for (int r = 0; r < NB; ++r) L_[r] = a.Lbuf[(size_t)g * NN + (size_t)cc * NB + r];
+    if (kc + 1 < Ns) {
+#pragma unroll
+      for (int p = 0; p < NB; ++p)
+        Zr[p] = a.Mbuf[(size_t)(g + 1) * NN + (size_t)p * NB + cc];
+    } else {
+#pragma unroll
+      for (int p = 0; p < NB; ++p) Zr[p] = 0.0;
+    }
+    id = a.Rbuf[g * NB + cc];
+    u = a.x[g * NB + cc];
+  };
+  // two block rows in flight: the backward step is short next to the
+  // latency of its loads
+  constexpr int PD = 2;
+  double Lb[PD][NB], Zb[PD][NB], idb[PD], ub[PD];
+  sfor<0, PD>([&](auto I) {
+    constexpr int t = decltype(I)::value;
+    if (Nw - 1 - t >= 0) load_b(Nw - 1 - t, Lb[t], Zb[t], idb[t], ub[t]);
+  });
+  double xn = 0.0;  // x_{k+1}[c]
+  for (int k0 = Nw - 1; k0 >= 0; k0 -= PD) {
+    sfor<0, PD>([&](auto I) {
+      constexpr int t = decltype(I)::value;
+      const int k = k0 - t;
+      if (k < 0) return;
+      const int64_t g = r0 + k;
+      const bool act = k < N;
+      double L0[NB], Zr[NB];
+#pragma unroll
+      for (int r = 0; r < NB; ++r) {
+        L0[r] = Lb[t][r];
+        Zr[r] = Zb[t][r];
+      }
+      double u = ub[t];
+      const double id = idb[t];
+      if (k - PD >= 0) load_b(k - PD, Lb[t], Zb[t], idb[t], ub[t]);
+      xn = k + 1 < N ? xn : 0.0;
+      double u1 = 0.0;  // two chains over the columns of Za_{k+1}
+      sfor<0, NB>([&](auto P) {
+        constexpr int p = decltype(P)::value;
+        if constexpr (p % 2 == 0)
+          u = fnb<p>(u, xn, Zr[p]);
+        else
+          u1 = fnb<p>(u1, xn, Zr[p]);
+      });
+      u += u1;
+      // x_r = u_r / d_r (lane r), then the columns above take Sc[r][c] x_r
+      sfor<0, NB>([&](auto J) {
+        constexpr int r = NB - 1 - decltype(J)::value;
+        u = fnb<r>(u, u * id, L0[r]);
+      });
+      xn = u * id;
+      if (wr && act) a.x[g * NB + c] = xn;
+      dpp_exec_fence();
+    });
+  }
+  if (live && c == 0) {
+    bt_info* inf = a.info + sys;
+    inf->status = fail < 0 ? BT_OK : BT_ENOTSPD;
+    inf->iters = 0;
+    inf->outer = 0;
+    inf->fail_index = fail;
+    inf->relres = NAN;
+    inf->relres_true = NAN;
+    inf->gemv_exec = 0;
+    inf->gemv_paper = 0;
+  }
+}
+
 template <int NB>
 hipError_t launch_nb(const DirectArgs& a, hipStream_t s) {
+  if constexpr (NB <= 16) {
+    const int per = 4 * kDirectWaves;  // systems per workgroup
+    const dim3 grid((a.B + per - 1) / per), block(64 * kDirectWaves);
+    if (a.dtype == BT_DT_F64)
+      hipLaunchKernelGGL((k_direct4<NB, double>), grid, block, 0, s, a);
+    else
+      hipLaunchKernelGGL((k_direct4<NB, float>), grid, block, 0, s, a);
+    return hipGetLastError();
+  }
   if (a.dtype == BT_DT_F64)
     hipLaunchKernelGGL((k_direct<NB, double>), dim3(a.B), dim3(64), 0, s, a);
   else
@@ -241,7 +583,7 @@ hipError_t launch_nb(const DirectArgs& a, hipStream_t s) {
 }  // namespace btd
 
 size_t bt_direct_scratch_bytes(int64_t R, int n) {
-  return 2 * (size_t)R * n * n * sizeof(double);
+  return (size_t)R * (2 * (size_t)n * n + n) * sizeof(double);
 }
 
 bool bt_direct_supported(int n) {
@@ -264,6 +606,7 @@ hipError_t bt_launch_direct(int B, int n, int dtype, const int64_t* off,
   a.x = x;
   a.Lbuf = (double*)scratch;
   a.Mbuf = a.Lbuf + (size_t)R * n * n;
+  a.Rbuf = a.Mbuf + (size_t)R * n * n;
   a.info = info;
   switch (n) {
     case 1: return btd::launch_nb<1>(a, s);

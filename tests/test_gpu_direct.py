@@ -35,10 +35,12 @@ def run(data, record="f32"):
 
 @pytest.mark.parametrize("n,record", [(12, "f32"), (12, "f64"), (6, "f64"),
                                       (16, "f32"), (5, "f64"), (1, "f64"),
+                                      (3, "f32"), (8, "f32"), (13, "f64"),
                                       (24, "f32"), (32, "f64"), (48, "f32"),
                                       (64, "f64")])
 def test_direct_matches_oracle(n, record):
-    """Ragged batches (horizons 1..90, or 1..40 for n >= 32) against the
+    """Ragged batches (horizons 1..90, or 1..40 for n >= 32; 37 systems, so
+    the last group of four sharing a wavefront is incomplete) against the
     oracle's block Cholesky, globally and per block row."""
     hi = 90 if n < 32 else 40
     data = lqrgen.lqr_batch(37 if n < 32 else 12, (1, hi), n, max(1, n // 3),
