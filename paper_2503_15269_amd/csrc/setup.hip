@@ -740,6 +740,82 @@ __global__ void __launch_bounds__(256) k_offdiag_block(SetupArgs a) {
   }
 }
 
+// F_g for n = 32, 48, 64 on the matrix cores (v_mfma_f64_16x16x4f64),
+// one workgroup per block row with a wavefront per 16-wide strip. Operands
+// in LDS as float64, rows padded to n + 2 entries so that the 16 rows a
+// wavefront reads at once fall in distinct banks. Li is lower triangular
+// (zeros above the diagonal), so the k-steps past a strip's diagonal are
+// skipped: T = Li_g O_g by column strips (wave w: columns 16w.., every row
+// strip I summing k < 16 (I + 1)), then F = T Li_{g+1}^T by row strips
+// (wave w: rows 16w.., column strip J summing k < 16 (J + 1)); both splits
+// give every wavefront the same number of steps.
+// Layouts (16x16x4, float64): A operand lane l = A[l % 16][l / 16], B
+// operand lane l = B[l / 16][l % 16], result lane l element i =
+// D[4 (l / 16) + i][l % 16].
+template <int NB>
+constexpr size_t offdiag_mfma_lds() {
+  return 4 * sizeof(double) * (size_t)NB * (NB + 2);
+}
+
+template <int NB, typename T, typename Rec>
+__global__ void __launch_bounds__(64 * (NB / 16)) k_offdiag_mfma(SetupArgs a) {
+  static_assert(NB % 16 == 0, "strips of 16");
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  constexpr int W = NB / 16, NN = NB * NB, P = NB + 2, NT = 64 * W;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* Lg = reinterpret_cast<double*>(smem_raw);
+  double* Og = Lg + NB * P;
+  double* Ln = Og + NB * P;
+  double* Tm = Ln + NB * P;
+  const int64_t g = blockIdx.x;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const int inst = a.rowinst[g];
+  const bool has_next = g + 1 < a.off[inst + 1];
+  T* F = (T*)a.F + (size_t)g * NN;
+  if (!has_next) {
+    for (int e = t; e < NN; e += NT) F[e] = (T)0;
+    return;
+  }
+  const T* lig = (const T*)a.Li + (size_t)g * NN;
+  const Rec* og = (const Rec*)a.O + (size_t)(g - inst) * NN;
+  for (int e = t; e < NN; e += NT) {
+    const int r = e / NB, c = e - r * NB;
+    Lg[r * P + c] = (double)lig[e];
+    Ln[r * P + c] = (double)lig[NN + e];
+    Og[r * P + c] = (double)og[e];
+  }
+  __syncthreads();
+  const int li = l & 15, lk = l >> 4;
+  // T, column strip w
+#pragma unroll
+  for (int I = 0; I < W; ++I) {
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4 * (I + 1); ++s) {
+      const double av = Lg[(16 * I + li) * P + 4 * s + lk];
+      const double bv = Og[(4 * s + lk) * P + 16 * w + li];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) Tm[(16 * I + 4 * lk + i) * P + 16 * w + li] = acc[i];
+  }
+  __syncthreads();
+  // F, row strip w
+#pragma unroll
+  for (int J = 0; J < W; ++J) {
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4 * (J + 1); ++s) {
+      const double av = Tm[(16 * w + li) * P + 4 * s + lk];
+      const double bv = Ln[(16 * J + li) * P + 4 * s + lk];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+      F[(size_t)(16 * w + 4 * lk + i) * NB + 16 * J + li] = (T)acc[i];
+  }
+}
+
 template <int NB, typename T, typename Rec>
 hipError_t launch_wave(const SetupArgs& a, hipStream_t s) {
   constexpr size_t flds = factor_wave_lds<NB>();
@@ -754,6 +830,15 @@ hipError_t launch_wave(const SetupArgs& a, hipStream_t s) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || !a.F) return e;
   if (NB == 24) return launch_offdiag<24, T, Rec>(a, s);
+  if constexpr (NB % 16 == 0) {
+    constexpr size_t lds = offdiag_mfma_lds<NB>();
+    static std::atomic<uint64_t> attr{0};
+    e = lds_limit((const void*)k_offdiag_mfma<NB, T, Rec>, lds, attr);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_offdiag_mfma<NB, T, Rec>), dim3((unsigned)a.R),
+                       dim3(64 * (NB / 16)), lds, s, a);
+    return hipGetLastError();
+  }
   constexpr size_t lds = 4 * sizeof(double) * (size_t)NB * NB;
   static std::atomic<uint64_t> attr{0};
   e = lds_limit((const void*)k_offdiag_block<NB, T, Rec>, lds, attr);
