@@ -221,12 +221,18 @@ int bt_solve_adjoint(const bt_handle* h, const double* x, const double* g,
  * each column an independent PCG with the handle's preconditioner, the
  * operator applied to the whole [n][nrhs] panel of a block row with matrix-
  * core products. Requires a handle set up with prec BT_BF16X2_IR, B = 1,
- * n in {16, 32, 48, 64}, a = 1, m in {1, 2}; nrhs a multiple of 64, at most
- * 256. b, x: device [R][n][nrhs] float64 (right-hand-side index fastest).
+ * n in {16, 32, 48, 64}, pc BT_PC_POLY with any splitting weights, order
+ * and coefficients (BT_PC_NONE, plain CG on A, would need the factors L_k,
+ * which this path does not keep: BT_EINVAL). nrhs a multiple of 16,
+ * 16..BT_MRHS_MAX. At a = 1 with m <= 2 the preconditioner is fused into
+ * two passes per inner iteration; otherwise it is evaluated by Horner's
+ * rule from panel passes (one per application of C).
+ * b, x: device [R][n][nrhs] float64 (right-hand-side index fastest).
  * info: device, nrhs entries. scratch: device, >= bt_mrhs_workspace_bytes.
  * Unlike the other calls this one waits on the stream between refinement
  * steps (convergence checks), so it cannot be captured into a graph.
  * Errors: BT_EINVAL, BT_ENOSPACE, BT_EHIP. */
+#define BT_MRHS_MAX 4096
 size_t bt_mrhs_workspace_bytes(const bt_handle* h, int nrhs);
 int bt_solve_mrhs(const bt_handle* h, int nrhs, const double* b, double* x,
                   double tol, int maxit, bt_info* info, void* scratch,

@@ -381,16 +381,15 @@ int bt_solve_mrhs(const bt_handle* h, int nrhs, const double* b, double* x,
                   size_t scratch_bytes, void* stream) {
   if (!h || !b || !x || !info || !scratch || !(tol >= 0.0) || maxit < 0)
     return BT_EINVAL;
-  if (h->p.prec != BT_BF16X2_IR || h->B != 1 || h->p.pc != BT_PC_POLY ||
-      h->p.a != 1.0 || h->p.m > 2)
+  if (h->p.prec != BT_BF16X2_IR || h->B != 1 || h->p.pc != BT_PC_POLY)
     return BT_EINVAL;
   if (!(h->n == 16 || h->n == 32 || h->n == 48 || h->n == 64)) return BT_EINVAL;
-  if (nrhs < 64 || nrhs > 256 || nrhs % 64 != 0) return BT_EINVAL;
+  if (nrhs < 16 || nrhs > BT_MRHS_MAX || nrhs % 16 != 0) return BT_EINVAL;
   if (scratch_bytes < bt_mrhs_scratch_bytes(h->R, h->n, nrhs))
     return BT_ENOSPACE;
   return bt_mrhs_run(h->R, h->n, nrhs, h->Fhi, h->Flo, (const float*)h->Li,
                      h->D, h->O, h->dtype, b, x, tol, maxit, h->p.max_outer,
-                     h->p.inner_tol, h->p.m, h->p.m > 1 ? h->p.alpha[1] : 0.0,
+                     h->p.inner_tol, h->p.pc, h->p.a, h->p.m, h->p.alpha,
                      h->p.warm_start, scratch, info, (hipStream_t)stream);
 }
 

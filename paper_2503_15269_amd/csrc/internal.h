@@ -168,9 +168,9 @@ hipError_t bt_mrhs_split(const float* F, unsigned short* hi, unsigned short* lo,
 int bt_mrhs_run(int64_t R, int n, int nrhs, const unsigned short* Fhi,
                 const unsigned short* Flo, const float* Li, const void* D,
                 const void* O, int dtype, const double* b, double* x,
-                double tol, int maxit, int max_outer, double inner_tol, int m,
-                double alpha1, int warm, void* scratch, bt_info* info,
-                hipStream_t s);
+                double tol, int maxit, int max_outer, double inner_tol,
+                int pc, double a, int m, const double* alpha, int warm,
+                void* scratch, bt_info* info, hipStream_t s);
 size_t bt_direct_scratch_bytes(int64_t R, int n);
 bool bt_direct_supported(int n);
 hipError_t bt_launch_direct(int B, int n, int dtype, const int64_t* off,

@@ -87,6 +87,10 @@ struct MrArgs {
   int *act, *done, *first, *inner, *total, *outer, *status;
   double alpha1;              // polynomial coefficient of the second term
   int m;
+  int pc;                     // BT_PC_POLY
+  double aw;                  // splitting weight a
+  double al[BT_MAX_M];        // polynomial coefficients (al[0] = 1)
+  int nz;                     // applications of C in z = M^{-1} r
   double tol, itol2;
   int maxit;
 };
@@ -250,6 +254,16 @@ __device__ __forceinline__ void pst(PRow r, int voff, int ld, int tt, int i,
                                         (16 * tt + i) * ld * 4, 0);
 }
 
+// Columns past nrhs (a workgroup covers 64; nrhs is a multiple of 16): the
+// lane's panel offset points past every block row, so buffer loads give 0
+// and stores are dropped, and the per-column state is not read.
+__device__ __forceinline__ int col_voff(int col, int kq, int ld, int nrhs) {
+  return col < nrhs ? 4 * (kq * ld + col) : 0x40000000;
+}
+__device__ __forceinline__ bool col_act(const MrArgs& a, int col) {
+  return col < a.nrhs && a.act[col] != 0;
+}
+
 // ---------------------------------------------------------------------------
 // p = z + beta p (new p of the row and both neighbours, formed on the fly),
 // q = p - C p = Ahat p, sigma = p'q partials. For a column that has stopped
@@ -267,11 +281,11 @@ __global__ void __launch_bounds__(WG) k_mr_qu(MrArgs a, const float* pold,
   const int kq = 4 * (l >> 4);
   // nothing to do once every column of this workgroup has stopped (the host
   // only checks every few iterations)
-  if (!__syncthreads_or(a.act[blockIdx.y * CPB + (t & 63)])) return;
+  if (!__syncthreads_or(col_act(a, blockIdx.y * CPB + (t & 63)))) return;
   const int ld = a.nrhs;
-  const int voff = 4 * (kq * ld + col);
-  const bool act = a.act[col] != 0;
-  const float be = (float)a.beta[col];
+  const int voff = col_voff(col, kq, ld, a.nrhs);
+  const bool act = col_act(a, col);
+  const float be = act ? (float)a.beta[col] : 0.f;
   auto load = [&](int j) {
     const PRow po = prow<NB>(pold, j, ld), zr = prow<NB>(a.z, j, ld);
     Pan<NB> p;
@@ -316,7 +330,7 @@ __global__ void __launch_bounds__(WG) k_mr_qu(MrArgs a, const float* pold,
     }
   dp += __shfl_xor(dp, 16);
   dp += __shfl_xor(dp, 32);
-  if (l < 16) a.part[(size_t)k * ld + col] = dp;
+  if (l < 16 && col < a.nrhs) a.part[(size_t)k * ld + col] = dp;
 }
 
 // ---------------------------------------------------------------------------
@@ -343,13 +357,13 @@ __global__ void __launch_bounds__(WG) k_mr_post(MrArgs a) {
   const int t = threadIdx.x, l = t & 63;
   const int col = blockIdx.y * CPB + (t >> 6) * CPW + (l & 15);
   const int kq = 4 * (l >> 4);
-  if (!__syncthreads_or(a.act[blockIdx.y * CPB + (t & 63)])) return;
+  if (!__syncthreads_or(col_act(a, blockIdx.y * CPB + (t & 63)))) return;
   // slots for M = 2: 0 G_{k-3}, 1 F_{k-2}, 2 G_{k-1}, 3 F_k, 4 G_{k+1},
   // 5 F_{k+2}; for M = 1 only G_{k-1}, F_k, in slots 0 and 1
   constexpr int SG = M >= 2 ? 2 : 0;  // slot of G_{k-1}; F_k follows
   const int ld = a.nrhs;
-  const int voff = 4 * (kq * ld + col);
-  const bool act = a.act[col] != 0;
+  const int voff = col_voff(col, kq, ld, a.nrhs);
+  const bool act = col_act(a, col);
   const float al = UPD && act ? (float)a.alpha[col] : 0.f;
   auto load = [&](int j) {  // r' of row j
     const PRow rr = prow<NB>(a.r, j, ld);
@@ -478,7 +492,107 @@ __global__ void __launch_bounds__(WG) k_mr_post(MrArgs a) {
     }
   dp += __shfl_xor(dp, 16);
   dp += __shfl_xor(dp, 32);
-  if (l < 16) a.part[(size_t)k * ld + col] = dp;
+  if (l < 16 && col < a.nrhs) a.part[(size_t)k * ld + col] = dp;
+}
+
+// ---------------------------------------------------------------------------
+// The preconditioner for any splitting and order (eq. Mminv-polynomial-
+// coefficients in the scaled form, G = I + a C, H = (1 - a) C + a C^2),
+// evaluated by Horner's rule from panel passes of one kind:
+//   out_k = cx X_k + cy Y_k + cc (C V)_k
+// (X, Y, V optional), with the rho partials r'_k . out_k when ``rho``.
+// ---------------------------------------------------------------------------
+template <int NB>
+__global__ void __launch_bounds__(WG) k_mr_lin(MrArgs a, const float* X,
+                                              float cx, const float* Y,
+                                              float cy, const float* V,
+                                              float cc, float* out, int rho) {
+  constexpr int MT = NB / 16, BLK = Lds<NB>::BLK;
+  __shared__ __align__(16) unsigned short sF[2 * BLK];  // G_{k-1}, F_k
+  const int k = xcd_row(blockIdx.x, a.R);
+  if (k >= a.R) return;
+  const int t = threadIdx.x, l = t & 63;
+  const int col = blockIdx.y * CPB + (t >> 6) * CPW + (l & 15);
+  const int kq = 4 * (l >> 4);
+  if (!__syncthreads_or(col_act(a, blockIdx.y * CPB + (t & 63)))) return;
+  const int ld = a.nrhs;
+  const int voff = col_voff(col, kq, ld, a.nrhs);
+  auto load = [&](const float* P, int j) {
+    const PRow pr = prow<NB>(P, j, ld);
+    Pan<NB> v;
+#pragma unroll
+    for (int tt = 0; tt < MT; ++tt)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) v.v[tt][i] = pld(pr, voff, ld, tt, i);
+    return v;
+  };
+  const bool hm = V && k > 0, hp = V && k < a.R - 1;
+  const Pan<NB> zero{};
+  const Pan<NB> vm = hm ? load(V, k - 1) : zero;
+  const Pan<NB> vp = hp ? load(V, k + 1) : zero;
+  const Pan<NB> x = X ? load(X, k) : zero;
+  const Pan<NB> y = Y ? load(Y, k) : zero;
+  f32x4 acc[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  if (V) {
+    {
+      Blocks<NB, 2> blk;
+      blk.load(a, 0, a.Ghi, a.Glo, k - 1);
+      blk.load(a, 1, a.Fhi, a.Flo, k);
+      blk.store(0, sF);
+      blk.store(1, sF + BLK);
+    }
+    __syncthreads();
+    cprod<NB>(hm, sF, split(vm), hp, sF + BLK, split(vp), l, acc);
+  }
+  const PRow ow = prow<NB>(out, k, ld);
+  const PRow rr = prow<NB>(a.r, k, ld);
+  double dp = 0.0;
+#pragma unroll
+  for (int tt = 0; tt < MT; ++tt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      // C V = -acc
+      const float o = cx * x.v[tt][i] + cy * y.v[tt][i] - cc * acc[tt][i];
+      pst(ow, voff, ld, tt, i, o);
+      if (rho) dp += (double)pld(rr, voff, ld, tt, i) * (double)o;
+    }
+  if (rho) {
+    dp += __shfl_xor(dp, 16);
+    dp += __shfl_xor(dp, 32);
+    if (l < 16 && col < a.nrhs) a.part[(size_t)k * ld + col] = dp;
+  }
+}
+
+// r' = r - alpha q into r2 and d += alpha p, for the running columns (the
+// others keep r and d).
+template <int NB>
+__global__ void __launch_bounds__(WG) k_mr_rupd(MrArgs a) {
+  constexpr int MT = NB / 16;
+  const int k = xcd_row(blockIdx.x, a.R);
+  if (k >= a.R) return;
+  const int t = threadIdx.x, l = t & 63;
+  const int col = blockIdx.y * CPB + (t >> 6) * CPW + (l & 15);
+  const int kq = 4 * (l >> 4);
+  const int ld = a.nrhs;
+  const int voff = col_voff(col, kq, ld, a.nrhs);
+  const bool act = col_act(a, col);
+  const float al = act ? (float)a.alpha[col] : 0.f;
+  const PRow rr = prow<NB>(a.r, k, ld), qr = prow<NB>(a.q, k, ld),
+             rw = prow<NB>(a.r2, k, ld), dr = prow<NB>(a.d, k, ld),
+             pr = prow<NB>(a.p, k, ld);
+#pragma unroll
+  for (int tt = 0; tt < MT; ++tt)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const float rv = pld(rr, voff, ld, tt, i);
+      pst(rw, voff, ld, tt, i, act ? __fmaf_rn(-al, pld(qr, voff, ld, tt, i), rv) : rv);
+      if (act) {
+        const float dv = pld(dr, voff, ld, tt, i);
+        pst(dr, voff, ld, tt, i, __fmaf_rn(al, pld(pr, voff, ld, tt, i), dv));
+      }
+    }
 }
 
 // Per right-hand side: sum of the per-row partials in a fixed order, then
@@ -616,7 +730,8 @@ __global__ void __launch_bounds__(256) k_mr_resid(MrArgs a, double* r64,
     sOm[e] = hp ? O[(size_t)(k - 1) * NN + e] : (Rec)0;
   }
   __syncthreads();
-  const bool done = a.done[c] != 0;
+  const bool cv = c < L;  // a column of the panel (nrhs % 64 may be nonzero)
+  const bool done = !cv || a.done[c] != 0;
   double acc[MR];
 #pragma unroll
   for (int m = 0; m < MR; ++m) acc[m] = 0.0;
@@ -643,12 +758,12 @@ __global__ void __launch_bounds__(256) k_mr_resid(MrArgs a, double* r64,
   for (int m = 0; m < MR; ++m) {
     const size_t idx = (size_t)k * pn + (size_t)(w + 4 * m) * L + c;
     const double v = done ? 0.0 : a.b[idx] - acc[m];
-    r64[idx] = v;
+    if (cv) r64[idx] = v;
     ss = fma(v, v, ss);
   }
   red[w][lane] = ss;
   __syncthreads();
-  if (w == 0)
+  if (w == 0 && cv)
     a.part[(size_t)k * L + c] = (red[0][lane] + red[1][lane]) +
                                 (red[2][lane] + red[3][lane]);
 }
@@ -663,6 +778,7 @@ __global__ void __launch_bounds__(256) k_mr_tohat(MrArgs a, const double* r64) {
   const size_t pn = (size_t)NB * L;
   for (int e = t; e < NN; e += 256) sL[e] = a.Li[(size_t)k * NN + e];
   __syncthreads();
+  if (c >= L) return;  // past the panel (no barrier follows)
   float acc[MR];
 #pragma unroll
   for (int m = 0; m < MR; ++m) acc[m] = 0.f;
@@ -698,7 +814,7 @@ __global__ void __launch_bounds__(256) k_mr_xupd(MrArgs a) {
   const size_t pn = (size_t)NB * L;
   for (int e = t; e < NN; e += 256) sL[e] = a.Li[(size_t)k * NN + e];
   __syncthreads();
-  if (a.done[c]) return;
+  if (c >= L || a.done[c]) return;
   float acc[MR];
 #pragma unroll
   for (int m = 0; m < MR; ++m) acc[m] = 0.f;
@@ -745,14 +861,14 @@ __global__ void k_mr_info(MrArgs a, bt_info* info, int warm) {
   const double rr = nb > 0.0 ? sqrt(a.nr2[c] / nb) : 0.0;
   info[c].relres = rr;
   info[c].relres_true = rr;
-  // per refinement step: z = M^{-1} r (2m - 1 applications of C) and the
-  // two triangular transforms; per inner iteration: 2m applications; a
+  // per refinement step: z = M^{-1} r (nz applications of C) and the two
+  // triangular transforms; per inner iteration: 1 + nz applications; a
   // float64 residual after every step (and before the first from a guess)
   const int64_t halves =
-      2 * ((int64_t)(2 * a.m - 1) * a.outer[c] + (int64_t)2 * a.m * a.total[c]);
+      2 * ((int64_t)a.nz * a.outer[c] + (int64_t)(1 + a.nz) * a.total[c]);
   info[c].gemv_exec =
       bt_gemv_rows(a.R, halves, 2 * a.outer[c], a.outer[c] + (warm ? 1 : 0));
-  info[c].gemv_paper = (int64_t)a.total[c] * bt_gemv_g(BT_PC_POLY, 1.0, a.m);
+  info[c].gemv_paper = (int64_t)a.total[c] * bt_gemv_g(a.pc, a.aw, a.m);
 }
 
 // F (float32) -> hi + lo (bfloat16 pair): entries [0, R NN) the split of the
@@ -776,10 +892,13 @@ __global__ void k_mr_split(const float* F, unsigned short* hi,
   }
 }
 
+// workgroups over the columns (64 each; the last may be partly past nrhs)
+inline int cblk(const MrArgs& a) { return (a.nrhs + CPB - 1) / CPB; }
+
 template <int NB>
 hipError_t qu(const MrArgs& a, hipStream_t s) {
   const int rows = 8 * ((a.R + 7) / 8);
-  hipLaunchKernelGGL((k_mr_qu<NB>), dim3(rows, a.nrhs / CPB), dim3(WG), 0, s,
+  hipLaunchKernelGGL((k_mr_qu<NB>), dim3(rows, cblk(a)), dim3(WG), 0, s,
                      a, a.p, a.p2);
   return hipGetLastError();
 }
@@ -792,7 +911,7 @@ hipError_t post_m(const MrArgs& a, hipStream_t s) {
   const hipError_t e = lds_limit((const void*)k_mr_post<NB, M, UPD>, lds, attr);
   if (e != hipSuccess) return e;
   const int rows = 8 * ((a.R + 7) / 8);
-  hipLaunchKernelGGL((k_mr_post<NB, M, UPD>), dim3(rows, a.nrhs / CPB),
+  hipLaunchKernelGGL((k_mr_post<NB, M, UPD>), dim3(rows, cblk(a)),
                      dim3(WG), lds, s, a);
   return hipGetLastError();
 }
@@ -804,6 +923,73 @@ hipError_t post(const MrArgs& a, hipStream_t s) {
   return a.m >= 2 ? post_m<NB, 2, UPD>(a, s) : post_m<NB, 1, UPD>(a, s);
 }
 
+// The fused kernels cover the optimal splitting (a = 1) at m <= 2; every
+// other preconditioner of the family takes the panel passes below.
+inline bool fused(const MrArgs& a) {
+  return a.pc == BT_PC_POLY && a.aw == 1.0 && a.m <= 2;
+}
+
+template <int NB>
+hipError_t lin(const MrArgs& a, const float* X, double cx, const float* Y,
+               double cy, const float* V, double cc, float* out, int rho,
+               hipStream_t s) {
+  const int rows = 8 * ((a.R + 7) / 8);
+  hipLaunchKernelGGL((k_mr_lin<NB>), dim3(rows, cblk(a)), dim3(WG), 0, s, a,
+                     X, (float)cx, Y, (float)cy, V, (float)cc, out, rho);
+  return hipGetLastError();
+}
+
+// z = M^{-1} r (r = a.r) and the rho partials, any splitting weight a and
+// order m: y0 = G r = r + a C r, then Horner's rule on sum_i al_i H^i y0,
+//   t <- al_i y0 + H t  (i = m - 2 .. 0, starting from t = al_{m-1} y0),
+// H t = (1 - a) C t + a C (C t): a pass u = C t, then al_i y0 + (1 - a) u
+// + a C u (at a = 0 one pass, al_i y0 + C t). q, p2 and r2 are free here
+// (q was used up by the update of r, p2 and r2 hold the previous p and r);
+// a pass never writes a panel whose neighbour rows it reads.
+template <int NB>
+hipError_t precond_general(const MrArgs& a, hipStream_t s) {
+  hipError_t e;
+  const double aw = a.aw;
+  const int m = a.m;
+  const float* y0 = a.r;
+  if (aw != 0.0 || m == 1) {
+    float* dst = m == 1 ? a.z : a.q;
+    e = lin<NB>(a, a.r, 1, nullptr, 0, aw != 0.0 ? a.r : nullptr, aw, dst,
+                m == 1, s);
+    if (e != hipSuccess || m == 1) return e;
+    y0 = dst;
+  }
+  const float* t = y0;
+  double ct = a.al[m - 1];  // t stands for ct times the panel t
+  for (int i = m - 2, side = 0; i >= 0; --i, side ^= 1) {
+    const double ai = i == 0 ? 1.0 : a.al[i];
+    if (aw == 0.0) {
+      // t is y0 (= r) or the panel written by the previous pass: write the
+      // other temporary
+      float* dst = i == 0 ? a.z : (side ? a.r2 : a.p2);
+      e = lin<NB>(a, y0, ai, nullptr, 0, t, ct, dst, i == 0, s);
+      t = dst;
+    } else {
+      // u = C t into p2, then the new t into r2 (t, if not y0, was r2: its
+      // last reader is the first pass)
+      float* dst = i == 0 ? a.z : a.r2;
+      e = lin<NB>(a, nullptr, 0, nullptr, 0, t, ct, a.p2, 0, s);
+      if (e != hipSuccess) return e;
+      e = lin<NB>(a, y0, ai, a.p2, 1.0 - aw, a.p2, aw, dst, i == 0, s);
+      t = dst;
+    }
+    if (e != hipSuccess) return e;
+    ct = 1.0;
+  }
+  return hipSuccess;
+}
+
+// z = M^{-1} r and the rho partials at the start of a refinement step
+template <int NB>
+hipError_t precond_first(const MrArgs& a, hipStream_t s) {
+  return fused(a) ? post<NB, false>(a, s) : precond_general<NB>(a, s);
+}
+
 // One inner iteration up to the rho partials of the new residual; swaps the
 // p and r panels of ``a``.
 template <int NB>
@@ -812,10 +998,18 @@ hipError_t inner_iteration(MrArgs& a, hipStream_t s) {
   if (e != hipSuccess) return e;
   std::swap(a.p, a.p2);
   hipLaunchKernelGGL((k_mr_colsum<SUM_SIGMA>), dim3(a.nrhs), dim3(256), 0, s, a);
-  e = post<NB, true>(a, s);
+  if (fused(a)) {
+    e = post<NB, true>(a, s);
+    if (e != hipSuccess) return e;
+    std::swap(a.r, a.r2);
+    return hipSuccess;
+  }
+  const int rows = 8 * ((a.R + 7) / 8);
+  hipLaunchKernelGGL((k_mr_rupd<NB>), dim3(rows, cblk(a)), dim3(WG), 0, s, a);
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   std::swap(a.r, a.r2);
-  return hipSuccess;
+  return precond_general<NB>(a, s);
 }
 
 template <int NB>
@@ -843,17 +1037,17 @@ int solve(const MrArgs& a0, double* r64, int max_outer, int warm,
   hipLaunchKernelGGL(k_mr_init_cols, dim3(a.nrhs), dim3(256), 0, s, a, warm);
   for (int outer = 0;; ++outer) {
     if (a.dtype == BT_DT_F64)
-      hipLaunchKernelGGL((k_mr_resid<NB, double>), dim3(a.R, a.nrhs / CPB),
+      hipLaunchKernelGGL((k_mr_resid<NB, double>), dim3(a.R, cblk(a)),
                          dim3(256), 0, s, a, r64, outer == 0 && !warm);
     else
-      hipLaunchKernelGGL((k_mr_resid<NB, float>), dim3(a.R, a.nrhs / CPB),
+      hipLaunchKernelGGL((k_mr_resid<NB, float>), dim3(a.R, cblk(a)),
                          dim3(256), 0, s, a, r64, outer == 0 && !warm);
     hipLaunchKernelGGL((k_mr_colsum<SUM_RES>), dim3(a.nrhs), dim3(256), 0, s, a);
     if (!read_any(&hany)) return BT_EHIP;
     if (hany == 0 || outer >= max_outer) break;
-    hipLaunchKernelGGL((k_mr_tohat<NB>), dim3(a.R, a.nrhs / CPB), dim3(256),
+    hipLaunchKernelGGL((k_mr_tohat<NB>), dim3(a.R, cblk(a)), dim3(256),
                        0, s, a, r64);
-    if (post<NB, false>(a, s) != hipSuccess) return BT_EHIP;
+    if (precond_first<NB>(a, s) != hipSuccess) return BT_EHIP;
     hipLaunchKernelGGL((k_mr_colsum<SUM_RHO>), dim3(a.nrhs), dim3(256), 0, s, a);
     for (int it = 0;; ++it) {
       if ((it & 7) == 7) {
@@ -863,7 +1057,7 @@ int solve(const MrArgs& a0, double* r64, int max_outer, int warm,
       if (inner_iteration<NB>(a, s) != hipSuccess) return BT_EHIP;
       hipLaunchKernelGGL((k_mr_colsum<SUM_RHO>), dim3(a.nrhs), dim3(256), 0, s, a);
     }
-    hipLaunchKernelGGL((k_mr_xupd<NB>), dim3(a.R, a.nrhs / CPB), dim3(256),
+    hipLaunchKernelGGL((k_mr_xupd<NB>), dim3(a.R, cblk(a)), dim3(256),
                        0, s, a);
     hipLaunchKernelGGL(k_mr_outer_done, dim3((a.nrhs + 63) / 64), dim3(64), 0,
                        s, a);
@@ -896,9 +1090,9 @@ hipError_t bt_mrhs_split(const float* F, unsigned short* hi, unsigned short* lo,
 int bt_mrhs_run(int64_t R, int n, int nrhs, const unsigned short* Fhi,
                 const unsigned short* Flo, const float* Li, const void* D,
                 const void* O, int dtype, const double* b, double* x,
-                double tol, int maxit, int max_outer, double inner_tol, int m,
-                double alpha1, int warm, void* scratch, bt_info* info,
-                hipStream_t s) {
+                double tol, int maxit, int max_outer, double inner_tol,
+                int pc, double aw, int m, const double* alpha, int warm,
+                void* scratch, bt_info* info, hipStream_t s) {
   btm::MrArgs a{};
   a.R = (int)R;
   a.n = n;
@@ -916,8 +1110,13 @@ int bt_mrhs_run(int64_t R, int n, int nrhs, const unsigned short* Fhi,
   a.tol = tol;
   a.itol2 = inner_tol * inner_tol;
   a.maxit = maxit;
+  a.pc = pc;
+  a.aw = aw;
   a.m = m;
-  a.alpha1 = alpha1;
+  a.al[0] = 1.0;
+  for (int i = 1; i < BT_MAX_M; ++i) a.al[i] = i < m ? alpha[i] : 0.0;
+  a.alpha1 = a.al[1];
+  a.nz = (aw != 0.0 ? 1 : 0) + (m - 1) * (aw == 0.0 ? 1 : 2);
   const size_t pn = (size_t)R * n * nrhs;
   unsigned char* w = (unsigned char*)scratch;
   float* f = (float*)w;

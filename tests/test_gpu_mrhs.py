@@ -84,7 +84,10 @@ def test_mrhs_argument_checks():
         h.solve_mrhs(B)                      # handle not set up for bf16x2
     h2 = bt.Handle(Dt, Ot, None, bt.Params.polycoeff(2, prec="bf16x2_ir"))
     with pytest.raises(bt.BtError):
-        h2.solve_mrhs(B[:, :, :32].contiguous())   # nrhs not a multiple of 64
+        h2.solve_mrhs(B[:, :, :24].contiguous())   # nrhs not a multiple of 16
+    h3 = bt.Handle(Dt, Ot, None, bt.Params(pc="none", m=1, prec="bf16x2_ir"))
+    with pytest.raises(bt.BtError):
+        h3.solve_mrhs(B)                     # no preconditioner: not here
 
 
 @pytest.mark.parametrize("scale", [1e-14, 1e18])
@@ -103,3 +106,64 @@ def test_mrhs_scaled_columns(scale):
     X, info = h.solve_mrhs(to_dev(B, torch.float64), 1e-10)
     torch.cuda.synchronize()
     check(D, O, B, X.cpu().numpy(), bt.infos_to_numpy(info))
+
+
+# Preconditioners of the whole family (the fused kernels cover a = 1, m <= 2;
+# the rest goes through the Horner passes), nrhs multiples of 16 that leave
+# a workgroup's last columns past the panel.
+GENERAL = [(0.0, 1, None, 16, 16), (0.0, 3, [1.0, 0.5, 2.0], 48, 32),
+           (0.5, 2, [1.0, 3.0], 80, 16), (0.5, 4, [1.0, 1.0, 1.0, 7.0], 48, 48),
+           (1.0, 3, [1.0, 1.0, 7.0], 144, 32), (1.0, 4, [1.0, 2.0, 1.0, 7.0], 16, 16),
+           (1.0, 2, [1.0, 7.0], 48, 48)]
+
+
+def _params(a, m, alpha, **kw):
+    return bt.Params(a=a, m=m, alpha=alpha, prec="bf16x2_ir", **kw)
+
+
+@pytest.mark.parametrize("a,m,alpha,nrhs,n", GENERAL)
+def test_mrhs_general_first_step(a, m, alpha, nrhs, n):
+    """One inner iteration from x = 0 (maxit = 1) leaves X = alpha_0 z with
+    z = M^{-1} b the oracle's preconditioner (any splitting, order and
+    coefficients) and alpha_0 = b'z / z'Az: this pins the preconditioner the
+    panel passes evaluate, column by column, to the precision of the
+    bfloat16-pair products (~1e-5)."""
+    import torch
+    d = lqrgen.lqr_instance(24, n, max(1, n // 3), 70 + n, 0, s=0.1, nrhs=nrhs)
+    D, O, B = d["D"], d["O"], d["b"]
+    h = bt.Handle(to_dev(D, torch.float64), to_dev(O, torch.float64), None,
+                  _params(a, m, alpha, max_outer=1))
+    X, info = h.solve_mrhs(to_dev(B, torch.float64), 1e-10, maxit=1)
+    torch.cuda.synchronize()
+    X = X.cpu().numpy()
+    inf = bt.infos_to_numpy(info)
+    assert np.all(inf["iters"] == 1)
+    for c in range(nrhs):
+        b = B[:, :, c]
+        kind = orc.PC_OPT if a == 1.0 else orc.PC_SPLIT
+        z = orc.precond(D, O, b, kind=kind, a=a, b=1.0 - 2.0 * a, m=m,
+                        alpha=alpha)
+        x1 = (np.sum(b * z) / np.sum(z * orc.spmv(D, O, z))) * z
+        err = np.linalg.norm(X[:, :, c] - x1) / np.linalg.norm(x1)
+        assert err <= 1e-3, (c, err)
+
+
+@pytest.mark.parametrize("a,m,alpha,nrhs,n", GENERAL)
+def test_mrhs_general_converges(a, m, alpha, nrhs, n):
+    """Full solves to 1e-10 with every preconditioner of the family: every
+    column's true residual and its error against the oracle's direct solve,
+    and the gemv counts (the paper's g_a(m) per inner iteration)."""
+    import torch
+    d = lqrgen.lqr_instance(30, n, max(1, n // 3), 90 + n, 0, s=0.1, nrhs=nrhs)
+    D = d["D"].astype(np.float32).astype(np.float64)
+    O = d["O"].astype(np.float32).astype(np.float64)
+    B = d["b"]
+    h = bt.Handle(to_dev(D, torch.float32), to_dev(O, torch.float32), None,
+                  _params(a, m, alpha, inner_tol=1e-4))
+    X, info = h.solve_mrhs(to_dev(B, torch.float64), 1e-10)
+    torch.cuda.synchronize()
+    inf = bt.infos_to_numpy(info)
+    check(D, O, B, X.cpu().numpy(), inf)
+    g = orc.gemv_per_iteration(orc.PC_SPLIT if a != 1.0 else orc.PC_OPT,
+                               a=a, m=m)
+    assert np.all(inf["gemv_paper"] == g * inf["iters"])
