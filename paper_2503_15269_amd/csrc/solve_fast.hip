@@ -65,8 +65,6 @@ struct Geo {
   static_assert(NW <= MAXW, "at most 16 wavefronts");
 };
 
-// LDS position of entry j of a staged vector row
-__host__ __device__ constexpr int spos(int j) { return 4 * (j / 3) + j % 3; }
 
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
@@ -143,11 +141,22 @@ struct Ctx {
 
   __device__ Ctx(Smem<NB, EPT>& s) : sm(s) {}
 
-  // own entries into a staged row (SUB 16-byte slots)
-  __device__ __forceinline__ void put(float* row, const float (&v)[EPT]) const {
+  // Float offset of 16-byte chunk ``ch`` of staged row ``row``. At n = 12
+  // with two lanes per row, a quarter-wavefront's 16-byte accesses cover 8
+  // rows of 64 bytes, two chunks each, and rows r and r + 4 would meet in the
+  // same banks; rows 4..7 of every 8 swap their chunk pairs (ch xor 1), so
+  // the 16 accesses tile all 64 banks.
+  static constexpr bool SWZ = NB == 12 && G::TPR == 2;
+  __device__ __forceinline__ static int slot(int row, int ch) {
+    return row * G::ROW + 4 * (ch ^ (SWZ ? (row >> 2) & 1 : 0));
+  }
+
+  // own entries into staged row ``row`` of ``base`` (SUB 16-byte slots)
+  __device__ __forceinline__ void put(float* base, int row,
+                                      const float (&v)[EPT]) const {
 #pragma unroll
     for (int h = 0; h < G::SUB; ++h)
-      *reinterpret_cast<float4*>(row + 4 * (G::SUB * q + h)) =
+      *reinterpret_cast<float4*>(base + slot(row, G::SUB * q + h)) =
           make_float4(v[3 * h], v[3 * h + 1], v[3 * h + 2], 0.f);
   }
 
@@ -309,22 +318,21 @@ struct Ctx {
 #pragma unroll
       for (int z = 0; z < EPT; ++z) S[z] = tprod(z, v);
     }
-    put(&sm.V[BUF][lrow * G::ROW], v);
-    put(&sm.T[BUF][lrow * G::ROW], S);
+    put(sm.V[BUF], lrow, v);
+    put(sm.T[BUF], lrow, S);
   }
 
   template <int BUF>
   __device__ __forceinline__ void finish(float (&y)[EPT]) {
     ++nh;
     const int rp = k < N - 1 ? lrow + 1 : lrow;
-    const float* vr = &sm.V[BUF][rp * G::ROW];
     float acc[EPT];
     {
-      const float* tr = k > 0 ? &sm.T[BUF][(lrow - 1) * G::ROW] : sm.Z;
 #pragma unroll
       for (int h = 0; h < G::SUB; ++h) {
-        const float4 u =
-            *reinterpret_cast<const float4*>(tr + 4 * (G::SUB * q + h));
+        const float* tr = k > 0 ? sm.T[BUF] + slot(lrow - 1, G::SUB * q + h)
+                                : sm.Z + 4 * (G::SUB * q + h);
+        const float4 u = *reinterpret_cast<const float4*>(tr);
         acc[3 * h] = u.x;
         acc[3 * h + 1] = u.y;
         acc[3 * h + 2] = u.z;
@@ -335,7 +343,7 @@ struct Ctx {
 #pragma unroll
       for (int h = 0; h < G::SUB; ++h) {
         const float4 u = *reinterpret_cast<const float4*>(
-            vr + 4 * (G::SUB * (c ^ q) + h));
+            sm.V[BUF] + slot(rp, G::SUB * (c ^ q) + h));
         const float uc[3] = {u.x, u.y, u.z};
 #pragma unroll
         for (int e = 0; e < EPT; ++e)
@@ -416,14 +424,6 @@ struct Ctx {
   }
   __device__ __forceinline__ void put_flag(bool f) {
     if ((threadIdx.x & 63) == 0 && f) atomicAdd(&sm.active, 1);
-  }
-
-  // Stage own entries in natural layout for row-wise reads (transforms).
-  template <int BUF>
-  __device__ __forceinline__ const float* stage_row(const float (&v)[EPT]) {
-    put(&sm.V[BUF][lrow * G::ROW], v);
-    __syncthreads();
-    return &sm.V[BUF][lrow * G::ROW];
   }
 
   // z = M^{-1} r at the optimal weights (a, b) = (1, -1), in the scaled
@@ -708,12 +708,12 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
       // ---- inner system  Ahat d = L^{-1} r64  for the systems still running
       float r[EPT], p[EPT], z[EPT], qv[EPT];
       {
-        c.put(&sm.V[0][c.lrow * G::ROW], r64f);
+        c.put(sm.V[0], c.lrow, r64f);
         c.put_flag(!done);
         __syncthreads();
         if (!c.any_after_barrier()) break;  // every system of the bin is done
         if (!done) ++c.ntr;
-        const float* rk = &sm.V[0][c.lrow * G::ROW];
+        const float* rk = sm.V[0];
         float Lv[EPT][NB];
         if (c.row_ok && !done) {
           c.template load_li_rows<PK>(Li, g, Lv);
@@ -727,7 +727,8 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
         for (int e = 0; e < EPT; ++e) {
           float acc = 0.f;
 #pragma unroll
-          for (int j = 0; j < NB; ++j) acc = __fmaf_rn(Lv[e][j], rk[spos(j)], acc);
+          for (int j = 0; j < NB; ++j)
+            acc = __fmaf_rn(Lv[e][j], rk[c.slot(c.lrow, j / 3) + j % 3], acc);
           r[e] = acc;
           d[e] = 0.f;
         }
