@@ -151,6 +151,17 @@ struct Ctx {
     return row * G::ROW + 4 * (ch ^ (SWZ ? (row >> 2) & 1 : 0));
   }
 
+  // A 16-byte chunk from LDS, of which three entries are used. In the
+  // two-lane layout the fourth is kept alive so the read stays
+  // ds_read_b128: the compiler would narrow it to a 12-byte read, whose
+  // accesses meet in the banks (about twice the conflict cycles, measured);
+  // elsewhere the narrow read costs no conflicts and fewer registers.
+  __device__ __forceinline__ static float4 ld16(const float* p) {
+    const float4 u = *reinterpret_cast<const float4*>(p);
+    if constexpr (SWZ) asm volatile("" ::"v"(u.w));
+    return u;
+  }
+
   // own entries into staged row ``row`` of ``base`` (SUB 16-byte slots)
   __device__ __forceinline__ void put(float* base, int row,
                                       const float (&v)[EPT]) const {
@@ -332,7 +343,7 @@ struct Ctx {
       for (int h = 0; h < G::SUB; ++h) {
         const float* tr = k > 0 ? sm.T[BUF] + slot(lrow - 1, G::SUB * q + h)
                                 : sm.Z + 4 * (G::SUB * q + h);
-        const float4 u = *reinterpret_cast<const float4*>(tr);
+        const float4 u = ld16(tr);
         acc[3 * h] = u.x;
         acc[3 * h + 1] = u.y;
         acc[3 * h + 2] = u.z;
@@ -342,8 +353,7 @@ struct Ctx {
     for (int c = 0; c < G::TPR; ++c) {
 #pragma unroll
       for (int h = 0; h < G::SUB; ++h) {
-        const float4 u = *reinterpret_cast<const float4*>(
-            sm.V[BUF] + slot(rp, G::SUB * (c ^ q) + h));
+        const float4 u = ld16(sm.V[BUF] + slot(rp, G::SUB * (c ^ q) + h));
         const float uc[3] = {u.x, u.y, u.z};
 #pragma unroll
         for (int e = 0; e < EPT; ++e)
