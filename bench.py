@@ -670,7 +670,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32 inner / f64 refined",
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "instances": B,
                    "horizons": "uniform 16..256", "nx": n, "nu": w["nu"],
