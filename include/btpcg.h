@@ -61,6 +61,13 @@ extern "C" {
 #define BT_ETIMEOUT (-7)    /* bt_solve_grid: a grid barrier waited longer
                                than its limit (bt_set_grid_wait) and the
                                solve gave up; x is not a solution */
+#define BT_ESTAGNATED (-8)  /* float32 + refinement: a refinement step
+                               reduced the float64 residual by less than a
+                               factor 2 (the float32 operator is too coarse
+                               for the system's conditioning); x holds the
+                               last iterate. With bt_params.fallback_f64 set,
+                               bt_solve and bt_solve_batched finish such a
+                               system in float64 instead. */
 
 /* Arithmetic of the iteration. */
 #define BT_F64 0     /* float64 throughout */
@@ -103,17 +110,28 @@ typedef struct bt_params {
                              record) and the test stays ||r|| <= tol ||b||.
                              b = 0 still gives x = 0. bt_solve_adjoint and
                              bt_precondition ignore it. */
+  int fallback_f64;       /* BT_F32_IR: 1 keeps float64 factors and scaled
+                             off-diagonal blocks of every system in the
+                             workspace (3 R n^2 float64 more), and
+                             bt_solve / bt_solve_batched finish each system
+                             whose refinement stagnated (BT_ESTAGNATED) by a
+                             float64 PCG from its current iterate, on the
+                             device, in the same call and stream: the
+                             float64 setup and solve passes skip every
+                             system that did not stagnate. 0: such a system
+                             stops with BT_ESTAGNATED. Other precisions
+                             ignore it. */
 } bt_params;
 
 /* Defaults: a = 1, b = -1, m = 2, alpha = {1, 7} (the paper's "PolyCoeff"
  * choice, Section V), BT_PC_POLY, BT_F64, max_outer = 30, inner_tol = 1e-4,
- * warm_start = 0. */
+ * warm_start = 0, fallback_f64 = 0. */
 void bt_default_params(bt_params* p);
 
 /* Per-instance outcome, written on the device (48 bytes). */
 typedef struct bt_info {
   int32_t status;      /* BT_OK, BT_NOT_CONVERGED, BT_ENOTSPD, BT_EBREAKDOWN,
-                          BT_ENONFINITE */
+                          BT_ENONFINITE, BT_ESTAGNATED, BT_ETIMEOUT */
   int32_t iters;       /* PCG iterations = products with A (summed over the
                           inner solves under BT_F32_IR) */
   int32_t outer;       /* refinement steps (BT_F32_IR), else 1 */

@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libbtpcg.so")
 OK, NOT_CONVERGED, EINVAL, ENOTSPD, EBREAKDOWN, ENONFINITE, EHIP, ENOSPACE = \
     0, 1, -1, -2, -3, -4, -5, -6
 ETIMEOUT = -7
+ESTAGNATED = -8
 F64, F32, F32_IR, BF16X2_IR = 0, 1, 2, 3
 DT_F64, DT_F32 = 0, 1
 PC_POLY, PC_NONE = 0, 1
@@ -38,7 +39,7 @@ class _Params(ctypes.Structure):
                 ("m", ctypes.c_int), ("pc", ctypes.c_int),
                 ("alpha", ctypes.c_double * MAX_M), ("prec", ctypes.c_int),
                 ("max_outer", ctypes.c_int), ("inner_tol", ctypes.c_double),
-                ("warm_start", ctypes.c_int)]
+                ("warm_start", ctypes.c_int), ("fallback_f64", ctypes.c_int)]
 
 
 class BtError(RuntimeError):
@@ -132,6 +133,9 @@ class Params:
     default: all ones); pc: "poly" or "none"; prec: "f64", "f32", "f32_ir";
     warm_start: the solves start from the x passed in (initial guess)
     instead of 0.
+    fallback_f64: under "f32_ir", a system whose refinement stagnates is
+    finished in float64 on the device (the workspace holds float64 factors
+    too); without it such a system stops with status ESTAGNATED.
     """
     a: float = 1.0
     b: Optional[float] = None
@@ -142,6 +146,7 @@ class Params:
     max_outer: int = 30
     inner_tol: float = 1e-4
     warm_start: bool = False
+    fallback_f64: bool = False
 
     @staticmethod
     def polycoeff(m: int = 2, **kw) -> "Params":
@@ -169,6 +174,7 @@ class Params:
         p.max_outer = int(self.max_outer)
         p.inner_tol = float(self.inner_tol)
         p.warm_start = 1 if self.warm_start else 0
+        p.fallback_f64 = 1 if self.fallback_f64 else 0
         return p
 
 

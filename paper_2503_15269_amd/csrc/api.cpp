@@ -18,6 +18,7 @@ namespace {
 using btv::align_up;
 using btv::check_offsets;
 using btv::elem_bytes;
+using btv::keeps_f64;
 using btv::fast_capable;
 using btv::Layout;
 using btv::layout;
@@ -151,6 +152,53 @@ int run(const bt_handle* h, SolveArgs& a, hipStream_t s) {
   return hip_status(bt_launch_solve(cfg, a, grid, s));
 }
 
+// After a float32 + refinement solve (fallback_f64): the systems whose
+// refinement stagnated (info BT_ESTAGNATED) get float64 factors and blocks
+// (setup kernels masked by info: workgroups without such a system return at
+// once) and a float64 PCG from their current iterate (the generic kernel,
+// every other system skipped). Enqueued unconditionally, so the call stays
+// free of host waits; with nothing stagnated both passes only read info.
+int fallback_f64(const bt_handle* h, const double* b, double* x, double tol,
+                 int maxit, bt_info* info, hipStream_t s) {
+  if (bt_launch_setup_init(h->B, h->fail, h->ctr, s) != hipSuccess)
+    return BT_EHIP;
+  SetupArgs g{};
+  g.B = h->B;
+  g.n = h->n;
+  g.dtype = h->dtype;
+  g.prec = BT_F64;
+  g.R = h->R;
+  g.off = h->off;
+  g.rowinst = h->rowinst;
+  g.D = h->D;
+  g.O = h->O;
+  g.fail = h->fail;
+  g.F = h->F64;
+  g.L = h->L64;
+  g.Li = h->Li64;
+  g.Lp = nullptr;
+  g.mask = info;
+  if (bt_launch_setup(g, s) != hipSuccess) return BT_EHIP;
+  SolveArgs a = base_args(h);
+  a.ir = 0;
+  a.mode = 0;
+  a.warm = 1;
+  a.F = h->F64;
+  a.L = h->L64;
+  a.Li = h->Li64;
+  a.Lp = nullptr;
+  a.b = b;
+  a.x = x;
+  a.info = info;
+  a.tol = tol;
+  a.maxit = maxit;
+  a.only_stagnated = 1;
+  const int cfg = auto_config(BT_F64, (int64_t)h->maxN * h->n);
+  if (cfg < 0) return BT_EINVAL;
+  const int grid = std::max(1, std::min(h->B, bt_solve_max_grid(cfg)));
+  return hip_status(bt_launch_solve(cfg, a, grid, s));
+}
+
 }  // namespace
 
 extern "C" {
@@ -180,6 +228,7 @@ const char* bt_strerror(int code) {
     case BT_EHIP: return "HIP runtime error";
     case BT_ENOSPACE: return "workspace too small";
     case BT_ETIMEOUT: return "a grid barrier gave up waiting (workgroups not all resident)";
+    case BT_ESTAGNATED: return "float32 refinement stagnated (the system is too ill-conditioned for the float32 operator)";
     default: return "unknown status";
   }
 }
@@ -191,7 +240,7 @@ size_t bt_workspace_bytes(int B, const int64_t* offsets_host, int n,
   const int64_t R = check_offsets(B, offsets_host, &maxN);
   if (R < 0) return 0;
   return layout(B, R, n, elem_bytes(p), p->prec == BT_BF16X2_IR,
-                fast_capable(n, p))
+                fast_capable(n, p), keeps_f64(p))
       .total;
 }
 
@@ -213,8 +262,11 @@ int bt_batch_setup(bt_handle** h, int B, const int64_t* offsets_host, int n,
       auto_config(kernel_prec(p), (int64_t)maxN * n) < 0)
     return BT_EINVAL;
   const Layout l = layout(B, R, n, elem_bytes(p), p->prec == BT_BF16X2_IR,
-                          fast_capable(n, p));
+                          fast_capable(n, p), keeps_f64(p));
   if (ws_bytes < l.total) return BT_ENOSPACE;
+  // the float64 fallback runs the generic kernel on the largest system
+  if (keeps_f64(p) && auto_config(BT_F64, (int64_t)maxN * n) < 0)
+    return BT_EINVAL;
 
   bt_handle* hh = new (std::nothrow) bt_handle();
   if (!hh) return BT_EHIP;
@@ -243,6 +295,11 @@ int bt_batch_setup(bt_handle** h, int B, const int64_t* offsets_host, int n,
   if (p->prec == BT_BF16X2_IR) {
     hh->Fhi = (unsigned short*)(w + l.Fhi);
     hh->Flo = (unsigned short*)(w + l.Flo);
+  }
+  if (keeps_f64(p)) {
+    hh->F64 = w + l.F64;
+    hh->L64 = w + l.L64;
+    hh->Li64 = w + l.Li64;
   }
   hh->off_host.assign(offsets_host, offsets_host + B + 1);
 
@@ -343,7 +400,9 @@ static int solve_from(const bt_handle* h, const double* b, double* x,
   a.info = info;
   a.tol = tol;
   a.maxit = maxit;
-  return run(h, a, (hipStream_t)stream);
+  const int rc = run(h, a, (hipStream_t)stream);
+  if (rc != BT_OK || !h->F64) return rc;
+  return fallback_f64(h, b, x, tol, maxit, info, (hipStream_t)stream);
 }
 
 int bt_solve(const bt_handle* h, const double* b, double* x, double tol,

@@ -809,6 +809,7 @@ __global__ void __launch_bounds__(NT) k_g_solve(GArgs<T> a) {
       each([&](int wi) { ph_zero_x(a, wi); });
       barrier();
     }
+    double nr2_prev = INFINITY;  // before the last correction
     while (!aborted) {
       each([&](int wi) { ph_res(a, wi, red); });
       if (!barrier()) break;
@@ -825,7 +826,10 @@ __global__ void __launch_bounds__(NT) k_g_solve(GArgs<T> a) {
       }
       if (nr2 <= a.tol * a.tol * nb2) { status = BT_OK; break; }
       if (!(nr2 < INFINITY)) { status = BT_ENONFINITE; break; }
+      // a correction that cut the float64 residual by less than 2x
+      if (outer > 0 && nr2 > 0.25 * nr2_prev) { status = BT_ESTAGNATED; break; }
       if (outer >= a.max_outer || total >= a.maxit) break;
+      nr2_prev = nr2;
       st.sscale = bt_unit_scale(nr2);
       st.xscale = 1.0 / st.sscale;
       int settled = BT_NOT_CONVERGED;

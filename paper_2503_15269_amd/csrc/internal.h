@@ -39,6 +39,11 @@ struct bt_handle {
   void* Lp = nullptr;
   unsigned short* Fhi = nullptr;  // BT_BF16X2_IR: [2][R][n][n], F then F^T
   unsigned short* Flo = nullptr;  // blockwise, split into bfloat16 hi + lo
+  // fallback_f64: float64 F, L, L^{-1} for systems whose float32 refinement
+  // stagnated (computed, for those systems only, by the fallback pass)
+  void* F64 = nullptr;
+  void* L64 = nullptr;
+  void* Li64 = nullptr;
   int cfg = -1;             // solve-kernel configuration, -1 = automatic
   // L is current (the register-resident kernel does not read it; for the
   // other kernels it is computed on first use)
@@ -93,6 +98,10 @@ struct SolveArgs {
   const double* b;   // right-hand side (mode 0) or r (mode 1)
   double* x;         // solution (mode 0) or z (mode 1)
   bt_info* info;
+  // float64 fallback pass: only the systems whose info reports
+  // BT_ESTAGNATED are solved (from their current x); their counts add to
+  // the float32 solve's
+  int only_stagnated;
 };
 
 // Arguments of the setup kernel. L or F null: not computed.
@@ -109,6 +118,9 @@ struct SetupArgs {
   void* F;
   void* L;
   void* Li;
+  // non-null: only the block rows of systems whose info reports
+  // BT_ESTAGNATED are needed (a workgroup without any returns at once)
+  const bt_info* mask;
 };
 
 // The paper's block gemvs per block row and PCG iteration, g_a(m) of

@@ -639,6 +639,7 @@ __global__ void __launch_bounds__(256) k_mr_colsum(MrArgs a) {
       a.first[c] = 0;
     }
   } else {  // SUM_RES: float64 residual of the record
+    const double prev = a.nr2[c];  // before the last correction
     a.nr2[c] = tot;
     if (!a.done[c]) {
       const double t2 = a.tol * a.tol * a.nb2[c];
@@ -647,6 +648,10 @@ __global__ void __launch_bounds__(256) k_mr_colsum(MrArgs a) {
         a.done[c] = 1;
       } else if (!(tot < INFINITY)) {
         a.status[c] = BT_ENONFINITE;
+        a.done[c] = 1;
+      } else if (a.outer[c] > 0 && tot > 0.25 * prev) {
+        // the correction cut the float64 residual by less than 2x
+        a.status[c] = BT_ESTAGNATED;
         a.done[c] = 1;
       } else if (a.total[c] >= a.maxit) {
         a.done[c] = 1;

@@ -69,8 +69,22 @@ __device__ __forceinline__ void store(void* P, size_t i, double v) {
   ((T*)P)[i] = (T)v;
 }
 
+// Under a fallback mask only the block rows of systems whose float32
+// refinement stagnated are needed: a workgroup whose rows [g0, g1) hold none
+// returns at once (every thread takes part in the vote, so the return is
+// uniform).
+__device__ __forceinline__ bool rows_needed(const SetupArgs& a, int64_t g0,
+                                            int64_t g1) {
+  if (!a.mask) return true;
+  bool any = false;
+  for (int64_t g = g0 + threadIdx.x; g < g1 && g < a.R; g += blockDim.x)
+    any = any || a.mask[a.rowinst[g]].status == BT_ESTAGNATED;
+  return __syncthreads_or(any);
+}
+
 template <int NT, typename T>
 __global__ void __launch_bounds__(NT) k_setup(SetupArgs a) {
+  if (!rows_needed(a, blockIdx.x, (int64_t)blockIdx.x + 1)) return;
   extern __shared__ double sm[];
   __shared__ int flag;
   const int n = a.n;
@@ -254,6 +268,7 @@ __global__ void __launch_bounds__(64) k_factor_lane(SetupArgs a) {
   constexpr int NN = NB * NB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int64_t g0 = (int64_t)blockIdx.x * 64;
+  if (!rows_needed(a, g0, g0 + 64)) return;
   const int l = threadIdx.x;
   const int64_t g = g0 + l;
   const int nblk = (int)(a.R - g0 < 64 ? a.R - g0 : 64);
@@ -392,6 +407,10 @@ __global__ void __launch_bounds__((64 * OffdiagGeo<NB, T>::WPB))
   constexpr int NN = G::NN, RPW = G::RPW, TPR = G::TPR;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  {
+    const int64_t wg0 = (int64_t)blockIdx.x * G::WPB * RPW;
+    if (!rows_needed(a, wg0, wg0 + G::WPB * RPW)) return;
+  }
   T* Ls = reinterpret_cast<T*>(smem_raw) + (size_t)w * (2 * RPW + 1) * NN;
   T* Os = Ls + (size_t)(RPW + 1) * NN;
   const int64_t g0 = ((int64_t)blockIdx.x * G::WPB + w) * RPW;
@@ -601,6 +620,8 @@ __global__ void __launch_bounds__(64) k_factor_wave(SetupArgs a) {
   constexpr int BPW = NB <= 32 ? 2 : 1, LW = 64 / BPW;
   constexpr int NN = NB * NB;
   extern __shared__ __align__(16) unsigned char smem_raw[];
+  if (!rows_needed(a, (int64_t)blockIdx.x * BPW, (int64_t)blockIdx.x * BPW + BPW))
+    return;
   const int sub = threadIdx.x / LW;        // which block of the wavefront
   const int r = threadIdx.x % LW;          // row of this lane in its block
   // per block: two column buffers (Cholesky step j uses col[j & 1]) and two
@@ -707,6 +728,7 @@ __global__ void __launch_bounds__(256) k_offdiag_block(SetupArgs a) {
   double* Og = Ln + NN;
   double* Tm = Og + NN;
   const int64_t g = blockIdx.x;
+  if (!rows_needed(a, g, g + 1)) return;
   const int t = threadIdx.x;
   const int inst = a.rowinst[g];
   const bool has_next = g + 1 < a.off[inst + 1];
@@ -768,6 +790,7 @@ __global__ void __launch_bounds__(64 * (NB / 16)) k_offdiag_mfma(SetupArgs a) {
   double* Ln = Og + NB * P;
   double* Tm = Ln + NB * P;
   const int64_t g = blockIdx.x;
+  if (!rows_needed(a, g, g + 1)) return;
   const int t = threadIdx.x, w = t >> 6, l = t & 63;
   const int inst = a.rowinst[g];
   const bool has_next = g + 1 < a.off[inst + 1];

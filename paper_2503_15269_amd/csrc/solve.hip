@@ -470,6 +470,7 @@ __device__ __forceinline__ void solve_ir(const SolveArgs& a, Shared<T>& sh,
   const double itol2 = a.inner_tol * a.inner_tol;
   int status = BT_NOT_CONVERGED, total = 0, outer = 0;
   double nr2 = nb2;
+  double nr2_prev = INFINITY;  // before the last correction
   double unscale = 1.0;  // 1 / the scale of the current inner solve
   T r[S], d[S], p[S], q[S], z[S], t[S];
 #pragma unroll
@@ -497,7 +498,14 @@ __device__ __forceinline__ void solve_ir(const SolveArgs& a, Shared<T>& sh,
       status = BT_ENONFINITE;
       break;
     }
+    // a correction that cut the float64 residual by less than 2x: the
+    // float32 operator is too coarse for this system
+    if (outer > 0 && nr2 > 0.25 * nr2_prev) {
+      status = BT_ESTAGNATED;
+      break;
+    }
     if (outer >= a.max_outer || total >= a.maxit) break;
+    nr2_prev = nr2;
     ++outer;
 
     // inner system: Ahat dhat = L^{-1} r64, the residual scaled by a power
@@ -641,6 +649,14 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs a) {
     __syncthreads();
     if (q >= a.B) break;
     const int which = a.order[q];
+    // float64 fallback pass: the other systems keep their result
+    bt_info prev{};
+    if constexpr (MODE == MODE_DIRECT) {
+      if (a.only_stagnated) {
+        prev = a.info[which];
+        if (prev.status != BT_ESTAGNATED) continue;
+      }
+    }
     Inst<T, NT, S> in;
     in.init(a, which);
     if (a.fail[which] != BT_NO_FAIL) {
@@ -658,6 +674,14 @@ __global__ void __launch_bounds__(NT) k_solve(SolveArgs a) {
       solve_ir<T, NT, S>(a, sh, in);
     } else {
       solve_direct<T, NT, S>(a, sh, in);
+      if (a.only_stagnated && threadIdx.x == 0) {
+        // thread 0 wrote the float64 outcome; the float32 steps count too
+        bt_info* inf = a.info + which;
+        inf->iters += prev.iters;
+        inf->outer = prev.outer + 1;
+        inf->gemv_exec += prev.gemv_exec;
+        inf->gemv_paper += prev.gemv_paper;
+      }
     }
     __syncthreads();
   }

@@ -564,6 +564,7 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
     const double tol2 = a.tol * a.tol * nb2;
     int outer = 0, total = 0;
     double nr2 = nb2;
+    double nr2_prev = INFINITY;  // before the last correction
     double unscale = 1.0;  // 1 / the scale of the current inner solve
     c.nh = 0;
     c.ntr = 0;
@@ -710,9 +711,14 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
         } else if (!(nr2 < INFINITY)) {
           status = BT_ENONFINITE;
           done = true;
+        } else if (outer > 0 && nr2 > 0.25 * nr2_prev) {
+          // the correction cut the float64 residual by less than 2x
+          status = BT_ESTAGNATED;
+          done = true;
         } else if (outer >= a.max_outer || total >= a.maxit) {
           done = true;
         }
+        nr2_prev = nr2;
       }
 
       // ---- inner system  Ahat d = L^{-1} r64  for the systems still running

@@ -41,6 +41,7 @@ inline bool params_ok(const bt_params* p) {
   for (int i = 1; i < p->m; ++i)
     if (!std::isfinite(p->alpha[i])) return false;
   if (p->warm_start != 0 && p->warm_start != 1) return false;
+  if (p->fallback_f64 != 0 && p->fallback_f64 != 1) return false;
   if (p->prec == BT_F32_IR || p->prec == BT_BF16X2_IR) {
     if (p->max_outer < 1) return false;
     if (!(p->inner_tol > 0.0 && p->inner_tol < 1.0)) return false;
@@ -75,8 +76,13 @@ inline int64_t check_offsets(int B, const int64_t* off, int* maxN) {
 
 struct Layout {
   size_t off, order, rowinst, ctr, fail, bins, items, F, L, Li, Lp, Fhi, Flo,
-      total;
+      F64, L64, Li64, total;
 };
+
+// Float64 factors for the fallback of stagnating float32 refinement.
+inline bool keeps_f64(const bt_params* p) {
+  return p->fallback_f64 && p->prec == BT_F32_IR;
+}
 
 // The register-resident kernel can serve the handle (block size and
 // precision; whether its systems fit its bins is decided at setup).
@@ -86,7 +92,7 @@ inline bool fast_capable(int n, const bt_params* p) {
 
 // Workspace layout of a handle: every region 256-byte aligned.
 inline Layout layout(int B, int64_t R, int n, size_t es, bool split,
-                     bool packed) {
+                     bool packed, bool f64 = false) {
   Layout l{};
   size_t at = 0;
   l.off = at; at += align_up(sizeof(int64_t) * (B + 1));
@@ -105,6 +111,10 @@ inline Layout layout(int B, int64_t R, int n, size_t es, bool split,
   const size_t hblk = split ? align_up(2 * 2 * (size_t)R * n * n) : 0;
   l.Fhi = at; at += hblk;
   l.Flo = at; at += hblk;
+  const size_t dblk = f64 ? align_up(sizeof(double) * (size_t)R * n * n) : 0;
+  l.F64 = at; at += dblk;
+  l.L64 = at; at += dblk;
+  l.Li64 = at; at += dblk;
   l.total = at;
   return l;
 }
