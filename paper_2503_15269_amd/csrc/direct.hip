@@ -336,6 +336,18 @@ __device__ __forceinline__ void sfor(F&& f) {
   }
 }
 
+// 1 / sqrt(d) for d > 0: the hardware estimate and two Newton steps
+// y <- y + y (1 - d y^2) / 2, each doubling the correct bits.
+__device__ __forceinline__ double rsqrt_nr(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-d * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
+
 // 1 / d: the hardware estimate and two Newton steps y <- y + y (1 - d y).
 __device__ __forceinline__ double rcp_nr(double d) {
   double y = __builtin_amdgcn_rcp(d);
@@ -562,6 +574,321 @@ __global__ void __launch_bounds__(64 * kDirectWaves) k_direct4(DirectArgs a) {
   }
 }
 
+// ------------------------------------------------------------------------
+// n = 32, 48, 64: one workgroup per system, a wavefront per 16-wide strip,
+// the n^3 parts of each block row on the matrix cores
+// (v_mfma_f64_16x16x4f64), the blocks in LDS (rows padded to n + 2 entries,
+// so the 16 rows a wavefront reads at once fall in distinct banks):
+//   S_k = D_k - Z_k^T Z_k                 (Z_k = L_{k-1}^{-1} O_{k-1})
+//   L_k = chol(S_k), blocked by 16: the diagonal block factored (and
+//        inverted) by the column-in-lane DPP code of the small sizes, the
+//        panel below it times the inverse's transpose, the trailing blocks
+//        updated, all products on MFMA
+//   L_k^{-1} by block diagonals: X_ij = -X_ii sum_{k=j}^{i-1} L_ik X_kj
+//   y_k = L_k^{-1} (b_k - Z_k^T y_{k-1}),   Z_{k+1} = L_k^{-1} O_k
+// and backward x_k = L_k^{-T} (y_k - Z_{k+1} x_{k+1}): with the inverse
+// stored, both sweeps are products, never substitutions.
+// MFMA 16x16x4 float64 layouts: A operand lane l = A[l % 16][l / 16], B
+// operand lane l = B[l / 16][l % 16], result lane l element i =
+// D[4 i + l / 16][l % 16].
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+
+template <int NB>
+struct MfLds {
+  static constexpr int P = NB + 2;  // padded row stride
+  static constexpr int W = NB / 16;
+  static constexpr int TP = 17;     // stride of a wave's scratch tile
+  double S[NB * P];                 // D_k, S_k, then L_k (lower blocks)
+  double I[NB * P];                 // L_k^{-1} (lower blocks)
+  double Z[NB * P];                 // Z_k, then Z_{k+1}
+  double O[NB * P];                 // O_k
+  double T[W][16 * TP];             // per-wavefront tile hand-off
+  double v[NB], y[NB];
+  int fail;
+};
+
+// acc += (NEG ? -1 : 1) Xb Yb over K entries (a multiple of 4): Xb the 16
+// rows xr.. and columns xc.. of X (TX: of X^T, read as X[xc + kk][xr + i]),
+// Yb the rows yr.. and 16 columns yc.. of Y (TY: of Y^T). PX, PY: strides.
+template <int PX, int PY, bool TX, bool TY, bool NEG>
+__device__ __forceinline__ mf_d4 mm(const double* X, int xr, int xc,
+                                    const double* Y, int yr, int yc, int K,
+                                    mf_d4 acc, int li, int lk) {
+#pragma unroll 4
+  for (int s = 0; s < K; s += 4) {
+    const int kk = s + lk;
+    double av = TX ? X[(xc + kk) * PX + xr + li] : X[(xr + li) * PX + xc + kk];
+    if (NEG) av = -av;
+    const double bv = TY ? Y[(yc + li) * PY + yr + kk] : Y[(yr + kk) * PY + yc + li];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+  }
+  return acc;
+}
+
+template <int P>
+__device__ __forceinline__ mf_d4 tile_ld(const double* X, int r0, int c0,
+                                         int li, int lk) {
+  mf_d4 t;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) t[i] = X[(r0 + 4 * i + lk) * P + c0 + li];
+  return t;
+}
+template <int P>
+__device__ __forceinline__ void tile_st(double* X, int r0, int c0, mf_d4 t,
+                                        int li, int lk) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) X[(r0 + 4 * i + lk) * P + c0 + li] = t[i];
+}
+
+// Order the LDS accesses of one wavefront (a hand-off through its scratch
+// tile between lanes).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Diagonal block (b, b) of S, 16 x 16, by lanes 0..15 of one wavefront (the
+// column-in-lane pivot loop of the small sizes, unscaled): lane c ends with
+// column c of L_bb written into S and column c of L_bb^{-1} into I. Returns
+// false in every lane if a pivot is not positive.
+template <int P>
+__device__ __forceinline__ bool diag_block(double* S, double* I, int b,
+                                           int c) {
+  const int cc = c & 15;
+  double Sd[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r)
+    Sd[r] = r >= cc ? S[(b + r) * P + b + cc] : S[(b + cc) * P + b + r];
+  double dso = 1.0;
+  bool spd = true;
+  sfor<0, 16>([&](auto J) {
+    constexpr int j = decltype(J)::value;
+    const double d = nb<j>(Sd[j]);
+    spd = spd && d > 0.0 && d < INFINITY;
+    dso = cc == j ? d : dso;
+    const double m = cc > j ? Sd[j] * rcp_nr(d) : 0.0;
+    sfor<0, (15 - j) / 4>([&](auto G) {
+      constexpr int r = j + 1 + 4 * decltype(G)::value;
+      self4<j>(Sd[r], Sd[r + 1], Sd[r + 2], Sd[r + 3], m);
+    });
+    sfor<j + 1 + 4 * ((15 - j) / 4), 16>([&](auto R) {
+      constexpr int r = decltype(R)::value;
+      Sd[r] = self1<j>(Sd[r], m);
+    });
+  });
+  const double rs = rsqrt_nr(dso);  // 1 / L[cc][cc]
+  double Lc[16], X[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    Lc[r] = r > cc ? Sd[r] * rs : (r == cc ? dso * rs : 0.0);
+    X[r] = r == cc ? 1.0 : 0.0;
+  }
+  // column cc of L^{-1}: L X = e_cc by forward substitution, the entries of
+  // L from their columns' lanes
+  sfor<0, 16>([&](auto Pp) {
+    constexpr int p = decltype(Pp)::value;
+    X[p] *= nb<p>(rs);
+    sfor<p + 1, 16>([&](auto R) {
+      constexpr int r = decltype(R)::value;
+      X[r] = fnb<p>(X[r], Lc[r], X[p]);
+    });
+  });
+  if (c < 16) {
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      S[(b + r) * P + b + c] = Lc[r];
+      I[(b + r) * P + b + c] = X[r];
+    }
+  }
+  dpp_exec_fence();
+  return spd;
+}
+
+template <int NB, typename Rec>
+__global__ void __launch_bounds__(NB * 4) k_direct_mfma(DirectArgs a) {
+  using M = MfLds<NB>;
+  constexpr int P = M::P, W = M::W, NT = 64 * W, NN = NB * NB;
+  constexpr int PF = (NN + NT - 1) / NT;  // prefetched entries per thread
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  M& sm = *reinterpret_cast<M*>(smem_raw);
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const int li = l & 15, lk = l >> 4;
+  const int sys = a.order[blockIdx.x];
+  const int64_t r0 = a.off[sys];
+  const int N = (int)(a.off[sys + 1] - r0);
+  const int ob0 = (int)(r0 - sys);
+  if (t == 0) sm.fail = -1;
+
+  // entries e = t + NT i of D_k (lower triangle: the upper is never read)
+  // and O_{k} into registers
+  double pd[PF], po[PF];
+  auto fetch = [&](int k) {
+    const int64_t g = r0 + k;
+    const bool hasO = k + 1 < N;
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+      const int e = min(t + NT * i, NN - 1);
+      pd[i] = ld<Rec>(a.D, (size_t)g * NN + e);
+      po[i] = hasO ? ld<Rec>(a.O, (size_t)(ob0 + k) * NN + e) : 0.0;
+    }
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+      const int e = t + NT * i;
+      if (e < NN) {
+        const int r = e / NB, cl = e - r * NB;
+        sm.S[r * P + cl] = pd[i];
+        sm.O[r * P + cl] = po[i];
+      }
+    }
+  };
+  fetch(0);
+  for (int k = 0; k < N; ++k) {
+    const int64_t g = r0 + k;
+    stage();
+    if (k + 1 < N) fetch(k + 1);
+    __syncthreads();
+    // S_k = D_k - Z_k^T Z_k (lower tiles) and v = b_k - Z_k^T y_{k-1}
+    if (t < NB) {
+      double v = a.b[g * NB + t];
+      if (k > 0)
+        for (int p = 0; p < NB; ++p) v = fma(-sm.Z[p * P + t], sm.y[p], v);
+      sm.v[t] = v;
+    }
+    if (k > 0) {
+      for (int tile = w; tile < W * (W + 1) / 2; tile += W) {
+        int I = 0;
+        while ((I + 1) * (I + 2) / 2 <= tile) ++I;
+        const int J = tile - I * (I + 1) / 2;
+        mf_d4 acc = tile_ld<P>(sm.S, 16 * I, 16 * J, li, lk);
+        acc = mm<P, P, true, false, true>(sm.Z, 16 * I, 0, sm.Z, 0, 16 * J, NB,
+                                          acc, li, lk);
+        tile_st<P>(sm.S, 16 * I, 16 * J, acc, li, lk);
+      }
+    }
+    __syncthreads();
+    // blocked Cholesky of S_k with the inverses of the diagonal blocks
+    for (int jb = 0; jb < W; ++jb) {
+      if (w == 0) {
+        const bool spd = diag_block<P>(sm.S, sm.I, 16 * jb, l);
+        if (!spd && l == 0 && sm.fail < 0) sm.fail = k;
+      }
+      __syncthreads();
+      // panel: L_ib,jb = S_ib,jb L_jb,jb^{-T}
+      for (int ib = jb + 1 + w; ib < W; ib += W) {
+        mf_d4 acc = {0.0, 0.0, 0.0, 0.0};
+        acc = mm<P, P, false, true, false>(sm.S, 16 * ib, 16 * jb, sm.I,
+                                           16 * jb, 16 * jb, 16, acc, li, lk);
+        tile_st<P>(sm.S, 16 * ib, 16 * jb, acc, li, lk);
+      }
+      __syncthreads();
+      // trailing: S_ib,jc -= L_ib,jb L_jc,jb^T for ib >= jc > jb
+      const int rem = W - 1 - jb;
+      for (int tile = w; tile < rem * (rem + 1) / 2; tile += W) {
+        int u = 0;
+        while ((u + 1) * (u + 2) / 2 <= tile) ++u;
+        const int ib = jb + 1 + u, jc = jb + 1 + (tile - u * (u + 1) / 2);
+        mf_d4 acc = tile_ld<P>(sm.S, 16 * ib, 16 * jc, li, lk);
+        acc = mm<P, P, false, true, true>(sm.S, 16 * ib, 16 * jb, sm.S,
+                                          16 * jb, 16 * jc, 16, acc, li, lk);
+        tile_st<P>(sm.S, 16 * ib, 16 * jc, acc, li, lk);
+      }
+      __syncthreads();
+    }
+    // L_k^{-1} below the diagonal blocks, one block diagonal at a time
+    for (int d = 1; d < W; ++d) {
+      for (int jb = w; jb + d < W; jb += W) {
+        const int ib = jb + d;
+        mf_d4 acc = {0.0, 0.0, 0.0, 0.0};
+        for (int kb = jb; kb < ib; ++kb)
+          acc = mm<P, P, false, false, false>(sm.S, 16 * ib, 16 * kb, sm.I,
+                                              16 * kb, 16 * jb, 16, acc, li,
+                                              lk);
+        tile_st<M::TP>(sm.T[w], 0, 0, acc, li, lk);
+        wave_lds_sync();
+        mf_d4 x = {0.0, 0.0, 0.0, 0.0};
+        x = mm<P, M::TP, false, false, true>(sm.I, 16 * ib, 16 * ib, sm.T[w],
+                                             0, 0, 16, x, li, lk);
+        tile_st<P>(sm.I, 16 * ib, 16 * jb, x, li, lk);
+        wave_lds_sync();
+      }
+      __syncthreads();
+    }
+    // y_k = L_k^{-1} v, then Z_{k+1} = L_k^{-1} O_k
+    if (t < NB) {
+      double y = 0.0;
+      for (int j = 0; j <= t; ++j) y = fma(sm.I[t * P + j], sm.v[j], y);
+      sm.y[t] = y;
+      a.x[g * NB + t] = y;  // y_k, replaced by x_k on the way back
+    }
+    if (k + 1 < N) {
+      for (int tile = w; tile < W * W; tile += W) {
+        const int I = tile / W, J = tile - I * W;
+        mf_d4 acc = {0.0, 0.0, 0.0, 0.0};
+        acc = mm<P, P, false, false, false>(sm.I, 16 * I, 0, sm.O, 0, 16 * J,
+                                            16 * (I + 1), acc, li, lk);
+        tile_st<P>(sm.Z, 16 * I, 16 * J, acc, li, lk);
+      }
+    }
+    __syncthreads();
+    // L_k^{-1} and Z_{k+1} for the backward sweep (zeros above the diagonal)
+    for (int e = t; e < NN; e += NT) {
+      const int r = e / NB, cl = e - r * NB;
+      a.Lbuf[(size_t)g * NN + e] = cl <= r ? sm.I[r * P + cl] : 0.0;
+      if (k + 1 < N) a.Mbuf[(size_t)(g + 1) * NN + e] = sm.Z[r * P + cl];
+    }
+  }
+
+  // ----------------------------------------------------------- backward
+  // x_k = L_k^{-T} (y_k - Z_{k+1} x_{k+1}); the blocks of row k - 1 are
+  // loaded while row k is computed
+  auto bfetch = [&](int k) {
+    const int64_t g = r0 + k;
+#pragma unroll
+    for (int i = 0; i < PF; ++i) {
+      const int e = min(t + NT * i, NN - 1);
+      pd[i] = a.Lbuf[(size_t)g * NN + e];
+      po[i] = k + 1 < N ? a.Mbuf[(size_t)(g + 1) * NN + e] : 0.0;
+    }
+  };
+  __syncthreads();
+  bfetch(N - 1);
+  for (int k = N - 1; k >= 0; --k) {
+    const int64_t g = r0 + k;
+    stage();  // L_k^{-1} into S, Z_{k+1} into O
+    if (k > 0) bfetch(k - 1);
+    __syncthreads();
+    if (t < NB) {
+      double u = a.x[g * NB + t];
+      if (k + 1 < N)
+        for (int j = 0; j < NB; ++j) u = fma(-sm.O[t * P + j], sm.y[j], u);
+      sm.v[t] = u;
+    }
+    __syncthreads();
+    if (t < NB) {
+      double x = 0.0;
+      for (int j = t; j < NB; ++j) x = fma(sm.S[j * P + t], sm.v[j], x);
+      a.x[g * NB + t] = x;
+      sm.y[t] = x;  // x_k for the row above
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    bt_info* inf = a.info + sys;
+    const int fail = sm.fail;
+    inf->status = fail < 0 ? BT_OK : BT_ENOTSPD;
+    inf->iters = 0;
+    inf->outer = 0;
+    inf->fail_index = fail;
+    inf->relres = NAN;
+    inf->relres_true = NAN;
+    inf->gemv_exec = 0;
+    inf->gemv_paper = 0;
+  }
+}
+
 template <int NB>
 hipError_t launch_nb(const DirectArgs& a, hipStream_t s) {
   if constexpr (NB <= 16) {
@@ -572,12 +899,28 @@ hipError_t launch_nb(const DirectArgs& a, hipStream_t s) {
     else
       hipLaunchKernelGGL((k_direct4<NB, float>), grid, block, 0, s, a);
     return hipGetLastError();
+  } else if constexpr (NB % 16 == 0) {
+    constexpr size_t lds = sizeof(MfLds<NB>);
+    const void* fn = a.dtype == BT_DT_F64
+                         ? (const void*)k_direct_mfma<NB, double>
+                         : (const void*)k_direct_mfma<NB, float>;
+    const hipError_t e = hipFuncSetAttribute(
+        fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    if (a.dtype == BT_DT_F64)
+      hipLaunchKernelGGL((k_direct_mfma<NB, double>), dim3(a.B), dim3(NB * 4),
+                         lds, s, a);
+    else
+      hipLaunchKernelGGL((k_direct_mfma<NB, float>), dim3(a.B), dim3(NB * 4),
+                         lds, s, a);
+    return hipGetLastError();
+  } else {
+    if (a.dtype == BT_DT_F64)
+      hipLaunchKernelGGL((k_direct<NB, double>), dim3(a.B), dim3(64), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_direct<NB, float>), dim3(a.B), dim3(64), 0, s, a);
+    return hipGetLastError();
   }
-  if (a.dtype == BT_DT_F64)
-    hipLaunchKernelGGL((k_direct<NB, double>), dim3(a.B), dim3(64), 0, s, a);
-  else
-    hipLaunchKernelGGL((k_direct<NB, float>), dim3(a.B), dim3(64), 0, s, a);
-  return hipGetLastError();
 }
 
 }  // namespace btd

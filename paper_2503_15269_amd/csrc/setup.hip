@@ -773,7 +773,8 @@ __global__ void __launch_bounds__(256) k_offdiag_block(SetupArgs a) {
 // give every wavefront the same number of steps.
 // Layouts (16x16x4, float64): A operand lane l = A[l % 16][l / 16], B
 // operand lane l = B[l / 16][l % 16], result lane l element i =
-// D[4 (l / 16) + i][l % 16].
+// D[4 i + l / 16][l % 16] (unlike the float32 shapes, whose element i is
+// row 4 (l / 16) + i).
 template <int NB>
 constexpr size_t offdiag_mfma_lds() {
   return 4 * sizeof(double) * (size_t)NB * (NB + 2);
@@ -820,7 +821,7 @@ __global__ void __launch_bounds__(64 * (NB / 16)) k_offdiag_mfma(SetupArgs a) {
       acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) Tm[(16 * I + 4 * lk + i) * P + 16 * w + li] = acc[i];
+    for (int i = 0; i < 4; ++i) Tm[(16 * I + 4 * i + lk) * P + 16 * w + li] = acc[i];
   }
   __syncthreads();
   // F, row strip w
@@ -835,7 +836,7 @@ __global__ void __launch_bounds__(64 * (NB / 16)) k_offdiag_mfma(SetupArgs a) {
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
-      F[(size_t)(16 * w + 4 * lk + i) * NB + 16 * J + li] = (T)acc[i];
+      F[(size_t)(16 * w + 4 * i + lk) * NB + 16 * J + li] = (T)acc[i];
   }
 }
 
