@@ -75,7 +75,7 @@ struct Bar {
 };
 
 template <typename T>
-struct GArgs {
+struct GArgsBase {
   int R, n, rb, depth, nwin, pc, m, dtype;
   int refine, warm, from_res, max_outer, maxit;
   double a, tol, itol;
@@ -99,6 +99,15 @@ struct GArgs {
   double* part;       // [P_SLOTS][nwin]
   Bar* bar;
   bt_info* info;
+};
+
+// The arguments with the block size fixed at compile time (NS > 0: the
+// loops over a block's entries unroll completely) or read at run time.
+template <typename T, int NS>
+struct GArgs : GArgsBase<T> {
+  __host__ __device__ __forceinline__ int nv() const {
+    return NS > 0 ? NS : this->n;
+  }
 };
 
 // Per-solve state that every workgroup holds identically.
@@ -239,45 +248,53 @@ struct FBlocks {
 
 constexpr size_t FSTAGE_MAX = 48 * 1024;  // bytes of staged blocks at most
 
-template <typename T>
-__device__ FBlocks<T> stage_F(const GArgs<T>& a, int b0, int b1, T* lds) {
-  const size_t nn = (size_t)a.n * a.n;
+// ``copy`` false: the blocks are already in ``lds`` (staged by an earlier
+// phase of the same window), only the descriptor is formed.
+template <typename T, int NS>
+__device__ FBlocks<T> stage_F(const GArgs<T, NS>& a, int b0, int b1, T* lds,
+                              bool copy = true) {
+  const size_t nn = (size_t)a.nv() * a.nv();
   b0 = max(b0, 0);
   b1 = min(b1, a.R - 1);  // F_b exists for b <= R - 2
   FBlocks<T> f{a.F, 0};
   if (lds == nullptr || b1 <= b0) return f;
-  const size_t cnt = (size_t)(b1 - b0) * nn;
-  const T* src = a.F + (size_t)b0 * nn;
-  for (size_t e = threadIdx.x; e < cnt; e += NT) lds[e] = src[e];
-  __syncthreads();
+  if (copy) {
+    const size_t cnt = (size_t)(b1 - b0) * nn;
+    const T* src = a.F + (size_t)b0 * nn;
+    for (size_t e = threadIdx.x; e < cnt; e += NT) lds[e] = src[e];
+    __syncthreads();
+  }
   return FBlocks<T>{lds, b0};
 }
 
-// out = C v on rows [lo, hi); v valid on the rows it needs; both in the
-// window layout (row k at (k - w0) n). Same arithmetic order as the other
-// solve kernels: the F_{k-1}^T term, then the F_k term, in order j.
-template <typename T>
-__device__ void applyC(const GArgs<T>& a, const FBlocks<T>& F, const T* v,
-                       T* out, int w0, int lo, int hi) {
-  const int n = a.n;
+// C v on rows [lo, hi), v valid on the rows it needs, in the window layout
+// (row k at (k - w0) n): ``ep(o, c)`` receives entry o of the window and its
+// value c = (C v)[o], and stores what the caller needs (C v itself, or a
+// combination with other vectors at the same entry). The F_{k-1}^T and F_k
+// terms are summed in two chains and then added.
+template <typename T, int NS, typename Ep>
+__device__ __forceinline__ void applyC(const GArgs<T, NS>& a,
+                                       const FBlocks<T>& F, const T* v,
+                                       int w0, int lo, int hi, Ep&& ep) {
+  const int n = a.nv();
   const size_t nn = (size_t)n * n;
   const int cnt = (hi - lo) * n;
   for (int e = threadIdx.x; e < cnt; e += NT) {
     const int k = lo + e / n, i = e % n;
-    T acc = T(0);
+    T am = T(0), ap = T(0);
     if (k > 0) {
       const T* Fm = F.blk(k - 1, nn) + i;
       const T* vm = v + (k - 1 - w0) * n;
-#pragma unroll 4
-      for (int j = 0; j < n; ++j) acc += Fm[(size_t)j * n] * vm[j];
+#pragma unroll
+      for (int j = 0; j < n; ++j) am += Fm[(size_t)j * n] * vm[j];
     }
     if (k < a.R - 1) {
       const T* Fk = F.blk(k, nn) + (size_t)i * n;
       const T* vp = v + (k + 1 - w0) * n;
-#pragma unroll 4
-      for (int j = 0; j < n; ++j) acc += Fk[j] * vp[j];
+#pragma unroll
+      for (int j = 0; j < n; ++j) ap += Fk[j] * vp[j];
     }
-    out[(k - w0) * n + i] = -acc;
+    ep((k - w0) * n + i, -(am + ap));
   }
 }
 
@@ -288,45 +305,51 @@ __device__ __forceinline__ void shrink(int R, int& lo, int& hi) {
 }
 
 // z = M^{-1} r on the own rows; r known on the whole window (LDS), y, w1,
-// w2, z window buffers. Returns with z valid on [k0, k1).
-template <typename T>
-__device__ void precond(const GArgs<T>& a, const FBlocks<T>& F, const Win& W,
-                        const T* r, T* y, T* w1, T* w2, T* z) {
-  const int n = a.n, w0 = W.w0;
+// w2, z window buffers. Returns with z valid on [k0, k1). The updates of
+// y and z run inside the applications of C that produce their operands.
+template <typename T, int NS>
+__device__ void precond(const GArgs<T, NS>& a, const FBlocks<T>& F,
+                        const Win& W, const T* r, T* y, T* w1, T* w2, T* z) {
+  const int n = a.nv(), w0 = W.w0;
   const T av = (T)a.a, om = (T)(1.0 - a.a);
   int lo = W.w0, hi = W.w1;
-  // y_0 = r + a C r
-  if (a.a != 0.0) {
+  const T* cur = r;  // y_{i}, the operand of the next application
+  if (a.a != 0.0) {  // y_0 = r + a C r
     shrink(a.R, lo, hi);
-    applyC(a, F, r, w1, w0, lo, hi);
-    __syncthreads();
+    applyC(a, F, r, w0, lo, hi, [&](int o, T c) {
+      const T yv = r[o] + av * c;
+      y[o] = yv;
+      z[o] = yv;
+    });
+    cur = y;
+  } else {  // y_0 = r
     for (int e = threadIdx.x; e < (hi - lo) * n; e += NT) {
       const int o = (lo - w0) * n + e;
-      y[o] = r[o] + av * w1[o];
-      z[o] = y[o];
-    }
-  } else {
-    for (int e = threadIdx.x; e < (hi - lo) * n; e += NT) {
-      const int o = (lo - w0) * n + e;
-      y[o] = r[o];
       z[o] = r[o];
     }
   }
   __syncthreads();
   for (int m = 1; m < a.m; ++m) {
-    shrink(a.R, lo, hi);
-    applyC(a, F, y, w1, w0, lo, hi);
-    __syncthreads();
-    if (a.a != 0.0) {
-      shrink(a.R, lo, hi);
-      applyC(a, F, w1, w2, w0, lo, hi);
-      __syncthreads();
-    }
     const T al = (T)a.alpha[m];
-    for (int e = threadIdx.x; e < (hi - lo) * n; e += NT) {
-      const int o = (lo - w0) * n + e;
-      y[o] = a.a != 0.0 ? om * w1[o] + av * w2[o] : w1[o];
-      z[o] += al * y[o];
+    if (a.a != 0.0) {  // y_m = (1 - a) C y + a C (C y)
+      shrink(a.R, lo, hi);
+      applyC(a, F, cur, w0, lo, hi, [&](int o, T c) { w1[o] = c; });
+      __syncthreads();
+      shrink(a.R, lo, hi);
+      applyC(a, F, w1, w0, lo, hi, [&](int o, T c) {
+        const T yv = om * w1[o] + av * c;
+        y[o] = yv;
+        z[o] += al * yv;
+      });
+      cur = y;
+    } else {  // y_m = C y_{m-1}, into the buffer the operand is not in
+      T* nxt = cur == w2 ? y : w2;
+      shrink(a.R, lo, hi);
+      applyC(a, F, cur, w0, lo, hi, [&](int o, T c) {
+        nxt[o] = c;
+        z[o] += al * c;
+      });
+      cur = nxt;
     }
     __syncthreads();
   }
@@ -353,8 +376,8 @@ __device__ __forceinline__ T lowerT(const T* M, const T* v, int n, int k,
 }
 
 // Partial of one reduction over the window's own rows into its slot.
-template <typename T>
-__device__ __forceinline__ void put_partial(const GArgs<T>& a, int slot,
+template <typename T, int NS>
+__device__ __forceinline__ void put_partial(const GArgs<T, NS>& a, int slot,
                                             int wi, double v, double* red) {
   const double s = wg_sum(v, red);
   if (threadIdx.x == 0) st_sh(a.part + slot * a.nwin + wi, s);
@@ -381,12 +404,48 @@ __host__ __device__ __forceinline__ size_t fstage_bytes(int rb, int depth,
 
 // LDS for staged blocks (after the five window vectors), or null when they
 // do not fit
-template <typename T>
-__device__ __forceinline__ T* lds_F(const GArgs<T>& a, double* red) {
-  const int lmax = wlen(a.rb, a.depth + 1, a.n);
-  return fstage_bytes<T>(a.rb, a.depth + 1, a.n) <= FSTAGE_MAX
+template <typename T, int NS>
+__device__ __forceinline__ T* lds_F(const GArgs<T, NS>& a, double* red) {
+  const int lmax = wlen(a.rb, a.depth + 1, a.nv());
+  return fstage_bytes<T>(a.rb, a.depth + 1, a.nv()) <= FSTAGE_MAX
              ? lds_vec<T>(red, 5, lmax)
              : nullptr;
+}
+
+// The factors L_k of a window's own rows, for the stopping norm ||L r||,
+// staged after the blocks F when both fit.
+constexpr size_t LSTAGE_MAX = 32 * 1024;
+template <typename T>
+__host__ __device__ __forceinline__ size_t lstage_bytes(int rb, int n) {
+  return (size_t)rb * n * n * sizeof(T);
+}
+template <typename T>
+__host__ __device__ __forceinline__ bool lstage_fits(int rb, int depth,
+                                                     int n) {
+  return fstage_bytes<T>(rb, depth, n) <= FSTAGE_MAX &&
+         lstage_bytes<T>(rb, n) <= LSTAGE_MAX;
+}
+template <typename T, int NS>
+__device__ __forceinline__ T* lds_L(const GArgs<T, NS>& a, double* red) {
+  const int n = a.nv();
+  if (!lstage_fits<T>(a.rb, a.depth + 1, n)) return nullptr;
+  return lds_F(a, red) + fstage_bytes<T>(a.rb, a.depth + 1, n) / sizeof(T);
+}
+
+// Row i of the lower-triangular block at ``row`` times v (columns 0..i),
+// over a loop of fixed length when n is known at compile time.
+template <typename T, int NS>
+__device__ __forceinline__ T lower_row(const T* row, const T* v, int n,
+                                       int i) {
+  T acc = T(0);
+  if constexpr (NS > 0) {
+#pragma unroll
+    for (int j = 0; j < NS; ++j)
+      if (j <= i) acc += row[j] * v[j];
+  } else {
+    for (int j = 0; j <= i; ++j) acc += row[j] * v[j];
+  }
+  return acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -397,11 +456,12 @@ __device__ __forceinline__ T* lds_F(const GArgs<T>& a, double* red) {
 // u = M^{-1} r on own rows +- 1 and w = Ahat u = u - C u on own rows, from
 // r in LDS on the window (depth D + 1); u and w to memory, partials of r'u
 // and w'u (and ||L r||^2 when ``nrm``) into the slots of parity ``par``.
-template <typename T>
-__device__ void u_and_w(const GArgs<T>& a, const FBlocks<T>& F, const Win& W,
-                        int par, bool nrm, int wi, T* r, T* y, T* w1, T* w2,
-                        T* z, double* red) {
-  const int n = a.n, w0 = W.w0;
+// ``Ls``: the own rows' factors L_k staged in LDS, or null (read from L).
+template <typename T, int NS>
+__device__ void u_and_w(const GArgs<T, NS>& a, const FBlocks<T>& F,
+                        const Win& W, int par, bool nrm, int wi, T* r, T* y,
+                        T* w1, T* w2, T* z, const T* Ls, double* red) {
+  const int n = a.nv(), w0 = W.w0;
   if (a.pc == BT_PC_NONE) {  // u = L^T L r, row-local, on own rows +- 1
     const int lo = max(W.k0 - 1, 0), hi = min(W.k1 + 1, a.R);
     for (int e = threadIdx.x; e < (hi - lo) * n; e += NT) {
@@ -417,26 +477,28 @@ __device__ void u_and_w(const GArgs<T>& a, const FBlocks<T>& F, const Win& W,
   } else {
     precond(a, F, W, r, y, w1, w2, z);
   }
-  applyC(a, F, z, w1, w0, W.k0, W.k1);  // C u on own rows
-  __syncthreads();
   typename AccOf<T>::type g, d, t2;
   g.zero();
   d.zero();
   t2.zero();
-  for (int e = threadIdx.x; e < (W.k1 - W.k0) * n; e += NT) {
-    const int o = (W.k0 - w0) * n + e;
+  // C u on own rows, w = u - C u, and the partials at each entry
+  applyC(a, F, z, w0, W.k0, W.k1, [&](int o, T c) {
+    const int e = o - (W.k0 - w0) * n;
     const size_t gi = (size_t)W.k0 * n + e;
-    const T wv = z[o] - w1[o];
-    a.u[gi] = z[o];
+    const T zv = z[o], wv = zv - c;
+    a.u[gi] = zv;
     st_sh(a.wbuf[par] + gi, wv);
-    g.add_prod(r[o], z[o]);
-    d.add_prod(wv, z[o]);
+    g.add_prod(r[o], zv);
+    d.add_prod(wv, zv);
     if (nrm) {  // ||r|| = ||L rhat|| of the original system
       const int k = W.k0 + e / n, i = e % n;
-      const T tv = lower(a.L, r + (k - w0) * n, n, k, i);
+      const T* rk = r + (k - w0) * n;
+      const T tv = Ls ? lower_row<T, NS>(Ls + ((size_t)(k - W.k0) * n + i) * n,
+                                         rk, n, i)
+                      : lower(a.L, rk, n, k, i);
       t2.add_prod(tv, tv);
     }
-  }
+  });
   double v[3] = {g.value(), d.value(), t2.value()};
   wg_sums<3>(v, red);
   if (threadIdx.x == 0) {
@@ -448,11 +510,14 @@ __device__ void u_and_w(const GArgs<T>& a, const FBlocks<T>& F, const Win& W,
 
 // Start of an inner solve: r = L^{-1} (src * sscale) on the window, xhat = 0,
 // u, w and their partials (parity 0), ||src * sscale||^2.
-template <typename T>
-__device__ void ph_init(const GArgs<T>& a, const St& st, int wi,
-                        double* red) {
+// ``resident``: the workgroup keeps this one window for the whole inner
+// solve, so the blocks staged here (F, and the own rows' L_k for the
+// stopping norm) serve every step.
+template <typename T, int NS>
+__device__ void ph_init(const GArgs<T, NS>& a, const St& st, int wi,
+                        bool resident, double* red) {
   const Win W = window(a.R, a.rb, a.depth + 1, wi);
-  const int n = a.n, len = (W.w1 - W.w0) * n;
+  const int n = a.nv(), len = (W.w1 - W.w0) * n;
   const int lmax = wlen(a.rb, a.depth + 1, n);
   T* r = lds_vec<T>(red, 0, lmax);
   T* y = lds_vec<T>(red, 1, lmax);
@@ -460,6 +525,14 @@ __device__ void ph_init(const GArgs<T>& a, const St& st, int wi,
   T* w2 = lds_vec<T>(red, 3, lmax);
   T* z = lds_vec<T>(red, 4, lmax);
   const FBlocks<T> F = stage_F(a, W.w0, W.w1 - 1, lds_F(a, red));
+  if (resident && !st.ir) {
+    T* Ls = lds_L(a, red);
+    if (Ls) {
+      const size_t cnt = (size_t)(W.k1 - W.k0) * n * n;
+      const T* src = a.L + (size_t)W.k0 * n * n;
+      for (size_t e = threadIdx.x; e < cnt; e += NT) Ls[e] = src[e];
+    }
+  }
   for (int e = threadIdx.x; e < len; e += NT)
     y[e] = (T)(ld_sh(st.src + (size_t)W.w0 * n + e) * st.sscale);
   __syncthreads();
@@ -476,7 +549,7 @@ __device__ void ph_init(const GArgs<T>& a, const St& st, int wi,
   }
   __syncthreads();
   put_partial(a, P_NB2, wi, nb, red);
-  u_and_w(a, F, W, 0, false, wi, r, y, w1, w2, z, red);
+  u_and_w(a, F, W, 0, false, wi, r, y, w1, w2, z, (const T*)nullptr, red);
   if (threadIdx.x == 0)
     st_sh(a.part + P_GF * a.nwin + wi, ld_sh(a.part + P_G * a.nwin + wi));
   __syncthreads();
@@ -488,8 +561,8 @@ __device__ void ph_init(const GArgs<T>& a, const St& st, int wi,
 // step i - 1 and are updated. Returns BT_NOT_CONVERGED to go on.
 constexpr int kCapped = 100;  // dec_step: the step cap is reached
 
-template <typename T>
-__device__ int dec_step(const GArgs<T>& a, const St& st, int i, bool capped,
+template <typename T, int NS>
+__device__ int dec_step(const GArgs<T, NS>& a, const St& st, int i, bool capped,
                         double* red, double* gprev, double* aprev, T* al,
                         T* be) {
   const int par = i & 1;
@@ -532,15 +605,15 @@ struct Pre {
   T r[PF], w[PF], s[PF], u[PF], p[PF];
 };
 
-template <typename T>
-__device__ __forceinline__ bool prefetchable(const GArgs<T>& a) {
-  return wlen(a.rb, a.depth + 1, a.n) <= PF * NT;
+template <typename T, int NS>
+__device__ __forceinline__ bool prefetchable(const GArgs<T, NS>& a) {
+  return wlen(a.rb, a.depth + 1, a.nv()) <= PF * NT;
 }
 
-template <typename T>
-__device__ void ph_step_fetch(const GArgs<T>& a, int i, int wi, Pre<T>& f) {
+template <typename T, int NS>
+__device__ void ph_step_fetch(const GArgs<T, NS>& a, int i, int wi, Pre<T>& f) {
   const Win W = window(a.R, a.rb, a.depth + 1, wi);
-  const int n = a.n, len = (W.w1 - W.w0) * n;
+  const int n = a.nv(), len = (W.w1 - W.w0) * n;
   const int cur = i & 1, nxt = cur ^ 1;
 #pragma unroll
   for (int t = 0; t < PF; ++t) {
@@ -562,11 +635,11 @@ __device__ void ph_step_fetch(const GArgs<T>& a, int i, int wi, Pre<T>& f) {
 // Step i: p = u + beta p, xhat += alpha p (own rows); s = w + beta s and
 // r -= alpha s on the window (depth D + 1); u, w of the new r and the
 // partials of step i + 1. ``f``: the window's data fetched ahead, or null.
-template <typename T>
-__device__ void ph_step(const GArgs<T>& a, const St& st, int i, T al, T be,
-                        int wi, const Pre<T>* f, double* red) {
+template <typename T, int NS>
+__device__ void ph_step(const GArgs<T, NS>& a, const St& st, int i, T al, T be,
+                        int wi, const Pre<T>* f, bool resident, double* red) {
   const Win W = window(a.R, a.rb, a.depth + 1, wi);
-  const int n = a.n, len = (W.w1 - W.w0) * n;
+  const int n = a.nv(), len = (W.w1 - W.w0) * n;
   const int lmax = wlen(a.rb, a.depth + 1, n);
   const int cur = i & 1, nxt = cur ^ 1;
   T* r = lds_vec<T>(red, 0, lmax);
@@ -603,18 +676,20 @@ __device__ void ph_step(const GArgs<T>& a, const St& st, int i, T al, T be,
           own && i > 0 ? a.p[g] : T(0));
     }
   }
-  const FBlocks<T> F = stage_F(a, W.w0, W.w1 - 1, lds_F(a, red));
+  const FBlocks<T> F =
+      stage_F(a, W.w0, W.w1 - 1, lds_F(a, red), !resident);
+  const T* Ls = resident && !st.ir ? lds_L(a, red) : nullptr;
   __syncthreads();
-  u_and_w(a, F, W, nxt, !st.ir, wi, r, y, w1, w2, z, red);
+  u_and_w(a, F, W, nxt, !st.ir, wi, r, y, w1, w2, z, Ls, red);
   __syncthreads();
 }
 
 // x = L^{-T} xhat * xscale (add = 0) or x += L^{-T} d * xscale, own rows.
-template <typename T>
-__device__ void ph_x(const GArgs<T>& a, const St& st, int add, int wi,
+template <typename T, int NS>
+__device__ void ph_x(const GArgs<T, NS>& a, const St& st, int add, int wi,
                      double* red) {
   const Win W = window(a.R, a.rb, 0, wi);
-  const int n = a.n;
+  const int n = a.nv();
   T* v = lds_vec<T>(red, 0, wlen(a.rb, a.depth + 1, n));
   for (int e = threadIdx.x; e < (W.k1 - W.k0) * n; e += NT)
     v[e] = a.xh[(size_t)W.k0 * n + e];
@@ -630,10 +705,10 @@ __device__ void ph_x(const GArgs<T>& a, const St& st, int add, int wi,
 }
 
 // r64 = b - A x in float64 from the record, own rows, ||r64||^2 and ||b||^2.
-template <typename T>
-__device__ void ph_res(const GArgs<T>& a, int wi, double* red) {
+template <typename T, int NS>
+__device__ void ph_res(const GArgs<T, NS>& a, int wi, double* red) {
   const Win W = window(a.R, a.rb, 0, wi);
-  const int n = a.n;
+  const int n = a.nv();
   const size_t nn = (size_t)n * n;
   double s2 = 0.0, b2 = 0.0;
   for (int e = threadIdx.x; e < (W.k1 - W.k0) * n; e += NT) {
@@ -664,11 +739,11 @@ __device__ void ph_res(const GArgs<T>& a, int wi, double* red) {
 }
 
 // x = 0 on the window's own rows.
-template <typename T>
-__device__ void ph_zero_x(const GArgs<T>& a, int wi) {
+template <typename T, int NS>
+__device__ void ph_zero_x(const GArgs<T, NS>& a, int wi) {
   const Win W = window(a.R, a.rb, 0, wi);
-  for (int e = threadIdx.x; e < (W.k1 - W.k0) * a.n; e += NT)
-    st_sh(a.x + (size_t)W.k0 * a.n + e, 0.0);
+  for (int e = threadIdx.x; e < (W.k1 - W.k0) * a.nv(); e += NT)
+    st_sh(a.x + (size_t)W.k0 * a.nv() + e, 0.0);
 }
 
 __global__ void k_g_reset(Bar* bar) {
@@ -678,8 +753,8 @@ __global__ void k_g_reset(Bar* bar) {
 
 // The whole solve. Every workgroup runs the same control flow and takes
 // the same decisions; workgroup 0 writes the outcome.
-template <typename T>
-__global__ void __launch_bounds__(NT) k_g_solve(GArgs<T> a) {
+template <typename T, int NS>
+__global__ void __launch_bounds__(NT) k_g_solve(GArgs<T, NS> a) {
   extern __shared__ double red[];
   __shared__ int s_flag;
   Sync sync{a.bar, gridDim.x, 0u, a.spin_limit};
@@ -710,13 +785,14 @@ __global__ void __launch_bounds__(NT) k_g_solve(GArgs<T> a) {
   St st{a.b, 1.0, 1.0, a.tol, 0};
   // one inner PCG solve from the right-hand side in st; returns the steps
   // taken, or -1 when aborted
+  // a workgroup with one window fetches its data before the decision and
+  // keeps the window's blocks in LDS from the init phase on
+  const bool pre = prefetchable(a) && a.nwin <= nwg;
   auto pcg = [&](int cap, int* settled) -> int {
-    each([&](int wi) { ph_init(a, st, wi, red); });
+    each([&](int wi) { ph_init(a, st, wi, pre, red); });
     if (!barrier()) return -1;
     int steps = 0;
     double gprev = 0.0, aprev = 0.0;
-    // a workgroup with one window fetches its data before the decision
-    const bool pre = prefetchable(a) && a.nwin <= nwg;
     for (int i = 0;; ++i) {
       Pre<T> f;
       if (pre && wg < a.nwin) ph_step_fetch(a, i, wg, f);
@@ -727,7 +803,9 @@ __global__ void __launch_bounds__(NT) k_g_solve(GArgs<T> a) {
         break;
       }
       steps = i + 1;
-      each([&](int wi) { ph_step(a, st, i, al, be, wi, pre ? &f : nullptr, red); });
+      each([&](int wi) {
+        ph_step(a, st, i, al, be, wi, pre ? &f : nullptr, pre, red);
+      });
       if (!barrier()) return -1;
     }
     // per step (and at the start): u = M^{-1} r and w = A u
@@ -894,7 +972,7 @@ struct Scratch {
 
 // Workgroups of k_g_solve that fit on the device at once with ``lds`` bytes
 // of LDS each (the grid never exceeds it: the barrier needs them all).
-template <typename T>
+template <typename T, int NS>
 int coresident(size_t lds) {
   int dev = 0, cus = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
@@ -902,9 +980,34 @@ int coresident(size_t lds) {
                             dev) != hipSuccess)
     return 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &per, (const void*)k_g_solve<T>, NT, lds) != hipSuccess)
+          &per, (const void*)k_g_solve<T, NS>, NT, lds) != hipSuccess)
     return 0;
   return cus * per;
+}
+
+// One persistent launch of k_g_solve with the block size fixed at compile
+// time (NS > 0) or read at run time (NS = 0).
+template <typename T, int NS>
+int launch(const GArgsBase<T>& base, size_t lds, hipStream_t s) {
+  GArgs<T, NS> a;
+  static_cast<GArgsBase<T>&>(a) = base;
+  static std::atomic<uint64_t> attr{0};
+  if (lds > 65536 &&
+      lds_limit((const void*)k_g_solve<T, NS>, 160 * 1024, attr) != hipSuccess)
+    return BT_EHIP;
+  const int res = coresident<T, NS>(lds);
+  if (res < 1) return BT_EHIP;
+  const int grid = std::min(a.nwin, res);
+  hipLaunchKernelGGL(k_g_reset, dim3(1), dim3(1), 0, s, a.bar);
+  if (hipGetLastError() != hipSuccess) return BT_EHIP;
+  // a cooperative launch: all workgroups resident at once (the barrier
+  // needs them; its bounded wait turns a violation into BT_ETIMEOUT)
+  void* args[] = {&a};
+  return hipLaunchCooperativeKernel((const void*)k_g_solve<T, NS>, dim3(grid),
+                                    dim3(NT), args, (unsigned)lds, s) ==
+                 hipSuccess
+             ? BT_OK
+             : BT_EHIP;
 }
 
 template <typename T>
@@ -912,7 +1015,7 @@ int run(const bt_handle* h, const double* b, double* x, double tol, int maxit,
         bt_info* info, void* ws, long long spin_limit, hipStream_t s) {
   const int64_t R = h->R;
   const int n = h->n;
-  GArgs<T> a{};
+  GArgsBase<T> a{};
   a.R = (int)R;
   a.n = n;
   a.rb = rows_per_win(R);
@@ -962,23 +1065,13 @@ int run(const bt_handle* h, const double* b, double* x, double tol, int maxit,
                5 * (size_t)wlen(a.rb, a.depth + 1, n) * sizeof(T);
   const size_t fb = fstage_bytes<T>(a.rb, a.depth + 1, n);
   if (fb <= FSTAGE_MAX) lds += fb;
-  static std::atomic<uint64_t> attr{0};
-  if (lds > 65536 &&
-      lds_limit((const void*)k_g_solve<T>, 160 * 1024, attr) != hipSuccess)
-    return BT_EHIP;
-  const int res = coresident<T>(lds);
-  if (res < 1) return BT_EHIP;
-  const int grid = std::min(a.nwin, res);
-  hipLaunchKernelGGL(k_g_reset, dim3(1), dim3(1), 0, s, a.bar);
-  if (hipGetLastError() != hipSuccess) return BT_EHIP;
-  // a cooperative launch: all workgroups resident at once (the barrier
-  // needs them; its bounded wait turns a violation into BT_ETIMEOUT)
-  void* args[] = {&a};
-  return hipLaunchCooperativeKernel((const void*)k_g_solve<T>, dim3(grid),
-                                    dim3(NT), args, (unsigned)lds, s) ==
-                 hipSuccess
-             ? BT_OK
-             : BT_EHIP;
+  if (lstage_fits<T>(a.rb, a.depth + 1, n)) lds += lstage_bytes<T>(a.rb, n);
+  switch (n) {
+    case 6: return launch<T, 6>(a, lds, s);
+    case 12: return launch<T, 12>(a, lds, s);
+    case 24: return launch<T, 24>(a, lds, s);
+    default: return launch<T, 0>(a, lds, s);
+  }
 }
 
 }  // namespace btg
