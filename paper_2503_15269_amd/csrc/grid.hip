@@ -139,15 +139,17 @@ __device__ __forceinline__ void st_sh(V* p, V v) {
 }
 
 // Sums over the workgroup of K values per thread, every thread gets them:
-// a wavefront butterfly (lane 0's result is taken), then the four
-// wavefronts in a fixed order. Deterministic and the same in every
-// workgroup for the same inputs. ``red`` holds at least 4 K doubles.
+// the wavefront sum of the DPP tree, then the four wavefronts in a fixed
+// order. Deterministic and the same in every workgroup for the same inputs.
+// ``red`` holds at least 4 K doubles.
 template <int K>
 __device__ __forceinline__ void wg_sums(double (&v)[K], double* red) {
 #pragma unroll
-  for (int k = 0; k < K; ++k)
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off);
+  for (int k = 0; k < K; ++k) {
+    btk::AccD t;
+    t.s = v[k];
+    v[k] = btk::wave_sum(t).s;
+  }
   const int wv = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
 #pragma unroll
@@ -199,12 +201,16 @@ struct Sync {
       __hip_atomic_fetch_add(&bar->count, 1u, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
       const long long t0 = (long long)wall_clock64();
+      unsigned polls = 0;
       while ((int)(__hip_atomic_load(&bar->count, __ATOMIC_RELAXED,
                                      __HIP_MEMORY_SCOPE_AGENT) -
                    target) < 0) {
-        if (__hip_atomic_load(&bar->abort, __ATOMIC_RELAXED,
-                              __HIP_MEMORY_SCOPE_AGENT) != 0 ||
-            (long long)wall_clock64() - t0 > limit) {
+        // the abort flag and the clock on the first poll and every 16th
+        // (a limit of 0 gives up as soon as the workgroup has to wait)
+        if ((polls++ & 15u) == 0 &&
+            (__hip_atomic_load(&bar->abort, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+             (long long)wall_clock64() - t0 >= limit)) {
           __hip_atomic_store(&bar->abort, 1, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
           ok = 0;
