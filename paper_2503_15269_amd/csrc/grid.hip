@@ -273,6 +273,35 @@ __device__ FBlocks<T> stage_F(const GArgs<T, NS>& a, int b0, int b1, T* lds,
   return FBlocks<T>{lds, b0};
 }
 
+// The blocks of one thread's entry (k, i) of its window, held in registers
+// for a whole inner solve: row i of F_k and column i of F_{k-1} (zeros
+// where the block does not exist). Used when n is fixed at compile time,
+// the workgroup keeps one window and the window has at most one entry per
+// thread (entry o = thread o); otherwise ``on`` is false and C reads the
+// blocks from LDS or memory.
+template <typename T, int NS>
+struct FReg {
+  static constexpr bool kUsed = NS > 0 && NS <= 16;  // registers suffice
+  static constexpr int L = kUsed ? NS : 1;
+  T fp[L];
+  T fm[L];
+  bool on;
+};
+
+// n consecutive entries of a window vector in LDS, as 16-byte reads when
+// every row of the window starts on a 16-byte boundary.
+template <typename T, int NS>
+__device__ __forceinline__ void ld_row(const T* p, T (&v)[FReg<T, NS>::L]) {
+  if constexpr ((NS * sizeof(T)) % 16 == 0) {
+    const T* q = (const T*)__builtin_assume_aligned(p, 16);
+#pragma unroll
+    for (int j = 0; j < NS; ++j) v[j] = q[j];
+  } else {
+#pragma unroll
+    for (int j = 0; j < FReg<T, NS>::L; ++j) v[j] = p[j];
+  }
+}
+
 // C v on rows [lo, hi), v valid on the rows it needs, in the window layout
 // (row k at (k - w0) n): ``ep(o, c)`` receives entry o of the window and its
 // value c = (C v)[o], and stores what the caller needs (C v itself, or a
@@ -280,8 +309,29 @@ __device__ FBlocks<T> stage_F(const GArgs<T, NS>& a, int b0, int b1, T* lds,
 // terms are summed in two chains and then added.
 template <typename T, int NS, typename Ep>
 __device__ __forceinline__ void applyC(const GArgs<T, NS>& a,
-                                       const FBlocks<T>& F, const T* v,
+                                       const FBlocks<T>& F,
+                                       const FReg<T, NS>& fr, const T* v,
                                        int w0, int lo, int hi, Ep&& ep) {
+  if constexpr (FReg<T, NS>::kUsed) {
+    if (fr.on) {
+      const int o = threadIdx.x, k = w0 + o / NS;
+      if (k >= lo && k < hi) {
+        T am = T(0), ap = T(0), x[FReg<T, NS>::L];
+        if (k > 0) {
+          ld_row<T, NS>(v + (k - 1 - w0) * NS, x);
+#pragma unroll
+          for (int j = 0; j < NS; ++j) am += fr.fm[j] * x[j];
+        }
+        if (k < a.R - 1) {
+          ld_row<T, NS>(v + (k + 1 - w0) * NS, x);
+#pragma unroll
+          for (int j = 0; j < NS; ++j) ap += fr.fp[j] * x[j];
+        }
+        ep(o, -(am + ap));
+      }
+      return;
+    }
+  }
   const int n = a.nv();
   const size_t nn = (size_t)n * n;
   const int cnt = (hi - lo) * n;
@@ -315,14 +365,15 @@ __device__ __forceinline__ void shrink(int R, int& lo, int& hi) {
 // y and z run inside the applications of C that produce their operands.
 template <typename T, int NS>
 __device__ void precond(const GArgs<T, NS>& a, const FBlocks<T>& F,
-                        const Win& W, const T* r, T* y, T* w1, T* w2, T* z) {
+                        const FReg<T, NS>& fr, const Win& W, const T* r, T* y,
+                        T* w1, T* w2, T* z) {
   const int n = a.nv(), w0 = W.w0;
   const T av = (T)a.a, om = (T)(1.0 - a.a);
   int lo = W.w0, hi = W.w1;
   const T* cur = r;  // y_{i}, the operand of the next application
   if (a.a != 0.0) {  // y_0 = r + a C r
     shrink(a.R, lo, hi);
-    applyC(a, F, r, w0, lo, hi, [&](int o, T c) {
+    applyC(a, F, fr, r, w0, lo, hi, [&](int o, T c) {
       const T yv = r[o] + av * c;
       y[o] = yv;
       z[o] = yv;
@@ -339,10 +390,10 @@ __device__ void precond(const GArgs<T, NS>& a, const FBlocks<T>& F,
     const T al = (T)a.alpha[m];
     if (a.a != 0.0) {  // y_m = (1 - a) C y + a C (C y)
       shrink(a.R, lo, hi);
-      applyC(a, F, cur, w0, lo, hi, [&](int o, T c) { w1[o] = c; });
+      applyC(a, F, fr, cur, w0, lo, hi, [&](int o, T c) { w1[o] = c; });
       __syncthreads();
       shrink(a.R, lo, hi);
-      applyC(a, F, w1, w0, lo, hi, [&](int o, T c) {
+      applyC(a, F, fr, w1, w0, lo, hi, [&](int o, T c) {
         const T yv = om * w1[o] + av * c;
         y[o] = yv;
         z[o] += al * yv;
@@ -351,7 +402,7 @@ __device__ void precond(const GArgs<T, NS>& a, const FBlocks<T>& F,
     } else {  // y_m = C y_{m-1}, into the buffer the operand is not in
       T* nxt = cur == w2 ? y : w2;
       shrink(a.R, lo, hi);
-      applyC(a, F, cur, w0, lo, hi, [&](int o, T c) {
+      applyC(a, F, fr, cur, w0, lo, hi, [&](int o, T c) {
         nxt[o] = c;
         z[o] += al * c;
       });
@@ -465,8 +516,9 @@ __device__ __forceinline__ T lower_row(const T* row, const T* v, int n,
 // ``Ls``: the own rows' factors L_k staged in LDS, or null (read from L).
 template <typename T, int NS>
 __device__ void u_and_w(const GArgs<T, NS>& a, const FBlocks<T>& F,
-                        const Win& W, int par, bool nrm, int wi, T* r, T* y,
-                        T* w1, T* w2, T* z, const T* Ls, double* red) {
+                        const FReg<T, NS>& fr, const Win& W, int par, bool nrm,
+                        int wi, T* r, T* y, T* w1, T* w2, T* z, const T* Ls,
+                        double* red) {
   const int n = a.nv(), w0 = W.w0;
   if (a.pc == BT_PC_NONE) {  // u = L^T L r, row-local, on own rows +- 1
     const int lo = max(W.k0 - 1, 0), hi = min(W.k1 + 1, a.R);
@@ -481,14 +533,14 @@ __device__ void u_and_w(const GArgs<T, NS>& a, const FBlocks<T>& F,
     }
     __syncthreads();
   } else {
-    precond(a, F, W, r, y, w1, w2, z);
+    precond(a, F, fr, W, r, y, w1, w2, z);
   }
   typename AccOf<T>::type g, d, t2;
   g.zero();
   d.zero();
   t2.zero();
   // C u on own rows, w = u - C u, and the partials at each entry
-  applyC(a, F, z, w0, W.k0, W.k1, [&](int o, T c) {
+  applyC(a, F, fr, z, w0, W.k0, W.k1, [&](int o, T c) {
     const int e = o - (W.k0 - w0) * n;
     const size_t gi = (size_t)W.k0 * n + e;
     const T zv = z[o], wv = zv - c;
@@ -521,7 +573,7 @@ __device__ void u_and_w(const GArgs<T, NS>& a, const FBlocks<T>& F,
 // stopping norm) serve every step.
 template <typename T, int NS>
 __device__ void ph_init(const GArgs<T, NS>& a, const St& st, int wi,
-                        bool resident, double* red) {
+                        bool resident, FReg<T, NS>& fr, double* red) {
   const Win W = window(a.R, a.rb, a.depth + 1, wi);
   const int n = a.nv(), len = (W.w1 - W.w0) * n;
   const int lmax = wlen(a.rb, a.depth + 1, n);
@@ -531,6 +583,20 @@ __device__ void ph_init(const GArgs<T, NS>& a, const St& st, int wi,
   T* w2 = lds_vec<T>(red, 3, lmax);
   T* z = lds_vec<T>(red, 4, lmax);
   const FBlocks<T> F = stage_F(a, W.w0, W.w1 - 1, lds_F(a, red));
+  fr.on = false;
+  if constexpr (FReg<T, NS>::kUsed) {
+    if (resident && len <= NT) {  // this thread's blocks into registers
+      fr.on = true;
+      const int o = threadIdx.x, k = W.w0 + o / NS, i = o % NS;
+      const size_t nn = (size_t)NS * NS;
+      const bool in = o < len;
+#pragma unroll
+      for (int j = 0; j < NS; ++j) {
+        fr.fp[j] = in && k < a.R - 1 ? F.blk(k, nn)[i * NS + j] : T(0);
+        fr.fm[j] = in && k > 0 ? F.blk(k - 1, nn)[j * NS + i] : T(0);
+      }
+    }
+  }
   if (resident && !st.ir) {
     T* Ls = lds_L(a, red);
     if (Ls) {
@@ -555,7 +621,7 @@ __device__ void ph_init(const GArgs<T, NS>& a, const St& st, int wi,
   }
   __syncthreads();
   put_partial(a, P_NB2, wi, nb, red);
-  u_and_w(a, F, W, 0, false, wi, r, y, w1, w2, z, (const T*)nullptr, red);
+  u_and_w(a, F, fr, W, 0, false, wi, r, y, w1, w2, z, (const T*)nullptr, red);
   if (threadIdx.x == 0)
     st_sh(a.part + P_GF * a.nwin + wi, ld_sh(a.part + P_G * a.nwin + wi));
   __syncthreads();
@@ -643,7 +709,8 @@ __device__ void ph_step_fetch(const GArgs<T, NS>& a, int i, int wi, Pre<T>& f) {
 // partials of step i + 1. ``f``: the window's data fetched ahead, or null.
 template <typename T, int NS>
 __device__ void ph_step(const GArgs<T, NS>& a, const St& st, int i, T al, T be,
-                        int wi, const Pre<T>* f, bool resident, double* red) {
+                        int wi, const Pre<T>* f, bool resident,
+                        const FReg<T, NS>& fr, double* red) {
   const Win W = window(a.R, a.rb, a.depth + 1, wi);
   const int n = a.nv(), len = (W.w1 - W.w0) * n;
   const int lmax = wlen(a.rb, a.depth + 1, n);
@@ -686,7 +753,7 @@ __device__ void ph_step(const GArgs<T, NS>& a, const St& st, int i, T al, T be,
       stage_F(a, W.w0, W.w1 - 1, lds_F(a, red), !resident);
   const T* Ls = resident && !st.ir ? lds_L(a, red) : nullptr;
   __syncthreads();
-  u_and_w(a, F, W, nxt, !st.ir, wi, r, y, w1, w2, z, Ls, red);
+  u_and_w(a, F, fr, W, nxt, !st.ir, wi, r, y, w1, w2, z, Ls, red);
   __syncthreads();
 }
 
@@ -761,7 +828,7 @@ __global__ void k_g_reset(Bar* bar) {
 // the same decisions; workgroup 0 writes the outcome.
 template <typename T, int NS>
 __global__ void __launch_bounds__(NT) k_g_solve(GArgs<T, NS> a) {
-  extern __shared__ double red[];
+  extern __shared__ __align__(16) double red[];
   __shared__ int s_flag;
   Sync sync{a.bar, gridDim.x, 0u, a.spin_limit};
   const int wg = blockIdx.x, nwg = gridDim.x;
@@ -794,8 +861,10 @@ __global__ void __launch_bounds__(NT) k_g_solve(GArgs<T, NS> a) {
   // a workgroup with one window fetches its data before the decision and
   // keeps the window's blocks in LDS from the init phase on
   const bool pre = prefetchable(a) && a.nwin <= nwg;
+  FReg<T, NS> fr;
+  fr.on = false;
   auto pcg = [&](int cap, int* settled) -> int {
-    each([&](int wi) { ph_init(a, st, wi, pre, red); });
+    each([&](int wi) { ph_init(a, st, wi, pre, fr, red); });
     if (!barrier()) return -1;
     int steps = 0;
     double gprev = 0.0, aprev = 0.0;
@@ -810,7 +879,7 @@ __global__ void __launch_bounds__(NT) k_g_solve(GArgs<T, NS> a) {
       }
       steps = i + 1;
       each([&](int wi) {
-        ph_step(a, st, i, al, be, wi, pre ? &f : nullptr, pre, red);
+        ph_step(a, st, i, al, be, wi, pre ? &f : nullptr, pre, fr, red);
       });
       if (!barrier()) return -1;
     }
