@@ -71,8 +71,8 @@ extern "C" {
 
 /* Arithmetic of the iteration. */
 #define BT_F64 0     /* float64 throughout */
-#define BT_F32 1     /* float32 iteration, float32 accumulation with
-                        compensated dot products; no refinement */
+#define BT_F32 1     /* float32 iteration (dot products of float32
+                        vectors summed in float64); no refinement */
 #define BT_F32_IR 2  /* float32 inner PCG inside a float64 iterative
                         refinement on the system of record */
 #define BT_BF16X2_IR 3 /* as BT_F32_IR; in addition the off-diagonal blocks are

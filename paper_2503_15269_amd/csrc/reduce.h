@@ -6,10 +6,11 @@
 // wave obtains the bitwise-same total. Across waves the per-wave totals go
 // through LDS and are added in wave order. The result is deterministic.
 //
-// Float32 sums use compensated arithmetic (Ogita, Rump and Oishi, "Accurate
-// sum and dot product", SIAM J. Sci. Comput. 26(6), 2005, algorithm Dot2):
-// each product is split exactly with an FMA (TwoProduct), each addition with
-// Knuth's TwoSum, and the error terms are accumulated in float32.
+// Dot products of float32 vectors sum the products in float64: the product
+// of two float32 values is exact there, so only the float64 additions
+// round, which is more accurate than a compensated float32 sum (Ogita, Rump
+// and Oishi's Dot2, twice the float32 precision) and takes fewer
+// instructions per term.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -74,59 +75,35 @@ struct AccD {
   }
 };
 
-// ----------------------------------------------------- compensated float
-#pragma clang fp contract(off)
-__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
-  s = a + b;
-  float z = s - a;
-  e = (a - (s - z)) + (b - z);
-}
-
-struct AccF {
-  float s, c;
-  __device__ __forceinline__ void zero() { s = 0.f; c = 0.f; }
-  __device__ __forceinline__ void add(float v) {
-    float t, e;
-    two_sum(s, v, t, e);
-    s = t;
-    c += e;
-  }
+// ---------------------------------------- float products, float64 sums
+// The product of two float32 values is exact in float64 (24 + 24 significant
+// bits), so each term enters the sum unrounded: two conversions and a float64
+// FMA per term, one float64 addition per merge.
+struct AccX {
+  double s;
+  __device__ __forceinline__ void zero() { s = 0.0; }
+  __device__ __forceinline__ void add(float v) { s += (double)v; }
   __device__ __forceinline__ void add_prod(float x, float y) {
-    float p = x * y;
-    float ep = __fmaf_rn(x, y, -p);  // exact: x*y = p + ep
-    float t, es;
-    two_sum(s, p, t, es);
-    s = t;
-    c += ep + es;
+    s = __fma_rn((double)x, (double)y, s);
   }
-  __device__ __forceinline__ void merge(const AccF& o) {
-    float t, e;
-    two_sum(s, o.s, t, e);
-    s = t;
-    c += o.c + e;
-  }
-  __device__ __forceinline__ double value() const {
-    return (double)s + (double)c;
-  }
+  __device__ __forceinline__ void merge(const AccX& o) { s += o.s; }
+  __device__ __forceinline__ double value() const { return s; }
   template <int CTRL>
-  __device__ __forceinline__ AccF moved() const {
-    AccF r;
+  __device__ __forceinline__ AccX moved() const {
+    AccX r;
     r.s = dpp<CTRL>(s);
-    r.c = dpp<CTRL>(c);
     return r;
   }
-  __device__ __forceinline__ AccF lane(int l) const {
-    AccF r;
+  __device__ __forceinline__ AccX lane(int l) const {
+    AccX r;
     r.s = readlane(s, l);
-    r.c = readlane(c, l);
     return r;
   }
 };
-#pragma clang fp contract(on)
 
 template <typename T> struct AccOf;
 template <> struct AccOf<double> { using type = AccD; };
-template <> struct AccOf<float> { using type = AccF; };
+template <> struct AccOf<float> { using type = AccX; };
 
 // Sum over the 16 lanes of each DPP row; every lane of a row returns it.
 template <typename A>

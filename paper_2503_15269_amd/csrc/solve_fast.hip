@@ -44,7 +44,7 @@
 namespace btf {
 
 using btk::AccD;
-using btk::AccF;
+using btk::AccX;
 
 constexpr int SL = 4;      // reduction slots (reuse distance)
 constexpr int MAXI = 64;   // systems per bin, upper bound
@@ -116,7 +116,7 @@ struct Smem {
   float T[2][G::RPB * G::ROW];  // transposed sums for row k+1
   float Z[G::ROW];              // zeros: the "previous row" of a first row
   double xs[G::RPB * NB];       // float64 iterate of the bin
-  AccF redF[SL][MAXW];
+  AccX redF[SL][MAXW];
   double redD[SL][MAXW];
   int active;   // running count of (wavefront, flag) events, never reset
   int bin;
@@ -377,8 +377,8 @@ struct Ctx {
   }
 
   // ---- reductions --------------------------------------------------------
-  __device__ __forceinline__ void put_wave(const AccF& acc) {
-    const AccF t = btk::wave_sum(acc);
+  __device__ __forceinline__ void put_wave(const AccX& acc) {
+    const AccX t = btk::wave_sum(acc);
     if ((threadIdx.x & 63) == 0) sm.redF[sf][wave] = t;
   }
   // Sum of the system's wavefront partials: lane l of every wavefront reads
@@ -386,7 +386,7 @@ struct Ctx {
   // reduction adds the 16 and lane 0 broadcasts. Fixed tree: deterministic.
   __device__ __forceinline__ double take() {  // after the barrier
     const int l = threadIdx.x & (MAXW - 1);
-    AccF v;
+    AccX v;
     if (l >= w0 && l < w1) v = sm.redF[sf][l];
     else v.zero();
     v = btk::row16_sum(v);
@@ -401,7 +401,7 @@ struct Ctx {
   __device__ __forceinline__ double dot(const float (&x)[EPT],
                                         const float (&y)[EPT], bool on = true) {
     if (on) {
-      AccF acc;
+      AccX acc;
       acc.zero();
 #pragma unroll
       for (int e = 0; e < EPT; ++e) acc.add_prod(x[e], y[e]);
@@ -774,7 +774,7 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
         // a system that has stopped keeps taking the barriers (with its
         // bin) but no longer does arithmetic
         if (act) {
-          AccF acc;
+          AccX acc;
           acc.zero();
 #pragma unroll
           for (int e = 0; e < EPT; ++e) acc.add_prod(r[e], z[e]);

@@ -90,7 +90,7 @@ def test_single_n12_f32_refinement():
 
 
 def test_single_n12_f32_plain():
-    """Pure float32 PCG (compensated dot products, no refinement) on the
+    """Pure float32 PCG (float64 sums in the dot products, no refinement) on the
     N = 512, n = 12 system (kappa ~ 1.7e4): run until the float32 iteration
     stagnates (recursive residual 1e-8) and meet the float32 bar of 1e-5
     against the float64 direct solve, globally and per block row."""
