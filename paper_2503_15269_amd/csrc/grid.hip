@@ -469,9 +469,20 @@ __device__ __forceinline__ T* lds_F(const GArgs<T, NS>& a, double* red) {
              : nullptr;
 }
 
+// LDS of a workgroup: the reduction scratch, the five window vectors and,
+// when they fit, the staged blocks F.
+template <typename T>
+__host__ __device__ __forceinline__ size_t lds_base_bytes(int rb, int depth,
+                                                          int n) {
+  const size_t fb = fstage_bytes<T>(rb, depth, n);
+  return NT * sizeof(double) + 5 * (size_t)wlen(rb, depth, n) * sizeof(T) +
+         (fb <= FSTAGE_MAX ? fb : 0);
+}
+
 // The factors L_k of a window's own rows, for the stopping norm ||L r||,
-// staged after the blocks F when both fit.
-constexpr size_t LSTAGE_MAX = 32 * 1024;
+// staged after the blocks F when both fit and the workgroup's LDS stays
+// within 64 KB (two workgroups per CU).
+constexpr size_t LDS_WITH_L_MAX = 64 * 1024;
 template <typename T>
 __host__ __device__ __forceinline__ size_t lstage_bytes(int rb, int n) {
   return (size_t)rb * n * n * sizeof(T);
@@ -480,7 +491,8 @@ template <typename T>
 __host__ __device__ __forceinline__ bool lstage_fits(int rb, int depth,
                                                      int n) {
   return fstage_bytes<T>(rb, depth, n) <= FSTAGE_MAX &&
-         lstage_bytes<T>(rb, n) <= LSTAGE_MAX;
+         lds_base_bytes<T>(rb, depth, n) + lstage_bytes<T>(rb, n) <=
+             LDS_WITH_L_MAX;
 }
 template <typename T, int NS>
 __device__ __forceinline__ T* lds_L(const GArgs<T, NS>& a, double* red) {
@@ -1066,10 +1078,18 @@ template <typename T, int NS>
 int launch(const GArgsBase<T>& base, size_t lds, hipStream_t s) {
   GArgs<T, NS> a;
   static_cast<GArgsBase<T>&>(a) = base;
-  static std::atomic<uint64_t> attr{0};
-  if (lds > 65536 &&
-      lds_limit((const void*)k_g_solve<T, NS>, 160 * 1024, attr) != hipSuccess)
-    return BT_EHIP;
+  // dynamic LDS beyond 64 KB needs the kernel's limit raised, to what the
+  // 160 KB of a workgroup leave beside the kernel's static LDS
+  if (lds > 65536) {
+    hipFuncAttributes fa{};
+    if (hipFuncGetAttributes(&fa, (const void*)k_g_solve<T, NS>) != hipSuccess)
+      return BT_EHIP;
+    const size_t cap = 160 * 1024 - fa.sharedSizeBytes;
+    if (lds > cap) return BT_EINVAL;
+    static std::atomic<uint64_t> attr{0};
+    if (lds_limit((const void*)k_g_solve<T, NS>, cap, attr) != hipSuccess)
+      return BT_EHIP;
+  }
   const int res = coresident<T, NS>(lds);
   if (res < 1) return BT_EHIP;
   const int grid = std::min(a.nwin, res);
@@ -1136,10 +1156,7 @@ int run(const bt_handle* h, const double* b, double* x, double tol, int maxit,
   a.r64 = (double*)((unsigned char*)ws + sl.r64);
   a.part = (double*)((unsigned char*)ws + sl.part);
   a.bar = (Bar*)((unsigned char*)ws + sl.bar);
-  size_t lds = NT * sizeof(double) +
-               5 * (size_t)wlen(a.rb, a.depth + 1, n) * sizeof(T);
-  const size_t fb = fstage_bytes<T>(a.rb, a.depth + 1, n);
-  if (fb <= FSTAGE_MAX) lds += fb;
+  size_t lds = lds_base_bytes<T>(a.rb, a.depth + 1, n);
   if (lstage_fits<T>(a.rb, a.depth + 1, n)) lds += lstage_bytes<T>(a.rb, n);
   switch (n) {
     case 6: return launch<T, 6>(a, lds, s);

@@ -50,7 +50,7 @@ VARIANTS = {
 }
 
 # (N, n): one workgroup, several with a ragged last one, many
-SHAPES = [(7, 6), (45, 12), (130, 5), (300, 12)]
+SHAPES = [(7, 6), (45, 12), (130, 5), (300, 12), (60, 24)]
 
 
 @pytest.mark.parametrize("N,n", SHAPES)
@@ -246,6 +246,23 @@ def test_grid_more_windows_than_resident_workgroups(N, n):
     if N * n <= 4000:
         xr, ri = orc.pcg(d["D"], d["O"], d["b"], tol=1e-10, **oracle_kind(P))
         assert iteration_match(int(info[0]["iters"]), ri), (info, ri)
+
+
+def test_grid_deep_window_above_64kb_of_lds():
+    """n = 48 at m = 7 (a = 1): a window carries 14 halo rows on each side,
+    so a workgroup needs more than 64 KB of LDS and the launch raises the
+    kernel's limit (within the 160 KB a workgroup has beside the kernel's
+    static LDS); the true residual and the error against the direct solve."""
+    N, n, m = 600, 48, 7
+    rb = max(4, min(16, N // 64))
+    depth = 1 + 2 * (m - 1) + 1
+    assert 256 * 8 + 5 * (rb + 2 * depth) * n * 8 > 64 * 1024
+    d = lqrgen.lqr_instance(N, n, 16, 41, 0, s=0.05)
+    x, info, _ = grid_solve(d["D"], d["O"], d["b"], bt.Params(a=1.0, m=m))
+    assert info[0]["status"] == bt.OK, info
+    assert true_relres(d["D"], d["O"], d["b"], x) <= F64_TRUE_RES
+    assert_close(x, orc.btchol_solve(d["D"], d["O"], d["b"]), 1e-7,
+                 "against the direct solve")
 
 
 def test_grid_barrier_gives_up_and_the_handle_recovers():
