@@ -43,6 +43,8 @@ namespace btm {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int WG = 256;       // 4 wavefronts, 16 right-hand sides each
 // A block in LDS: row r holds its NB / 4 groups of four columns as 16-byte
@@ -143,6 +145,29 @@ __device__ __forceinline__ f32x4 mma16(const unsigned short* A, int e,
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc, 0, 0, 0);
 }
 
+// The same for one K step of 32 (v_mfma_f32_16x16x32_bf16, twice the K of
+// one instruction above): the instruction pairs the 8 entries of A's lane
+// group g with the 8 entries of B's lane group g (measured on gfx950 with
+// integer operands), so items 0..3 may carry K rows 4g.. of one 16-row tile
+// and items 4..7 those of the next. The panel's tiles ks and ks + 1 then form
+// the B operand as they are, and the A operand is the two 16-byte chunks of
+// the block row at ``e0`` and ``e1`` (16 columns apart).
+__device__ __forceinline__ f32x4 mma32(const unsigned short* A, int e0, int e1,
+                                       bf16x4 bh0, bf16x4 bl0, bf16x4 bh1,
+                                       bf16x4 bl1, f32x4 acc) {
+  const uint4 c0 = *reinterpret_cast<const uint4*>(A + e0);
+  const uint4 c1 = *reinterpret_cast<const uint4*>(A + e1);
+  const bf16x8 ah = __builtin_bit_cast(bf16x8, make_uint4(c0.x, c0.y, c1.x, c1.y));
+  const bf16x8 al = __builtin_bit_cast(bf16x8, make_uint4(c0.z, c0.w, c1.z, c1.w));
+  const bf16x8 bh = __builtin_bit_cast(
+      bf16x8, (s16x8)__builtin_shufflevector(bh0, bh1, 0, 1, 2, 3, 4, 5, 6, 7));
+  const bf16x8 bl = __builtin_bit_cast(
+      bf16x8, (s16x8)__builtin_shufflevector(bl0, bl1, 0, 1, 2, 3, 4, 5, 6, 7));
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, acc, 0, 0, 0);
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, acc, 0, 0, 0);
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, acc, 0, 0, 0);
+}
+
 template <int NB, bool HM, bool HP>
 __device__ __forceinline__ void cprod_t(const unsigned short* Am,
                                         const Spl<NB>& Vm,
@@ -153,14 +178,24 @@ __device__ __forceinline__ void cprod_t(const unsigned short* Am,
   const int kq = 4 * (l >> 4);  // first K row of this lane in a K step
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) acc[mt] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // K steps of 32 over pairs of tiles, one of 16 for an odd last tile
 #pragma unroll
-  for (int ks = 0; ks < MT; ++ks) {
+  for (int ks = 0; ks < MT; ks += 2) {
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
       // chunk of columns 16 ks + kq .. + 3 of row 16 mt + l mod 16
       const int e = (16 * mt + (l & 15)) * RS + 2 * (16 * ks + kq);
-      if constexpr (HP) acc[mt] = mma16(Ap, e, Vp.h[ks], Vp.lo[ks], acc[mt]);
-      if constexpr (HM) acc[mt] = mma16(Am, e, Vm.h[ks], Vm.lo[ks], acc[mt]);
+      if (ks + 1 < MT) {
+        if constexpr (HP)
+          acc[mt] = mma32(Ap, e, e + 32, Vp.h[ks], Vp.lo[ks], Vp.h[ks + 1],
+                          Vp.lo[ks + 1], acc[mt]);
+        if constexpr (HM)
+          acc[mt] = mma32(Am, e, e + 32, Vm.h[ks], Vm.lo[ks], Vm.h[ks + 1],
+                          Vm.lo[ks + 1], acc[mt]);
+      } else {
+        if constexpr (HP) acc[mt] = mma16(Ap, e, Vp.h[ks], Vp.lo[ks], acc[mt]);
+        if constexpr (HM) acc[mt] = mma16(Am, e, Vm.h[ks], Vm.lo[ks], acc[mt]);
+      }
     }
   }
 }
