@@ -54,6 +54,13 @@ def test_mrhs_n48_small(m):
     check(D, O, B, X, info)
 
 
+def test_mrhs_n64():
+    """n = 64: every product takes two K steps of 32 (the 32-deep bfloat16
+    form over pairs of panel tiles)."""
+    D, O, B, X, info = run_mrhs(20, 64, 21, 64, seed=9)
+    check(D, O, B, X, info)
+
+
 def test_mrhs_n16_two_column_blocks():
     D, O, B, X, info = run_mrhs(33, 16, 5, 128, seed=6, s=0.1)
     check(D, O, B, X, info)
