@@ -390,20 +390,27 @@ constexpr size_t factor_lds_packed() {
 // instance has none): both ranges go to LDS with coalesced 16-byte loads,
 // the lanes of a row then read the same LDS words (broadcast), and the F
 // blocks return through LDS for coalesced stores.
-template <int NB, typename T>
+// Per wavefront the LDS holds RPW + 1 slots of LB entries (full blocks, or
+// the packed lower triangles with PK) and RPW full blocks (O, then F).
+// With PK two wavefronts per workgroup keep a workgroup small enough that
+// five fit on a CU (ten wavefronts).
+template <int NB, typename T, bool PK>
 struct OffdiagGeo {
   static constexpr int TPR = NB / 3;
   static constexpr int RPW = 64 / TPR;
   static constexpr int NN = NB * NB;
-  static constexpr int WPB = (2 * RPW + 1) * NN * sizeof(T) > 40000 ? 1
-                             : (2 * RPW + 1) * NN * sizeof(T) > 20000 ? 2 : 4;
-  static constexpr size_t LDS = (size_t)WPB * (2 * RPW + 1) * NN * sizeof(T);
+  static constexpr int LB = PK ? li_packed_len(NB) : NN;
+  static constexpr int PW = (RPW + 1) * LB + RPW * NN;  // entries per wave
+  static constexpr int WPB = PK ? 2
+                             : PW * sizeof(T) > 40000 ? 1
+                             : PW * sizeof(T) > 20000 ? 2 : 4;
+  static constexpr size_t LDS = (size_t)WPB * PW * sizeof(T);
 };
 
 template <int NB, typename T, typename Rec, bool PK>
-__global__ void __launch_bounds__((64 * OffdiagGeo<NB, T>::WPB))
+__global__ void __launch_bounds__((64 * OffdiagGeo<NB, T, PK>::WPB))
     k_offdiag_rows(SetupArgs a) {
-  using G = OffdiagGeo<NB, T>;
+  using G = OffdiagGeo<NB, T, PK>;
   constexpr int NN = G::NN, RPW = G::RPW, TPR = G::TPR;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -411,8 +418,8 @@ __global__ void __launch_bounds__((64 * OffdiagGeo<NB, T>::WPB))
     const int64_t wg0 = (int64_t)blockIdx.x * G::WPB * RPW;
     if (!rows_needed(a, wg0, wg0 + G::WPB * RPW)) return;
   }
-  T* Ls = reinterpret_cast<T*>(smem_raw) + (size_t)w * (2 * RPW + 1) * NN;
-  T* Os = Ls + (size_t)(RPW + 1) * NN;
+  T* Ls = reinterpret_cast<T*>(smem_raw) + (size_t)w * G::PW;
+  T* Os = Ls + (size_t)(RPW + 1) * G::LB;
   const int64_t g0 = ((int64_t)blockIdx.x * G::WPB + w) * RPW;
   const int r = l / TPR, q = l % TPR;
   const int64_t g = g0 + r;
@@ -558,7 +565,7 @@ __global__ void __launch_bounds__((64 * OffdiagGeo<NB, T>::WPB))
 
 template <int NB, typename T, typename Rec, bool PK>
 hipError_t launch_offdiag_pk(const SetupArgs& a, hipStream_t s) {
-  using G = OffdiagGeo<NB, T>;
+  using G = OffdiagGeo<NB, T, PK>;
   static std::atomic<uint64_t> attr{0};
   hipError_t e =
       lds_limit((const void*)k_offdiag_rows<NB, T, Rec, PK>, G::LDS, attr);
