@@ -712,8 +712,10 @@ __global__ void __launch_bounds__(NB * 4) k_direct_mfma(DirectArgs a) {
   constexpr int PF = (NN + NT - 1) / NT;  // prefetched entries per thread
   extern __shared__ __align__(16) unsigned char smem_raw[];
   M& sm = *reinterpret_cast<M*>(smem_raw);
-  const int t = threadIdx.x, w = t >> 6, l = t & 63;
-  const int li = l & 15, lk = l >> 4;
+  // the wavefront index, uniform across the wavefront (the diagonal block's
+  // DPP code runs under a test of it)
+  const int t = threadIdx.x, w = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int l = t & 63, li = l & 15, lk = l >> 4;
   const int sys = a.order[blockIdx.x];
   const int64_t r0 = a.off[sys];
   const int N = (int)(a.off[sys + 1] - r0);
@@ -901,11 +903,11 @@ hipError_t launch_nb(const DirectArgs& a, hipStream_t s) {
     return hipGetLastError();
   } else if constexpr (NB % 16 == 0) {
     constexpr size_t lds = sizeof(MfLds<NB>);
-    const void* fn = a.dtype == BT_DT_F64
-                         ? (const void*)k_direct_mfma<NB, double>
-                         : (const void*)k_direct_mfma<NB, float>;
-    const hipError_t e = hipFuncSetAttribute(
-        fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    static std::atomic<uint64_t> attr_d{0}, attr_f{0};
+    const hipError_t e =
+        a.dtype == BT_DT_F64
+            ? lds_limit((const void*)k_direct_mfma<NB, double>, lds, attr_d)
+            : lds_limit((const void*)k_direct_mfma<NB, float>, lds, attr_f);
     if (e != hipSuccess) return e;
     if (a.dtype == BT_DT_F64)
       hipLaunchKernelGGL((k_direct_mfma<NB, double>), dim3(a.B), dim3(NB * 4),
