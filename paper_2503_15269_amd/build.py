@@ -29,6 +29,16 @@ FLAGS = [
 ]
 
 
+# Per-source flags. The register-resident batch kernel runs at two
+# wavefronts per SIMD and is bound by instruction issue and latency; LLVM's
+# iterative ILP scheduling strategy orders its inner loop better than the
+# default (batch solve 0.94 -> 0.91 ms on gfx950, same arithmetic). It also
+# shortens the direct solver's dependent chains a little (n = 48: 3 %); the
+# other sources gain nothing from it.
+_ILP = ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"]
+SOURCE_FLAGS = {"solve_fast.hip": _ILP, "direct.hip": _ILP}
+
+
 def _hipcc():
     for c in ("/opt/rocm/bin/hipcc", "hipcc"):
         if os.path.isabs(c) and os.path.exists(c):
@@ -39,7 +49,7 @@ def _hipcc():
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     cmd = [_hipcc(), "-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
-    cmd += FLAGS
+    cmd += FLAGS + SOURCE_FLAGS.get(os.path.basename(src), [])
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
