@@ -64,9 +64,12 @@ def parse():
     return ap.parse_args()
 
 
+# what the solve kernel's machine code is built from (its sources and the
+# build flags)
 KERNEL_SOURCES = ("paper_2503_15269_amd/csrc/solve_fast.hip",
                   "paper_2503_15269_amd/csrc/reduce.h",
-                  "paper_2503_15269_amd/csrc/internal.h")
+                  "paper_2503_15269_amd/csrc/internal.h",
+                  "paper_2503_15269_amd/build.py")
 TRAFFIC_FILE = "profiles/traffic_k_fast_ir_batch_ragged_n12.md"
 
 
