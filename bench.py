@@ -67,6 +67,7 @@ def parse():
 # what the solve kernel's machine code is built from (its sources and the
 # build flags)
 KERNEL_SOURCES = ("paper_2503_15269_amd/csrc/solve_fast.hip",
+                  "paper_2503_15269_amd/csrc/solve_fast.h",
                   "paper_2503_15269_amd/csrc/reduce.h",
                   "paper_2503_15269_amd/csrc/internal.h",
                   "paper_2503_15269_amd/build.py")

@@ -17,8 +17,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libbtpcg.so")
 ARCH = os.environ.get("BTPCG_ARCH", "gfx950")
 
-SOURCES = ["api.cpp", "setup.hip", "solve.hip", "solve_fast.hip", "mrhs.hip",
-           "direct.hip", "grid.hip"]
+SOURCES = ["api.cpp", "setup.hip", "solve.hip", "solve_fast.hip",
+           "solve_fast24.hip", "mrhs.hip", "direct.hip", "grid.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
@@ -31,8 +31,10 @@ FLAGS = [
 
 # Per-source flags. The register-resident batch kernel runs at two
 # wavefronts per SIMD and is bound by instruction issue and latency; LLVM's
-# iterative ILP scheduling strategy orders its inner loop better than the
-# default (batch solve 0.94 -> 0.91 ms on gfx950, same arithmetic). It also
+# iterative ILP scheduling strategy orders the inner loop of its n = 12
+# variants better than the default (batch solve 0.94 -> 0.91 ms on gfx950,
+# same arithmetic) but that of the n = 24 variant worse (0.64 -> 0.83 ms),
+# which is therefore built in solve_fast24.hip with the default. It also
 # shortens the direct solver's dependent chains a little (n = 48: 3 %); the
 # other sources gain nothing from it.
 _ILP = ["-mllvm", "-amdgpu-sched-strategy=iterative-ilp"]

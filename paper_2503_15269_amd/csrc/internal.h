@@ -172,6 +172,9 @@ int bt_fast_max_systems_per_bin();
 hipError_t bt_launch_fast(const SolveArgs& a, int variant, int grid,
                           hipStream_t s);
 int bt_fast_max_grid(int n, int variant);
+// the n = 24 variant (solve_fast24.hip)
+hipError_t bt_launch_fast24(const SolveArgs& a, int grid, hipStream_t s);
+int bt_fast_max_grid24();
 hipError_t bt_launch_setup_init(int B, int32_t* fail, int32_t* ctr,
                                 hipStream_t s);
 size_t bt_mrhs_scratch_bytes(int64_t R, int n, int nrhs);
