@@ -639,8 +639,9 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
         for (int x = 0; x < NB; ++x) P[x] = 0.0;
         if (need && c.row_ok) {
           // rows e0 .. e0 + EPT - 1 of D_k and O_k, 16-byte loads, in
-          // batches of RB rows issued before their sums
-          constexpr int RB = sizeof(Rec) == 4 ? 3 : 1;
+          // batches of RB rows issued before their sums (one row at a time
+          // for n = 24: three rows of 24 spill; 286 -> 92 spilled VGPRs)
+          constexpr int RB = sizeof(Rec) == 4 && NB <= 12 ? 3 : 1;
           static_assert(EPT % RB == 0, "whole batches");
           const double* xn = sm.xs + (c.lrow + 1) * NB;
 #pragma unroll
