@@ -639,9 +639,13 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
         for (int x = 0; x < NB; ++x) P[x] = 0.0;
         if (need && c.row_ok) {
           // rows e0 .. e0 + EPT - 1 of D_k and O_k, 16-byte loads, in
-          // batches of RB rows issued before their sums (one row at a time
-          // for n = 24: three rows of 24 spill; 286 -> 92 spilled VGPRs)
-          constexpr int RB = sizeof(Rec) == 4 && NB <= 12 ? 3 : 1;
+          // batches of RB rows issued before their sums: enough loads in
+          // flight without spilling next to the F registers (n = 12, EPT = 6:
+          // two rows, 43 -> 36 spilled VGPRs and 2.5 % faster than three;
+          // n = 24: one row, 286 -> 92 spilled VGPRs)
+          constexpr int RB = sizeof(Rec) != 4 || NB > 12 ? 1
+                             : EPT % 2 == 0             ? 2
+                                                        : 3;
           static_assert(EPT % RB == 0, "whole batches");
           const double* xn = sm.xs + (c.lrow + 1) * NB;
 #pragma unroll
