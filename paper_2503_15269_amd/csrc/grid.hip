@@ -30,6 +30,13 @@
 // one more: the workgroup forms r - alpha s on its window's rows plus D + 1
 // on each side in LDS and applies C there on windows that shrink by one row
 // per application, so u and w of its own rows need no further exchange.
+// When a workgroup keeps one window for the whole solve, the window's blocks
+// F (and its own rows' L_k for ||L r||) are staged in LDS once per inner
+// solve; with n <= 16 fixed at compile time and at most one window entry
+// per thread, each thread also keeps the F entries of its own entry (row i
+// of F_k, column i of F_{k-1}) in registers, so an application of C reads
+// only the vector from LDS. The updates of y, z and w run inside the
+// applications of C that produce their operands.
 // Scalars never leave the device: each window writes one partial per
 // reduction, and every workgroup sums all partials in the same fixed order,
 // so all of them take the same decisions without a broadcast.
@@ -38,9 +45,11 @@
 // barrier j is passed once it reaches (j + 1) times the workgroups. The data
 // windows exchange is written and read with agent-coherent accesses, and
 // every thread waits for its stores to complete before its workgroup
-// arrives, so no cache has to be written back or invalidated. The wait is bounded by a wall-clock limit: a
-// workgroup that gives up raises an abort flag, every other workgroup sees it
-// at its next wait and returns, and the solve reports BT_ETIMEOUT. The grid
+// arrives, so no cache has to be written back or invalidated. The wait is
+// bounded by a wall-clock limit (checked with the abort flag on the first
+// poll and every 16th): a workgroup that gives up raises an abort flag,
+// every other workgroup sees it at its next wait and returns, and the solve
+// reports BT_ETIMEOUT. The grid
 // never exceeds the workgroups that fit on the device at once, and each
 // workgroup loops over several windows when there are more windows than
 // that.
