@@ -6,16 +6,18 @@
 //   backward x_k = L_k^{-T} (y_k - M_{k+1}^T x_{k+1}).
 // Each system is sequential in its horizon; the parallelism is the batch.
 //
-// Layout: one wavefront per system (one per workgroup: no barrier and no
-// LDS at all), lane i < n holding row i of the current blocks in registers.
-// Every entry a lane needs from another row (the pivots and columns of the
-// Cholesky of S_k, the rows of L_{k-1} in the solve for M_k, the rows of M_k
-// in M_k M_k^T, the finished entries of the substitutions) is read from the
-// owning lane's register with v_readlane: the sequential horizon never waits
-// on memory. The rows of L_k and M_k go to the caller's scratch for the
-// backward sweep; the next block row's operands are loaded while the current
-// one is factored. float64 throughout, from the system of record (float32
-// or float64).
+// Three layouts by block size, float64 throughout, from the system of record
+// (float32 or float64); in each the next block row's operands are loaded
+// while the current one is factored, and what the backward sweep needs goes
+// to the caller's scratch:
+//   n <= 16 (k_direct4): four systems per wavefront, lane c of a 16-lane row
+//     holding column c of its system's blocks; entries of other columns come
+//     with DPP broadcasts inside the FMAs, on unscaled Schur complements.
+//   n = 24 (k_direct): one wavefront per system (no barrier, no LDS), lane i
+//     holding row i; entries of other rows are read from the owning lane's
+//     register with v_readlane, so the horizon never waits on memory.
+//   n = 32, 48, 64 (k_direct_mfma): one workgroup per system, a wavefront
+//     per 16-wide strip, the n^3 parts on the matrix cores (below).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
