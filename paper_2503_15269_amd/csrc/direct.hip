@@ -35,8 +35,13 @@ struct DirectArgs {
   const void* O;
   const double* b;
   double* x;
-  double* Lbuf;  // [R][n][n] rows of L_k
-  double* Mbuf;  // [R][n][n] rows of M_k (unused for a system's first row)
+  // what the backward sweep reads, per block row: the diagonal factor and
+  // the coupling block, each kernel in its own form (n = 24: L_k and M_k;
+  // n <= 16: their unscaled forms, with the pivots 1/d_c in Rbuf; n >= 32:
+  // L_k^{-1} and Z_k = L_{k-1}^{-1} O_{k-1}); the coupling block of a
+  // system's first row is unused
+  double* Lbuf;  // [R][n][n]
+  double* Mbuf;  // [R][n][n]
   double* Rbuf;  // [R][n] 1 / d_c, the pivots of S_k (n <= 16)
   bt_info* info;
 };
