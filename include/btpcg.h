@@ -264,9 +264,11 @@ int bt_solve_mrhs(const bt_handle* h, int nrhs, const double* b, double* x,
  * preconditioner parameters; n in 1..16, 24, 32, 48 or 64. For n <= 16
  * four instances share a wavefront, one per row of 16 lanes, lane c holding
  * column c of the current blocks, with values moved between columns by DPP
- * broadcasts fused into the float64 FMAs; above 16, one wavefront per
- * instance, lane i holding row i, with readlane broadcasts. No square roots
- * are taken for n <= 16 (unscaled Schur complements, pivots 1 / d).
+ * broadcasts fused into the float64 FMAs; for n = 24, one wavefront per
+ * instance, lane i holding row i, with readlane broadcasts; for n = 32, 48
+ * and 64, one workgroup per instance with the n^3 products on the matrix
+ * cores (float64 16x16x4 MFMA tiles in LDS). No square roots are taken for
+ * n <= 16 (unscaled Schur complements, pivots 1 / d).
  * b, x: device [R][n] float64. info:
  * device, B entries (status BT_OK or BT_ENOTSPD with fail_index = the block
  * row whose Schur complement is not positive definite; iters = 0; relres
