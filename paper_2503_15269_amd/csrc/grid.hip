@@ -1045,8 +1045,21 @@ inline int depth_of(const bt_params& p) {
   return d1 + (p.m - 1) * dh;
 }
 
-inline int rows_per_win(int64_t R) {
-  return (int)std::max<int64_t>(4, std::min<int64_t>(16, R / 64));
+// Rows per window. Larger windows mean fewer workgroups and cheaper grid
+// barriers. With n = 6 or 12 (block size fixed at compile time) a window of
+// at most one entry per thread keeps each thread's F entries in registers;
+// that is worth more (N = 2048, n = 12: 0.35 -> 0.28 ms) as long as every
+// window still gets a workgroup of its own, so the window shrinks to fit
+// when its windows number at most one per CU (256).
+constexpr int64_t kWindowsForRegisters = 256;
+inline int rows_per_win(int64_t R, int n, int depth) {
+  int rb = (int)std::max<int64_t>(4, std::min<int64_t>(16, R / 64));
+  if (n == 6 || n == 12) {
+    const int fit = NT / n - 2 * std::max(depth + 1, 1);
+    if (fit >= 4 && fit < rb && (R + fit - 1) / fit <= kWindowsForRegisters)
+      rb = fit;
+  }
+  return rb;
 }
 
 // Scratch layout: nine T vectors (r, s and w twice, u, p, xhat), the
@@ -1055,8 +1068,8 @@ constexpr int NVEC = 9;
 template <typename T>
 struct Scratch {
   size_t r64, part, bar, total;
-  Scratch(int64_t R, int n) {
-    const int rb = rows_per_win(R);
+  Scratch(int64_t R, int n, int depth) {
+    const int rb = rows_per_win(R, n, depth);
     const int nwin = (int)((R + rb - 1) / rb);
     const size_t v = (size_t)R * n;
     r64 = (NVEC * v * sizeof(T) + 255) / 256 * 256;
@@ -1122,7 +1135,7 @@ int run(const bt_handle* h, const double* b, double* x, double tol, int maxit,
   GArgsBase<T> a{};
   a.R = (int)R;
   a.n = n;
-  a.rb = rows_per_win(R);
+  a.rb = rows_per_win(R, n, depth_of(h->p));
   a.nwin = (int)((R + a.rb - 1) / a.rb);
   a.depth = depth_of(h->p);
   a.pc = h->p.pc;
@@ -1161,7 +1174,7 @@ int run(const bt_handle* h, const double* b, double* x, double tol, int maxit,
   a.u = f + 6 * v;
   a.p = f + 7 * v;
   a.xh = f + 8 * v;
-  const Scratch<T> sl(R, n);
+  const Scratch<T> sl(R, n, a.depth);
   a.r64 = (double*)((unsigned char*)ws + sl.r64);
   a.part = (double*)((unsigned char*)ws + sl.part);
   a.bar = (Bar*)((unsigned char*)ws + sl.bar);
@@ -1179,8 +1192,9 @@ int run(const bt_handle* h, const double* b, double* x, double tol, int maxit,
 
 size_t bt_grid_scratch_bytes(const bt_handle* h) {
   if (!h || h->B != 1) return 0;
-  return h->p.prec == BT_F64 ? btg::Scratch<double>(h->R, h->n).total
-                             : btg::Scratch<float>(h->R, h->n).total;
+  const int depth = btg::depth_of(h->p);
+  return h->p.prec == BT_F64 ? btg::Scratch<double>(h->R, h->n, depth).total
+                             : btg::Scratch<float>(h->R, h->n, depth).total;
 }
 
 int bt_grid_solve(const bt_handle* h, const double* b, double* x, double tol,
