@@ -1045,21 +1045,30 @@ inline int depth_of(const bt_params& p) {
   return d1 + (p.m - 1) * dh;
 }
 
-// Rows per window. Larger windows mean fewer workgroups and cheaper grid
-// barriers. With n = 6 or 12 (block size fixed at compile time) a window of
-// at most one entry per thread keeps each thread's F entries in registers;
-// that is worth more (N = 2048, n = 12: 0.35 -> 0.28 ms) as long as every
-// window still gets a workgroup of its own, so the window shrinks to fit
-// when its windows number at most one per CU (256).
-constexpr int64_t kWindowsForRegisters = 256;
+// Rows per window. Larger windows mean fewer workgroups, cheaper grid
+// barriers and less halo recomputed per own row: 4..16 rows (R / 64) up to
+// 1024 block rows, then about one window per CU (R / 256, at most 64 rows;
+// N = 8192, n = 12: 0.81 -> 0.56 ms, N = 32768: 2.66 -> 1.53 ms against
+// 16 rows; that growth keeps the five window vectors within 64 KB of LDS).
+// With n = 6 or 12 (block size fixed at compile time) a window of at most
+// one entry per thread keeps each thread's F entries in registers; that is
+// worth more (N = 2048, n = 12: 0.35 -> 0.28 ms) as long as every window
+// still gets a workgroup of its own, so the window shrinks to fit when its
+// windows then number at most one per CU (256).
+constexpr int64_t kWindowsPerGrid = 256;
 inline int rows_per_win(int64_t R, int n, int depth) {
-  int rb = (int)std::max<int64_t>(4, std::min<int64_t>(16, R / 64));
-  if (n == 6 || n == 12) {
-    const int fit = NT / n - 2 * std::max(depth + 1, 1);
-    if (fit >= 4 && fit < rb && (R + fit - 1) / fit <= kWindowsForRegisters)
-      rb = fit;
+  const int halo = 2 * std::max(depth + 1, 1);
+  int64_t rb = std::max<int64_t>(4, std::min<int64_t>(16, R / 64));
+  if (R / kWindowsPerGrid > rb) {  // grow towards one window per CU
+    const int64_t lds_cap = (64 * 1024 - NT * (int64_t)sizeof(double)) /
+                                (5 * n * (int64_t)sizeof(double)) - halo;
+    rb = std::max(rb, std::min<int64_t>({64, R / kWindowsPerGrid, lds_cap}));
   }
-  return rb;
+  if (n == 6 || n == 12) {
+    const int fit = NT / n - halo;
+    if (fit >= 4 && fit < rb && (R + fit - 1) / fit <= kWindowsPerGrid) rb = fit;
+  }
+  return (int)rb;
 }
 
 // Scratch layout: nine T vectors (r, s and w twice, u, p, xhat), the
