@@ -230,12 +230,15 @@ def test_grid_repeated_solves_and_iteration_cap(prec):
         assert rel(x.cpu().numpy().reshape(xr.shape), xr) <= 1e-10
 
 
-@pytest.mark.parametrize("N,n", [(300, 12), (40000, 6), (2000, 48)])
+@pytest.mark.parametrize("N,n", [(300, 12), (40000, 6), (2000, 48),
+                                 (8192, 12), (32768, 12)])
 def test_grid_more_windows_than_resident_workgroups(N, n):
-    """Systems with more row windows than one pass of the grid holds: each
-    workgroup loops over several windows; float64 counts equal the oracle's
-    where the oracle finishes quickly, otherwise the true residual and the
-    error against the direct solve."""
+    """Long systems: windows of 4 to 64 rows (N = 8192, n = 12: 32 rows, one
+    window per CU; N = 32768: 64 rows, two per workgroup), and systems with
+    more row windows than one pass of the grid holds, where each workgroup
+    loops over several windows; float64 counts equal the oracle's where the
+    oracle finishes quickly, otherwise the true residual and the error
+    against the direct solve."""
     d = lqrgen.lqr_instance(N, n, max(1, n // 3), 29, N, s=0.05)
     P = bt.Params.polycoeff(2)
     x, info, _ = grid_solve(d["D"], d["O"], d["b"], P)
