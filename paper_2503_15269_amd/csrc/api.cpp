@@ -314,12 +314,12 @@ int bt_batch_setup(bt_handle** h, int B, const int64_t* offsets_host, int n,
   for (int v = 0; v < BT_FAST_VARIANTS; ++v) {
     if (bt_fast_params(p) && bt_fast_supported(n, p->prec, v) &&
         maxN <= bt_fast_rows_per_bin(n)) {
-      const int rpw = bt_fast_rows_per_wave(n, v);
+      const int rps = bt_fast_rows_per_seg(n, v);
       const int full = bt_fast_rows_per_bin(n);
       const int maxper = bt_fast_max_systems_per_bin();
-      btpack::pack_bins(order, offsets_host, rpw, full, maxper, bins[v],
+      btpack::pack_bins(order, offsets_host, rps, full, maxper, bins[v],
                         items[v]);
-      btpack::balanced_capacity(order, offsets_host, rpw, full, maxper,
+      btpack::balanced_capacity(order, offsets_host, rps, full, maxper,
                                 bt_fast_max_grid(n, v),
                                 (int)(bins[v].size() / 2), bins[v], items[v]);
       hh->nbins[v] = (int)(bins[v].size() / 2);

@@ -166,7 +166,7 @@ hipError_t bt_launch_setup(const SetupArgs& a, hipStream_t s);
 bool bt_fast_supported(int n, int prec, int variant);
 bool bt_fast_params(const bt_params* p);
 int bt_fast_threads(int variant);
-int bt_fast_rows_per_wave(int n, int variant);
+int bt_fast_rows_per_seg(int n, int variant);  // system alignment
 int bt_fast_rows_per_bin(int n);
 int bt_fast_max_systems_per_bin();
 hipError_t bt_launch_fast(const SolveArgs& a, int variant, int grid,

@@ -11,7 +11,8 @@ namespace btpack {
 
 // First-fit-decreasing packing of the systems, taken in ``order`` (longest
 // first), into bins of at most ``cap`` rows and ``maxper`` systems; a system
-// of len rows takes len rounded up to whole wavefronts of ``rpw`` rows
+// of len rows takes len rounded up to whole segments of ``rpw`` rows (the
+// unit the kernel aligns systems to)
 // (every system must fit: its padded length <= cap). Output: ``bins`` holds
 // (first item, item count) per bin, ``items`` the system indices bin by bin.
 // First fit = the lowest-numbered bin with room, found in a max-tree over
@@ -57,7 +58,7 @@ inline void pack_bins(const std::vector<int32_t>& order, const int64_t* off,
 // full-capacity packing (``nbins`` bins, passed in ``bins``/``items``). Bins
 // of the full capacity can leave compute units idle: a batch of few rows
 // fills only a few bins, and the last round of a longer queue is partial.
-// The smallest capacity (whole wavefronts, at least the longest system) that
+// The smallest capacity (whole segments, at least the longest system) that
 // packs the systems into no more bins than those rounds of ``slots`` hold
 // spreads the same rows over more workgroups with less work each; its
 // packing replaces ``bins``/``items``. Returns the capacity taken.

@@ -30,12 +30,16 @@
 // The column order of the F registers is permuted per lane (chunk c of lane q
 // holds columns EPT (c xor q) .. +EPT-1) so that the reduce-scatter needs no
 // selects. In LDS a vector row is stored in 16-byte slots of 3 entries
-// (entry j at 4 (j / 3) + j % 3). Systems start on a wavefront boundary, so
-// every per-system quantity (scalars, convergence masks) is uniform within a
-// wavefront; reductions are a DPP wave sum plus an in-order sum over the
-// system's wavefronts, and a converged system stops updating while the
+// (entry j at 4 (j / 3) + j % 3). Systems start on a segment boundary, a
+// segment being the 16 lanes of a DPP row (16 / TPR block rows), so every
+// per-system quantity (scalars, convergence masks) is uniform within a DPP
+// row; a system is padded to whole segments, not whole wavefronts (on the
+// ragged batch at n = 12, EPT = 6: 2.6 % padding rows instead of 11 %).
+// Reductions are a DPP butterfly over each row, one partial per segment in
+// LDS, and a fixed-order sum over the system's segments that every row of
+// the system forms alike; a converged system stops updating while the
 // others in its bin go on. F is zero for the last row of a system, so systems
-// sharing a bin do not couple.
+// sharing a bin, or a wavefront, do not couple.
 // (kernel and launch templates; instantiated by solve_fast.hip for n = 12
 // and solve_fast24.hip for n = 24, which are built with different
 // instruction-scheduling strategies)
@@ -53,21 +57,22 @@ using btk::AccX;
 
 constexpr int SL = 4;      // reduction slots (reuse distance)
 constexpr int MAXI = 64;   // systems per bin, upper bound
-constexpr int MAXW = 16;   // wavefronts per workgroup, upper bound
+constexpr int MAXS = 64;   // 16-lane segments per workgroup, upper bound
 
 template <int NB, int EPT>
 struct Geo {
   static constexpr int TPR = NB / EPT;            // lanes per block row
-  static constexpr int RPW = 64 / TPR;            // block rows per wavefront
+  static constexpr int RPS = 16 / TPR;            // block rows per segment
   static constexpr int RPB = NB == 12 ? 256 : 128;  // block rows per bin
   static constexpr int NT = RPB * TPR;            // threads per workgroup
   static constexpr int NW = NT / 64;              // wavefronts
+  static constexpr int NSEG = NT / 16;            // 16-lane segments
   static constexpr int SUB = EPT / 3;             // 16-byte slots per lane
   static constexpr int ROW = NB / 3 * 4;          // floats per staged row
   static_assert(NB % EPT == 0 && EPT % 3 == 0, "EPT divides NB, 3 | EPT");
   static_assert(TPR == 1 || TPR == 2 || TPR == 4 || TPR == 8,
                 "1, 2, 4 or 8 lanes per block row");
-  static_assert(NW <= MAXW, "at most 16 wavefronts");
+  static_assert(NSEG <= MAXS && NSEG % 16 == 0, "16..64 segments");
 };
 
 
@@ -121,8 +126,8 @@ struct Smem {
   float T[2][G::RPB * G::ROW];  // transposed sums for row k+1
   float Z[G::ROW];              // zeros: the "previous row" of a first row
   double xs[G::RPB * NB];       // float64 iterate of the bin
-  AccX redF[SL][MAXW];
-  double redD[SL][MAXW];
+  AccX redF[SL][MAXS];   // per-segment partials
+  double redD[SL][MAXS];
   int active;   // running count of (wavefront, flag) events, never reset
   int bin;
   int cnt;
@@ -135,7 +140,8 @@ template <int NB, int EPT>
 struct Ctx {
   using G = Geo<NB, EPT>;
   Smem<NB, EPT>& sm;
-  int lrow, q, wave, w0, w1;
+  int lrow, q, seg;  // block row in the bin, lane in the row, segment
+  int s0, s1;        // the system's segments (an idle lane: its own)
   int k, N;          // row within the system, system length (0: idle lane)
   bool row_ok;       // a real block row (not padding, not idle)
   int sf, sd, seen;
@@ -371,7 +377,7 @@ struct Ctx {
     for (int e = 0; e < EPT; ++e) y[e] = -acc[e];
   }
 
-  // ``on``: this wavefront's system still iterates (wavefront-uniform); the
+  // ``on``: this lane's system still iterates (uniform over its segment); the
   // barrier is always taken, the arithmetic only when needed.
   template <int BUF>
   __device__ __forceinline__ void C(const float (&v)[EPT], float (&y)[EPT],
@@ -382,21 +388,28 @@ struct Ctx {
   }
 
   // ---- reductions --------------------------------------------------------
-  __device__ __forceinline__ void put_wave(const AccX& acc) {
-    const AccX t = btk::wave_sum(acc);
-    if ((threadIdx.x & 63) == 0) sm.redF[sf][wave] = t;
+  // Every value below is uniform over a 16-lane segment, and the sums over a
+  // system are bitwise equal in all of its lanes.
+  __device__ __forceinline__ void put_seg(const AccX& acc) {
+    const AccX t = btk::row16_sum(acc);
+    if ((threadIdx.x & 15) == 0) sm.redF[sf][seg] = t;
   }
-  // Sum of the system's wavefront partials: lane l of every wavefront reads
-  // slot l (one LDS load), slots outside the system are zeroed, a DPP row
-  // reduction adds the 16 and lane 0 broadcasts. Fixed tree: deterministic.
+  // Sum of the system's segment partials: lane l of each DPP row adds slots
+  // l, l + 16, .. that lie in [s0, s1) in that order, and the row's
+  // butterfly adds the 16 (a fixed tree: deterministic, and the same in
+  // every row of the system).
   __device__ __forceinline__ double take() {  // after the barrier
-    const int l = threadIdx.x & (MAXW - 1);
+    const int l = threadIdx.x & 15;
     AccX v;
-    if (l >= w0 && l < w1) v = sm.redF[sf][l];
-    else v.zero();
+    v.zero();
+#pragma unroll
+    for (int i = 0; i < G::NSEG; i += 16) {
+      const AccX u = sm.redF[sf][l + i];
+      if (l + i >= s0 && l + i < s1) v.merge(u);
+    }
     v = btk::row16_sum(v);
     sf = (sf + 1) % SL;
-    return uni(v.lane(0).value());
+    return v.value();
   }
   __device__ __forceinline__ double take_if(bool on) {  // after the barrier
     if (on) return take();
@@ -410,7 +423,7 @@ struct Ctx {
       acc.zero();
 #pragma unroll
       for (int e = 0; e < EPT; ++e) acc.add_prod(x[e], y[e]);
-      put_wave(acc);
+      put_seg(acc);
     }
     __syncthreads();
     return take_if(on);
@@ -418,15 +431,20 @@ struct Ctx {
   __device__ __forceinline__ double sumd(double v) {
     AccD a;
     a.s = v;
-    const AccD t = btk::wave_sum(a);
-    if ((threadIdx.x & 63) == 0) sm.redD[sd][wave] = t.s;
+    const AccD t = btk::row16_sum(a);
+    if ((threadIdx.x & 15) == 0) sm.redD[sd][seg] = t.s;
     __syncthreads();
-    const int l = threadIdx.x & (MAXW - 1);
-    AccD v2;
-    v2.s = (l >= w0 && l < w1) ? sm.redD[sd][l] : 0.0;
-    v2 = btk::row16_sum(v2);
+    const int l = threadIdx.x & 15;
+    AccD u;
+    u.zero();
+#pragma unroll
+    for (int i = 0; i < G::NSEG; i += 16) {
+      const double w = sm.redD[sd][l + i];
+      if (l + i >= s0 && l + i < s1) u.s += w;
+    }
+    u = btk::row16_sum(u);
     sd = (sd + 1) % SL;
-    return uni(v2.lane(0).s);
+    return u.s;
   }
   // Any wavefront that raised its flag since the last check bumped the
   // counter; every lane compares with the value it saw last time. The next
@@ -437,8 +455,9 @@ struct Ctx {
     seen = now;
     return any;
   }
-  __device__ __forceinline__ void put_flag(bool f) {
-    if ((threadIdx.x & 63) == 0 && f) atomicAdd(&sm.active, 1);
+  __device__ __forceinline__ void put_flag(bool f) {  // every lane calls
+    const bool any = __builtin_amdgcn_ballot_w64(f) != 0;
+    if ((threadIdx.x & 63) == 0 && any) atomicAdd(&sm.active, 1);
   }
 
   // z = M^{-1} r at the optimal weights (a, b) = (1, -1), in the scaled
@@ -477,7 +496,7 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
   const int t = threadIdx.x;
   c.lrow = t / G::TPR;
   c.q = t % G::TPR;
-  c.wave = t >> 6;
+  c.seg = t >> 4;
   c.sf = 0;
   c.sd = 0;
   if (t == 0) sm.active = 0;
@@ -505,7 +524,7 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
         sm.inst[j] = id;
         sm.lstart[j] = at;
         sm.nrows[j] = Nj;
-        at += (Nj + G::RPW - 1) / G::RPW * G::RPW;
+        at += (Nj + G::RPS - 1) / G::RPS * G::RPS;
       }
       sm.cnt = cnt;
     }
@@ -515,30 +534,27 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
     int j = -1;
     for (int jj = 0; jj < sm.cnt; ++jj) {
       const int ls = sm.lstart[jj];
-      const int pad = (sm.nrows[jj] + G::RPW - 1) / G::RPW * G::RPW;
+      const int pad = (sm.nrows[jj] + G::RPS - 1) / G::RPS * G::RPS;
       if (c.lrow >= ls && c.lrow < ls + pad) j = jj;
     }
-    const bool sys = j >= 0;  // uniform within the wavefront
+    const bool sys = j >= 0;  // uniform within the segment
     int inst = 0;
     bool lead = false;
     if (sys) {
       const int ls = sm.lstart[j];
-      const int pad = (sm.nrows[j] + G::RPW - 1) / G::RPW * G::RPW;
+      const int pad = (sm.nrows[j] + G::RPS - 1) / G::RPS * G::RPS;
       c.N = sm.nrows[j];
       c.k = c.lrow - ls;
       inst = sm.inst[j];
-      c.w0 = ls / G::RPW;
-      c.w1 = (ls + pad) / G::RPW;
+      c.s0 = ls / G::RPS;
+      c.s1 = (ls + pad) / G::RPS;
       lead = (c.k == 0 && c.q == 0);
     } else {
       c.N = 0;
       c.k = 0;
-      c.w0 = c.wave;
-      c.w1 = c.wave + 1;
+      c.s0 = c.seg;
+      c.s1 = c.seg + 1;
     }
-    c.N = uni(c.N);
-    c.w0 = uni(c.w0);
-    c.w1 = uni(c.w1);
     c.row_ok = sys && c.k < c.N;
     const int64_t g = sys ? a.off[inst] + c.k : 0;  // global block row
     const int64_t ob = g - inst;                     // its upper block
@@ -629,7 +645,7 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
       // norm in [1, 2) before the float32 inner solve ----------------------
       float r64f[EPT];
       {
-        const bool need = !done && (outer > 0 || a.warm);  // wave-uniform
+        const bool need = !done && (outer > 0 || a.warm);  // segment-uniform
         const double* xk = sm.xs + c.lrow * NB;
         double acc[EPT];
         double P[NB];  // column sums of O_k^T x_k over own rows, natural
@@ -789,7 +805,7 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
 #pragma unroll
           for (int e = 0; e < EPT; ++e) acc.add_prod(r[e], z[e]);
           c.template prep<0>(z);
-          c.put_wave(acc);
+          c.put_seg(acc);
         }
         c.put_flag(act);
         __syncthreads();

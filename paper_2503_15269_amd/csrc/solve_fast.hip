@@ -17,7 +17,7 @@ bool bt_fast_params(const bt_params* p) {
 }
 
 int bt_fast_threads(int v) { return 3072 / btf::kEpt[v]; }
-int bt_fast_rows_per_wave(int n, int v) { return 64 / (n / btf::kEpt[v]); }
+int bt_fast_rows_per_seg(int n, int v) { return 16 / (n / btf::kEpt[v]); }
 int bt_fast_rows_per_bin(int n) { return n == 24 ? 128 : 256; }
 int bt_fast_max_systems_per_bin() { return btf::MAXI; }
 
