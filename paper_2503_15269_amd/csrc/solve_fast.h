@@ -31,13 +31,14 @@
 // holds columns EPT (c xor q) .. +EPT-1) so that the reduce-scatter needs no
 // selects. In LDS a vector row is stored in 16-byte slots of 3 entries
 // (entry j at 4 (j / 3) + j % 3). Systems start on a segment boundary, a
-// segment being the 16 lanes of a DPP row (16 / TPR block rows), so every
-// per-system quantity (scalars, convergence masks) is uniform within a DPP
-// row; a system is padded to whole segments, not whole wavefronts (on the
-// ragged batch at n = 12, EPT = 6: 2.6 % padding rows instead of 11 %).
-// Reductions are a DPP butterfly over each row, one partial per segment in
-// LDS, and a fixed-order sum over the system's segments that every row of
-// the system forms alike; a converged system stops updating while the
+// segment being the 16 lanes of a DPP row at n = 12 (16 / TPR block rows)
+// and a wavefront at n = 24, so every per-system quantity (scalars,
+// convergence masks) is uniform within a segment; a system is padded to
+// whole segments (on the ragged batch at n = 12, EPT = 6: 2.6 % padding rows
+// instead of the 11 % of whole wavefronts). Reductions are a DPP sum over
+// each segment, one partial per segment in LDS, and a fixed-order sum over
+// the system's segments that every row of the system forms alike; a
+// converged system stops updating while the
 // others in its bin go on. F is zero for the last row of a system, so systems
 // sharing a bin, or a wavefront, do not couple.
 // (kernel and launch templates; instantiated by solve_fast.hip for n = 12
@@ -57,22 +58,27 @@ using btk::AccX;
 
 constexpr int SL = 4;      // reduction slots (reuse distance)
 constexpr int MAXI = 64;   // systems per bin, upper bound
-constexpr int MAXS = 64;   // 16-lane segments per workgroup, upper bound
+constexpr int MAXS = 64;   // segments per workgroup, upper bound
 
 template <int NB, int EPT>
 struct Geo {
   static constexpr int TPR = NB / EPT;            // lanes per block row
-  static constexpr int RPS = 16 / TPR;            // block rows per segment
+  // Systems are aligned to segments of SEG lanes: a DPP row at n = 12 (less
+  // padding on ragged batches), a wavefront at n = 24 (per-system values stay
+  // in scalar registers, which the larger F needs).
+  static constexpr int SEG = NB == 12 ? 16 : 64;
+  static constexpr int RPS = SEG / TPR;           // block rows per segment
   static constexpr int RPB = NB == 12 ? 256 : 128;  // block rows per bin
   static constexpr int NT = RPB * TPR;            // threads per workgroup
   static constexpr int NW = NT / 64;              // wavefronts
-  static constexpr int NSEG = NT / 16;            // 16-lane segments
+  static constexpr int NSEG = NT / SEG;           // segments
   static constexpr int SUB = EPT / 3;             // 16-byte slots per lane
   static constexpr int ROW = NB / 3 * 4;          // floats per staged row
   static_assert(NB % EPT == 0 && EPT % 3 == 0, "EPT divides NB, 3 | EPT");
   static_assert(TPR == 1 || TPR == 2 || TPR == 4 || TPR == 8,
                 "1, 2, 4 or 8 lanes per block row");
-  static_assert(NSEG <= MAXS && NSEG % 16 == 0, "16..64 segments");
+  static_assert(NSEG <= MAXS && (SEG == 64 ? NSEG <= 16 : NSEG % 16 == 0),
+                "segment slots: 16-lane rows read them 16 at a time");
 };
 
 
@@ -388,11 +394,23 @@ struct Ctx {
   }
 
   // ---- reductions --------------------------------------------------------
-  // Every value below is uniform over a 16-lane segment, and the sums over a
-  // system are bitwise equal in all of its lanes.
+  // Every value below is uniform over a segment, and the sums over a system
+  // are bitwise equal in all of its lanes.
+  template <typename A>
+  __device__ __forceinline__ static A seg_sum(A v) {
+    if constexpr (G::SEG == 64) return btk::wave_sum(v);
+    else return btk::row16_sum(v);
+  }
+  // a segment-uniform value; whole-wavefront segments keep it in scalar
+  // registers
+  template <typename V>
+  __device__ __forceinline__ static V seg_uni(V v) {
+    if constexpr (G::SEG == 64) return uni(v);
+    else return v;
+  }
   __device__ __forceinline__ void put_seg(const AccX& acc) {
-    const AccX t = btk::row16_sum(acc);
-    if ((threadIdx.x & 15) == 0) sm.redF[sf][seg] = t;
+    const AccX t = seg_sum(acc);
+    if ((threadIdx.x & (G::SEG - 1)) == 0) sm.redF[sf][seg] = t;
   }
   // Sum of the system's segment partials: lane l of each DPP row adds slots
   // l, l + 16, .. that lie in [s0, s1) in that order, and the row's
@@ -409,7 +427,7 @@ struct Ctx {
     }
     v = btk::row16_sum(v);
     sf = (sf + 1) % SL;
-    return v.value();
+    return seg_uni(v.value());
   }
   __device__ __forceinline__ double take_if(bool on) {  // after the barrier
     if (on) return take();
@@ -431,8 +449,8 @@ struct Ctx {
   __device__ __forceinline__ double sumd(double v) {
     AccD a;
     a.s = v;
-    const AccD t = btk::row16_sum(a);
-    if ((threadIdx.x & 15) == 0) sm.redD[sd][seg] = t.s;
+    const AccD t = seg_sum(a);
+    if ((threadIdx.x & (G::SEG - 1)) == 0) sm.redD[sd][seg] = t.s;
     __syncthreads();
     const int l = threadIdx.x & 15;
     AccD u;
@@ -444,7 +462,7 @@ struct Ctx {
     }
     u = btk::row16_sum(u);
     sd = (sd + 1) % SL;
-    return u.s;
+    return seg_uni(u.s);
   }
   // Any wavefront that raised its flag since the last check bumped the
   // counter; every lane compares with the value it saw last time. The next
@@ -496,7 +514,7 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
   const int t = threadIdx.x;
   c.lrow = t / G::TPR;
   c.q = t % G::TPR;
-  c.seg = t >> 4;
+  c.seg = t / G::SEG;
   c.sf = 0;
   c.sd = 0;
   if (t == 0) sm.active = 0;
@@ -555,6 +573,9 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
       c.s0 = c.seg;
       c.s1 = c.seg + 1;
     }
+    c.N = c.seg_uni(c.N);
+    c.s0 = c.seg_uni(c.s0);
+    c.s1 = c.seg_uni(c.s1);
     c.row_ok = sys && c.k < c.N;
     const int64_t g = sys ? a.off[inst] + c.k : 0;  // global block row
     const int64_t ob = g - inst;                     // its upper block

@@ -17,7 +17,14 @@ bool bt_fast_params(const bt_params* p) {
 }
 
 int bt_fast_threads(int v) { return 3072 / btf::kEpt[v]; }
-int bt_fast_rows_per_seg(int n, int v) { return 16 / (n / btf::kEpt[v]); }
+int bt_fast_rows_per_seg(int n, int v) {
+  if (n == 24) return btf::Geo<24, 6>::RPS;
+  switch (btf::kEpt[v]) {
+    case 3: return btf::Geo<12, 3>::RPS;
+    case 6: return btf::Geo<12, 6>::RPS;
+    default: return btf::Geo<12, 12>::RPS;
+  }
+}
 int bt_fast_rows_per_bin(int n) { return n == 24 ? 128 : 256; }
 int bt_fast_max_systems_per_bin() { return btf::MAXI; }
 
