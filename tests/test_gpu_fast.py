@@ -138,7 +138,7 @@ def test_fast_many_systems_per_bin(n, v):
     small["O"] = big["O"][:R - B]
     xs, infs, _ = run(small, P, cfg=cfg)
     check_against_oracle(small, xs, infs)
-    # a system's wavefront partials meet in a tree fixed by their slots in
+    # a system's segment partials meet in a tree fixed by their slots in
     # the bin, so the two packings may round differently: both reach the
     # 1e-10 residual and agree to the conditioning of these short horizons
     assert rel(xs, x[:R]) <= 1e-7
