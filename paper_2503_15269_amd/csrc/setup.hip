@@ -634,9 +634,12 @@ __global__ void __launch_bounds__(64) k_factor_wave(SetupArgs a) {
   // per block: two column buffers (Cholesky step j uses col[j & 1]) and two
   // row buffers (inverse step k uses row[k & 1]); alternating buffers let a
   // step write while the previous one's readers may still be reading, so
-  // each step needs one barrier
-  double* col = reinterpret_cast<double*>(smem_raw) + sub * 4 * NB;
-  double* row = col + 2 * NB;
+  // each step needs one barrier. The buffers hold LW entries so that every
+  // lane publishes its column entry without a branch (entries past the
+  // block are never read): at n = 24 the branch-free step takes 121 instead
+  // of 180 VGPRs, four wavefronts per SIMD instead of two.
+  double* col = reinterpret_cast<double*>(smem_raw) + sub * 4 * LW;
+  double* row = col + 2 * LW;
   const int64_t gb = (int64_t)blockIdx.x * BPW + sub;
   const bool real = gb < a.R;              // the last wavefront may hold one
   const int64_t g = real ? gb : a.R - 1;   // (always valid memory)
@@ -662,8 +665,8 @@ __global__ void __launch_bounds__(64) k_factor_wave(SetupArgs a) {
     // updates below run unmasked (no branches in the unrolled loops)
     m[j] = rr == j ? dj : m[j] * rd;
     if (rr == j) myrd = rd;
-    double* cj = col + (j & 1) * NB;
-    if (r < NB) cj[r] = m[j];  // column j of L (rows above j never read)
+    double* cj = col + (j & 1) * LW;
+    cj[r] = m[j];  // column j of L (entries above j never read)
     __syncthreads();
 #pragma unroll
     for (int c = j + 1; c < NB; ++c) m[c] = fma(-m[j], cj[c], m[c]);
@@ -691,7 +694,7 @@ __global__ void __launch_bounds__(64) k_factor_wave(SetupArgs a) {
     const double sc = rr == k ? myrd : 1.0;  // row k becomes final
 #pragma unroll
     for (int c = 0; c <= k; ++c) x[c] *= sc;
-    double* rk = row + (k & 1) * NB;
+    double* rk = row + (k & 1) * LW;
     if (r == k) {
 #pragma unroll
       for (int c = 0; c <= k; ++c) rk[c] = x[c];
@@ -721,7 +724,8 @@ constexpr int factor_wave_bpw() { return NB <= 32 ? 2 : 1; }
 
 template <int NB>
 constexpr size_t factor_wave_lds() {
-  return factor_wave_bpw<NB>() * sizeof(double) * 4 * (size_t)NB;
+  constexpr int bpw = factor_wave_bpw<NB>();  // LW = 64 / bpw entries
+  return bpw * sizeof(double) * 4 * (size_t)(64 / bpw);
 }
 
 // F_g = Li_g O_g Li_{g+1}^T (zero for the last row of each instance), one
