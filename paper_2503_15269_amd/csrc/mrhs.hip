@@ -8,9 +8,10 @@
 // block row:  (C V)_k = -(F_{k-1}^T V_{k-1} + F_k V_{k+1}).
 // These run on the matrix cores: v_mfma_f32_16x16x32_bf16 (16x16x16 for an
 // odd last tile) with the blocks stored split as F = Fhi + Flo (two bfloat16
-// arrays) and the panel split the same way on the fly; the product is hi*hi + hi*lo + lo*hi with float32
-// accumulation (relative error ~1e-5), and the float64 refinement on the
-// record removes what the inner float32 solve leaves.
+// arrays) and the panel split the same way on the fly; the product is
+// hi*hi + hi*lo + lo*hi with float32 accumulation (relative error ~1e-5), and
+// the float64 refinement on the record removes what the inner float32 solve
+// leaves.
 //
 // One inner iteration (m = 2 shown; the polynomial follows eq. Mminv-poly-
 // nomial-coefficients at a = 1: y_0 = r + C r, y_i = C(C y_{i-1}))
