@@ -514,7 +514,7 @@ __global__ void __launch_bounds__((Geo<NB, EPT>::NT)) k_fast_ir(SolveArgs a) {
   const int t = threadIdx.x;
   c.lrow = t / G::TPR;
   c.q = t % G::TPR;
-  c.seg = t / G::SEG;
+  c.seg = c.seg_uni(t / G::SEG);  // scalar for whole-wavefront segments
   c.sf = 0;
   c.sd = 0;
   if (t == 0) sm.active = 0;
